@@ -1,0 +1,449 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the property it pins and the part of the paper it comes from.  None of
+them compares the oracle with itself: references are arbitrary-precision integrals,
+closed forms, invariants, textbook rules or brute force.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from tests import mp_reference as R
+from workloads import equidistant_grid, graded_grid, icosphere, get_config
+
+GRIDS = {
+    "eq10": (equidistant_grid(10, 4.0), "bump"),
+    "graded64": (graded_grid(64, 8.0, seed=2), "bump"),
+    "eq8_erf": (equidistant_grid(8, 4.0), "erf"),
+}
+
+
+# --- cutoff and partition of unity (Section 3) -----------------------------------------------
+@pytest.mark.parametrize("kind", ["bump", "erf"])
+def test_cutoff_values_and_derivatives(oracle_mod, kind):
+    """F against its defining formula (Shepard-normalised bump / erf(2 artanh)) and F', F''
+    against high-precision numerical differentiation."""
+    Fm = R.F_bump if kind == "bump" else R.F_erf
+    for u in np.random.default_rng(0).uniform(0.02, 0.98, 25):
+        F = oracle_mod.cutoff(u, kind)
+        ref = [float(Fm(u)), float(mp.diff(Fm, u)), float(mp.diff(Fm, u, 2))]
+        scale = [1.0, max(1.0, abs(ref[1])), max(1.0, abs(ref[2]))]
+        for m in range(3):
+            assert abs(F[m] - ref[m]) <= 2e-14 * scale[m], (u, m, F[m], ref[m])
+    assert oracle_mod.cutoff(0.0, kind)[0] == 0.0 and oracle_mod.cutoff(1.0, kind)[0] == 1.0
+    assert abs(oracle_mod.cutoff(0.5, kind)[0] - 0.5) < 1e-15
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_partition_of_unity(oracle_mod, name):
+    """P1: sum_j mu_j(t) = 1 on [0, T] (construction of mu_1..mu_N, Section 3)."""
+    grid, kind = GRIDS[name]
+    N = len(grid)
+    for t in np.concatenate([np.random.default_rng(1).uniform(0, grid[-1], 400), grid]):
+        s = sum(oracle_mod.mu(grid, j, t, kind)[0] for j in range(N))
+        ds = sum(oracle_mod.mu(grid, j, t, kind)[1] for j in range(N))
+        assert abs(s - 1.0) < 1e-15 and abs(ds) < 1e-11 * max(1, 1 / np.diff(grid).min())
+
+
+def test_first_basis_causal_factor(oracle_mod):
+    """b_1 = 8 mu_1 (t/dt)^2 (eq. (BasisFunctions), p = 0): value 1 at dt/2, C^1 at t = 0,
+    b_1(0) = b_1'(0) = 0 as required by the zero initial conditions."""
+    grid = equidistant_grid(10, 4.0)
+    h = grid[1]
+    for kind in ("bump", "erf"):
+        assert abs(oracle_mod.basis(grid, 0, h / 2, kind)[0] - 1.0) < 1e-15
+        v = oracle_mod.basis(grid, 0, 1e-9, kind)
+        assert abs(v[0]) < 1e-15 and abs(v[1]) < 1e-6
+        assert np.all(oracle_mod.basis(grid, 0, -0.1, kind) == 0.0)
+
+
+# --- time kernels (eq. (psis)) ----------------------------------------------------------------
+CASES = [("eq10", 6, 4, 0.61), ("eq10", 0, 0, 0.2), ("eq10", 3, 0, 1.1), ("eq10", 9, 8, 0.3),
+         ("graded64", 30, 28, 0.21), ("graded64", 5, 0, 0.5), ("graded64", 63, 61, 0.1),
+         ("eq8_erf", 4, 3, 0.7), ("eq8_erf", 2, 0, 0.9)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_psi_against_arbitrary_precision(oracle_mod, case):
+    """psi and tilde psi (eq. (psis)) against 30-digit tanh-sinh quadrature of the definition
+    with mpmath-differentiated bases."""
+    name, k, i, r = case
+    grid, kind = GRIDS[name]
+    got = oracle_mod.psi(grid, k, i, r, kind)
+    ref = R.psi_ref(grid, k, i, r, kind)
+    # scale: max |psi| over the support, from the oracle itself at a few points
+    lo, hi = oracle_mod.support(grid, k, i)
+    sc = np.abs([oracle_mod.psi(grid, k, i, x, kind) for x in np.linspace(lo, hi, 41)[1:-1]]).max(0)
+    assert abs(got[0] - ref[0]) <= 1e-12 * sc[0], (got, ref, sc)
+    assert abs(got[1] - ref[1]) <= 1e-12 * sc[1], (got, ref, sc)
+
+
+def test_psi_known_value(oracle_mod):
+    """A fixed value on the 10-node equidistant bump grid (T = 4), independently recorded with
+    30-digit quadrature: psi_{6,4}(0.61) = -22.7421197321..."""
+    got = oracle_mod.psi(equidistant_grid(10, 4.0), 6, 4, 0.61)
+    assert abs(got[0] - (-22.7421197321)) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["eq10", "graded64"])
+def test_psi_is_second_derivative_of_tilde_psi(oracle_mod, name):
+    """P3: psi_{k,i} = d^2/dr^2 tilde psi_{k,i} (two integrations by parts of eq. (psis)),
+    checked with a 4th-order central difference."""
+    grid, kind = GRIDS[name]
+    rng = np.random.default_rng(3)
+    N = len(grid)
+    for _ in range(12):
+        k = int(rng.integers(0, N)); i = int(rng.integers(max(0, k - 3), min(N, k + 2)))
+        lo, hi = oracle_mod.support(grid, k, i)
+        if hi - lo < 1e-3:
+            continue
+        r = rng.uniform(lo + 0.1 * (hi - lo), hi - 0.1 * (hi - lo))
+        hstep = 1e-3 * (hi - lo)
+        f = [oracle_mod.psi(grid, k, i, r + m * hstep, kind)[1] for m in (-2, -1, 0, 1, 2)]
+        d2 = (-f[0] + 16 * f[1] - 30 * f[2] + 16 * f[3] - f[4]) / (12 * hstep ** 2)
+        sc = np.abs([oracle_mod.psi(grid, k, i, x, kind)[0] for x in np.linspace(lo, hi, 31)[1:-1]]).max()
+        assert abs(d2 - oracle_mod.psi(grid, k, i, r, kind)[0]) < 1e-6 * sc
+
+
+def test_psi_toeplitz_and_odd_prototype(oracle_mod):
+    """P4: for equidistant inner bases psi_{k,i}(r) = xi(r - (k-i) dt) (eq. (psiTildeRed)), so
+    psi depends on k-i only, and xi, tilde xi are odd for p = 0 (eq. (symmetryXi))."""
+    grid = equidistant_grid(10, 4.0)
+    dt = grid[1]
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        k = int(rng.integers(1, 7)); d = int(rng.integers(-1, 4)); i = k - d
+        if not (1 <= i <= 7):
+            continue
+        r = rng.uniform(0.0, 0.999 * (d + 2) * dt)
+        a = oracle_mod.psi(grid, k, i, r)
+        b = oracle_mod.psi(grid, k + 1, i + 1, r)
+        assert np.allclose(a, b, rtol=0, atol=1e-12 * (1 + np.abs(a).max()))
+        # oddness: xi(alpha) = -xi(-alpha); alpha = r - d dt, partner with d' and r' >= 0
+        alpha = r - d * dt
+        for d2 in range(-1, 4):
+            r2 = -alpha + d2 * dt
+            if r2 <= 1e-9 or not (1 <= k - d2 <= 8):
+                continue
+            c = oracle_mod.psi(grid, k, k - d2, r2)
+            assert np.allclose(a, -c, rtol=0, atol=1e-12 * (1 + np.abs(a).max())), (k, d, d2, r, a, c)
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_psi_at_zero_closed_forms(oracle_mod, name):
+    """P5 (integration by parts of eq. (psis) at r -> 0):
+    tilde psi_{k,k}(0) = (b_k(T)^2 - b_k(0)^2)/2,
+    tilde psi_{k,i}(0) + tilde psi_{i,k}(0) = b_i(T) b_k(T) - b_i(0) b_k(0),
+    psi_{k,k}(0) = (b_k'(T)^2 - b_k'(0)^2)/2."""
+    grid, kind = GRIDS[name]
+    N = len(grid); T = grid[-1]
+    r0 = 1e-200  # r -> 0+ (r = 0 itself is the closed end of the open support)
+    for k in range(N):
+        bT = oracle_mod.basis(grid, k, T, kind); b0 = oracle_mod.basis(grid, k, 0.0, kind)
+        p = oracle_mod.psi(grid, k, k, r0, kind)
+        assert abs(p[1] - 0.5 * (bT[0] ** 2 - b0[0] ** 2)) < 1e-11
+        sc = 1.0 / np.diff(grid).min() ** 2
+        assert abs(p[0] - 0.5 * (bT[1] ** 2 - b0[1] ** 2)) < 1e-9 * sc
+        for i in (k - 1, k + 1):
+            if 0 <= i < N:
+                bi_T = oracle_mod.basis(grid, i, T, kind)[0]; bi_0 = oracle_mod.basis(grid, i, 0.0, kind)[0]
+                s = oracle_mod.psi(grid, k, i, r0, kind)[1] + oracle_mod.psi(grid, i, k, r0, kind)[1]
+                assert abs(s - (bi_T * bT[0] - bi_0 * b0[0])) < 1e-11
+
+
+@pytest.mark.parametrize("name", list(GRIDS))
+def test_psi_support(oracle_mod, name):
+    """P6: supp psi_{k,i} = [t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}] cap [0, inf) with t_{-1} = 0,
+    t_N = T (Section 3.2); psi_{k,i} = 0 for i >= k + 2 (block Hessenberg, eq. (Apartitioned));
+    the bases are flat at their support ends, so psi vanishes continuously there."""
+    grid, kind = GRIDS[name]
+    N = len(grid)
+    tm = lambda j: grid[max(j - 1, 0)]
+    tp = lambda j: grid[min(j + 1, N - 1)]
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        k = int(rng.integers(0, N)); i = int(rng.integers(max(0, k - 4), min(N, k + 4)))
+        lo, hi = oracle_mod.support(grid, k, i)
+        assert lo == max(0.0, tm(k) - tp(i)) and hi == tp(k) - tm(i)
+        if i >= k + 2:
+            assert hi <= 0.0
+            continue
+        w = hi - lo
+        for x in (hi - 1e-3 * w, hi + 1e-3 * w):
+            assert np.all(np.abs(oracle_mod.psi(grid, k, i, x, kind)) < 1e-6 * (1 + 1 / np.diff(grid).min() ** 2))
+        if lo > 0:
+            assert np.all(oracle_mod.psi(grid, k, i, lo * 0.999, kind) == 0.0)
+            # the true integral outside the support is zero as well
+            ref = R.psi_ref(grid, k, i, lo * 0.99, kind)
+            assert abs(ref[0]) < 1e-12 and abs(ref[1]) < 1e-12
+
+
+# --- spatial quadrature ----------------------------------------------------------------------
+def _tri_moment(a, b):
+    # int over {0 <= x2 <= x1 <= 1} of x1^a x2^b
+    return 1.0 / ((b + 1) * (a + b + 2))
+
+
+def test_rule7_exact_degree5(oracle_mod):
+    """P7: the 7-point rule integrates every monomial of degree <= 5 exactly, and not degree 6."""
+    B, W = oracle_mod.rule7()
+    assert abs(W.sum() - 1.0) < 1e-15
+    # reference triangle (0,0),(1,0),(0,1): int x^a y^b = a! b! / (a+b+2)!
+    for a in range(6):
+        for b in range(6 - a):
+            ex = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            x = B[:, 1]; y = B[:, 2]
+            assert abs(0.5 * np.sum(W * x ** a * y ** b) - ex) < 1e-15
+    x = B[:, 1]
+    assert abs(0.5 * np.sum(W * x ** 6) - math.factorial(6) / math.factorial(8)) > 1e-6
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_sauter_schwab_maps_are_exact_decompositions(oracle_mod, kind):
+    """The regions of each Sauter-Schwab transformation tile T x T: with a high-order rule
+    they reproduce every polynomial moment int_T int_T x1^a x2^b y1^c y2^d."""
+    rule = oracle_mod.ss_rule(kind, 10)
+    rng = np.random.default_rng(6)
+    for _ in range(40):
+        a, b, c, d = rng.integers(0, 4, 4)
+        val = np.sum(rule[:, 4] * rule[:, 0] ** a * rule[:, 1] ** b * rule[:, 2] ** c * rule[:, 3] ** d)
+        ex = _tri_moment(a, b) * _tri_moment(c, d)
+        assert abs(val - ex) < 1e-13 * ex
+    assert np.all(rule[:, 1] <= rule[:, 0] + 1e-15) and np.all(rule[:, 3] <= rule[:, 2] + 1e-15)
+
+
+def _two_triangle_meshes():
+    """Coincident, edge, vertex and separated pairs on the icosphere (level 1)."""
+    xyz, tri = icosphere(1)
+    sets = [set(t) for t in tri]
+    out = {"coincident": (0, 0)}
+    for e in range(1, len(tri)):
+        n = len(sets[0] & sets[e])
+        if n == 2 and "edge" not in out:
+            out["edge"] = (0, e)
+        if n == 1 and "vertex" not in out:
+            out["vertex"] = (0, e)
+        if n == 0 and "regular" not in out:
+            out["regular"] = (0, e)
+    return xyz, tri, out
+
+
+def _geom(xyz, tri, e):
+    P = xyz[tri[e]]
+    n = np.cross(P[1] - P[0], P[2] - P[0])
+    area = 0.5 * np.linalg.norm(n)
+    edges = [P[2] - P[1], P[0] - P[2], P[1] - P[0]]
+    return P, n / np.linalg.norm(n), area, edges
+
+
+@pytest.mark.parametrize("rel", ["coincident", "edge", "vertex", "regular"])
+def test_local_integrals_with_linear_psi(oracle_mod, rel):
+    """P8: with psi = tilde psi = r the kernel of eq. (MatrixEntries) is constant, so the local
+    block equals (n_x.n_y)|tau||sigma|/(36 pi) + (curl lam_a.curl lam_b)|tau||sigma|/(4 pi)
+    exactly, with curl lam_a = -e_a/(2|tau|) (tangential rotation of the P1 hats)."""
+    xyz, tri, pairs = _two_triangle_meshes()
+    ex, ey = pairs[rel]
+    loc = oracle_mod.pair_local(xyz, tri, ex, ey, np.array([0.0, 1.0]), mode="r")[0, 0]
+    _, nx, ax, ea = _geom(xyz, tri, ex)
+    _, ny, ay, eb = _geom(xyz, tri, ey)
+    for a in range(3):
+        for b in range(3):
+            cab = np.dot(ea[a], eb[b]) / (4 * ax * ay)
+            ref = np.dot(nx, ny) * ax * ay / (36 * np.pi) + cab * ax * ay / (4 * np.pi)
+            assert abs(loc[a, b] - ref) < 1e-14 * (abs(ref) + 1e-3)
+
+
+@pytest.mark.parametrize("rel", ["coincident", "edge", "vertex"])
+def test_singular_rules_exact_for_polynomial_kernel(oracle_mod, rel):
+    """P8: with psi = tilde psi = r^3 the kernel is |x-y|^2, a polynomial of degree 2 in x and
+    in y, which the 7 x 7 tensor rule integrates exactly; the order-4 Sauter-Schwab rule must
+    agree (its transformed integrand is a polynomial of degree <= 7 per variable)."""
+    xyz, tri, pairs = _two_triangle_meshes()
+    ex, ey = pairs[rel]
+    ss = oracle_mod.pair_local(xyz, tri, ex, ey, np.array([0.0, 1.0]), mode="r3", ss_order=4)[0, 0]
+    # the same pair integrated with the tensor rule: shift the y-triangle far away? No -
+    # |x - y|^2 is a polynomial, so integrate it directly with the 7-point rule on both.
+    B, W = oracle_mod.rule7()
+    P, nx, ax, ea = _geom(xyz, tri, ex)
+    Q, ny, ay, eb = _geom(xyz, tri, ey)
+    X = B @ P; Y = B @ Q
+    D2 = ((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    S1 = ax * ay * np.einsum("q,p,qa,pb,qp->ab", W, W, B, B, D2)
+    S2 = ax * ay * np.einsum("q,p,qp->", W, W, D2)
+    for a in range(3):
+        for b in range(3):
+            cab = np.dot(ea[a], eb[b]) / (4 * ax * ay)
+            ref = (np.dot(nx, ny) * S1[a, b] + cab * S2) / (4 * np.pi)
+            assert abs(ss[a, b] - ref) < 1e-14 * np.abs(ss).max()
+
+
+def _flat_triangle_potential(P, x):
+    """int_T 1/|x - y| dy for a flat triangle T with vertices P and a point x (closed form of
+    the single-layer potential of a unit density: sum over edges of a log term and a solid
+    angle term)."""
+    n = np.cross(P[1] - P[0], P[2] - P[0]); n /= np.linalg.norm(n)
+    h = np.dot(x - P[0], n)
+    rho = x - h * n
+    val = 0.0
+    for e in range(3):
+        A, Bv = P[e], P[(e + 1) % 3]
+        lvec = (Bv - A) / np.linalg.norm(Bv - A)
+        u = np.cross(lvec, n)                       # outward in-plane edge normal (CCW)
+        t0 = np.dot(A - rho, u)
+        lm = np.dot(A - rho, lvec); lp = np.dot(Bv - rho, lvec)
+        Rm = np.linalg.norm(A - x); Rp = np.linalg.norm(Bv - x)
+        R0 = math.hypot(t0, h)
+        if R0 > 1e-14:
+            val += t0 * math.log((Rp + lp) / (Rm + lm))
+        ah = abs(h)
+        val -= ah * (math.atan2(t0 * lp, R0 * R0 + ah * Rp) - math.atan2(t0 * lm, R0 * R0 + ah * Rm))
+    return val
+
+
+def _outer_rule(P, n):
+    """Points and weights of a fine rule on triangle P: three centroid sub-triangles, each with
+    an n x n Gauss-Legendre Duffy rule (collapsed at the centroid)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x = 0.5 * (x + 1); w = 0.5 * w
+    c = P.mean(0)
+    pts, wts = [], []
+    for e in range(3):
+        A, Bv = P[e], P[(e + 1) % 3]
+        area = 0.5 * np.linalg.norm(np.cross(A - c, Bv - c))
+        for s, ws in zip(x, w):
+            for t, wt in zip(x, w):
+                pts.append(c + s * (A - c) + s * t * (Bv - A))
+                wts.append(2 * area * s * ws * wt)
+    return np.array(pts), np.array(wts)
+
+
+@pytest.mark.parametrize("rel", ["coincident", "edge", "vertex"])
+def test_singular_rules_against_closed_form_potential(oracle_mod, rel):
+    """P10: with psi = tilde psi = 1 the kernel is 1/|x-y|.  Brute force: the closed-form
+    potential of sigma at every point of a fine rule on tau.  The order-4 Sauter-Schwab value
+    is within its quadrature error of it; order 10 agrees to ~1e-7."""
+    xyz, tri, pairs = _two_triangle_meshes()
+    ex, ey = pairs[rel]
+    P, nx, ax, _ = _geom(xyz, tri, ex)
+    Q, ny, ay, _ = _geom(xyz, tri, ey)
+    pts, wts = _outer_rule(P, 60)
+    V = np.array([_flat_triangle_potential(Q, p) for p in pts])
+    bf = np.dot(wts, V) / (4 * np.pi)                    # sum over a, b of lam_a lam_b / (4 pi r)
+    ss4 = oracle_mod.pair_local(xyz, tri, ex, ey, np.array([0.0, 1.0]), mode="one", ss_order=4)[0, 0]
+    ss10 = oracle_mod.pair_local(xyz, tri, ex, ey, np.array([0.0, 1.0]), mode="one", ss_order=10)[0, 0]
+    # nn * S1 summed over a,b = nn * int int 1/(4 pi r); curl terms sum to zero over a (or b)
+    tot4 = ss4.sum() / np.dot(nx, ny)
+    tot10 = ss10.sum() / np.dot(nx, ny)
+    assert abs(tot10 - bf) < 1e-6 * abs(bf), (tot10, bf)
+    assert abs(tot4 - bf) < 1e-3 * abs(bf), (tot4, bf)
+
+
+# --- assembled blocks ------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_blocks(oracle_mod):
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]
+    return c, oracle_mod.assemble_dense(xyz, tri, c["grid"], kind=c["cutoff"])
+
+
+def test_blocks_symmetric_and_hessenberg(small_blocks):
+    """P11 and P6: A_{k,i}(j,l) = A_{k,i}(l,j) exactly (the kernel is symmetric in x <-> y);
+    blocks with i >= k + 2 vanish (eq. (Apartitioned))."""
+    c, A = small_blocks
+    N = A.shape[0]
+    assert np.array_equal(A, A.transpose(0, 1, 3, 2))
+    for k in range(N):
+        for i in range(k + 2, N):
+            assert np.all(A[k, i] == 0.0)
+    assert np.abs(A[N - 1, N - 1]).max() > 0
+
+
+def test_curl_term_annihilates_constants(oracle_mod):
+    """P12: sum_j curl phi_j = curl 1 = 0, so the curl-curl part of every block has zero row
+    sums: sum_j A^curl_{k,i}(j,l) = 0."""
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]
+    A = oracle_mod.assemble_dense(xyz, tri, c["grid"], kind=c["cutoff"], mode="curl", ss_order=2)
+    full = oracle_mod.assemble_dense(xyz, tri, c["grid"], kind=c["cutoff"], mode="nn", ss_order=2)
+    assert np.abs(A.sum(axis=2)).max() < 1e-12 * np.abs(A).max()
+    assert np.abs(full.sum(axis=2)).max() > 1e-3 * np.abs(full).max()
+
+
+def test_selected_entries_match_dense(oracle_mod, small_blocks):
+    """The per-entry assembly path reproduces the dense assembly (same discrete definition)."""
+    c, A = small_blocks
+    xyz, tri = c["mesh"]
+    M = len(xyz)
+    rng = np.random.default_rng(7)
+    sj = rng.integers(0, M, 6); sl = rng.integers(0, M, 6)
+    sj[0] = sl[0]
+    sel = oracle_mod.assemble_entries(xyz, tri, c["grid"], sj, sl, kind=c["cutoff"])
+    for s in range(len(sj)):
+        ref = A[:, :, sj[s], sl[s]]
+        assert np.allclose(sel[s], ref, rtol=0, atol=1e-15 * np.abs(A).max())
+
+
+def test_block_count_formula():
+    """P16: the number of inner non-zero blocks on an equidistant grid is
+    n_z = (N^2 - N - 4)/2 - (N - n~_z - 2)/2 max(N - n~_z - 1, 0) (Section 5.1), where n~_z is
+    the number of non-zero blocks in the first inner column; Fig. 5.3 has N = 8, n~_z = 3 and
+    20 blocks.  Counted here from the supports (Section 3.2) for several diameters."""
+    for N, T, diam in [(8, 7.0, 1.0), (12, 4.0, 2.0), (20, 6.0, 1.3), (10, 4.0, 3.9)]:
+        grid = equidistant_grid(N, T)
+        tm = lambda j: grid[max(j - 1, 0)]
+        tp = lambda j: grid[min(j + 1, N - 1)]
+        nz = lambda k, i: max(0.0, tm(k) - tp(i)) < min(diam, tp(k) - tm(i))
+        inner = range(1, N - 1)
+        count = sum(1 for k in inner for i in inner if nz(k, i))
+        ntz = sum(1 for k in inner if nz(k, 1) and k >= 1)
+        formula = 0.5 * (N * N - N - 4) - 0.5 * (N - ntz - 2) * max(N - ntz - 1, 0)
+        assert count == formula, (N, T, diam, count, formula, ntz)
+    assert 0.5 * (64 - 8 - 4) - 0.5 * (8 - 3 - 2) * max(8 - 3 - 1, 0) == 20
+
+
+# --- solver (Section 4, Algorithm 1) ---------------------------------------------------------
+def test_fgmres_and_alg1_against_lu(oracle_mod, small_blocks):
+    """P15: FGMRES with and without the recursive block-Hessenberg preconditioner reaches the
+    LAPACK solution of the assembled system within the conditioning times the tolerance."""
+    c, A = small_blocks
+    xyz, tri = c["mesh"]
+    N, _, M, _ = A.shape
+    Af = oracle_mod.system_matrix(A)
+    g = oracle_mod.rhs_plane_pulse(xyz, tri, c["grid"], c["direction"], c["t0"], c["width"], kind=c["cutoff"])
+    ref = np.linalg.solve(Af, g)
+    kappa = np.linalg.cond(Af)
+    for inner in (None, [2, 10], [5]):
+        x, its, hist = oracle_mod.solve(Af, g, N, M, tol=1e-10, restart=30, max_it=3000, alg1_inner=inner)
+        res = np.linalg.norm(g - Af @ x) / np.linalg.norm(g)
+        assert res <= 1e-10 * 1.0001, (inner, res, its)
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= kappa * 1e-10
+    # the preconditioner reduces the outer iteration count
+    _, it_plain, _ = oracle_mod.solve(Af, g, N, M, tol=1e-10, restart=30, max_it=3000)
+    _, it_prec, _ = oracle_mod.solve(Af, g, N, M, tol=1e-10, restart=30, max_it=3000, alg1_inner=[2, 10])
+    assert it_prec < it_plain
+
+
+def test_rhs_against_direct_integration(oracle_mod):
+    """The plane-pulse RHS g_k(l) = int int g phi_l b_k' (Section 3) with g = G'(t-t0-d.x)(d.n):
+    spot values against scipy adaptive integration in time at the 7 spatial points."""
+    from scipy.integrate import quad
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]
+    grid = c["grid"]; N = len(grid); M = len(xyz)
+    d = c["direction"]; w = c["width"]; t0 = c["t0"]
+    g = oracle_mod.rhs_plane_pulse(xyz, tri, grid, d, t0, w, kind="erf")
+    B, W = oracle_mod.rule7()
+    for k in (0, 2, N - 1):
+        ref = np.zeros(M)
+        for e in range(len(tri)):
+            P, n, area, _ = _geom(xyz, tri, e)
+            for q in range(7):
+                x = B[q] @ P
+                f = lambda t: (-2 * (t - t0 - d @ x) / w ** 2 * math.exp(-((t - t0 - d @ x) / w) ** 2)
+                               * oracle_mod.basis(grid, k, t, "erf")[1])
+                lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, N - 1)]
+                val = quad(f, lo, hi, points=[grid[k]], epsabs=1e-14, epsrel=1e-13, limit=200)[0]
+                ref[tri[e]] += area * W[q] * np.dot(d, n) * val * B[q]
+        assert np.abs(g[k * M:(k + 1) * M] - ref).max() < 1e-11 * np.abs(ref).max()
