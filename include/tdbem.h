@@ -1,0 +1,152 @@
+/*
+ * tdbem.h -- C ABI of the MI355X (gfx950) space-time Galerkin solver for the sound-hard
+ * time-domain boundary integral equation of Veit, Merta, Zapletal and Lukas
+ * (arXiv:1503.07221).
+ *
+ * The library assembles the block-Hessenberg system A alpha = g of the space-time Galerkin
+ * discretisation of the hypersingular equation W phi = g (Section 2, eqs. (BIE) and
+ * (VarForm)) with P1 hats phi_j on flat triangles and one smooth, compactly supported
+ * temporal basis b_i per time node (Section 3, eq. (BasisFunctions) with p = 0), and solves it
+ * with FGMRES and the recursive block-Hessenberg preconditioner of Section 4.2 (Algorithm 1).
+ *
+ * Conventions
+ *   - Every call returns a tdbem_status; 0 is success, negative values are errors, positive
+ *     values are warnings.  Errors never abort: the message is kept and returned by
+ *     tdbem_last_error() until the next call on the same context.
+ *   - Host arrays passed in are copied; the caller keeps ownership.
+ *   - Device pointers (vectors of the solve and the matvec) belong to the caller, must live in
+ *     device memory of the context's device and are used in place on the context's stream.
+ *   - Vectors follow the block partition of eq. (A): x[i*M + j] multiplies b_i(t) phi_j(x);
+ *     row (k, l) of the system is y[k*M + l].  Indices are 0-based.
+ *   - A_{k,i}(j, l) is the entry of eq. (MatrixEntries): test functions (b_k, phi_l) in the
+ *     x variable, trial functions (b_i, phi_j) in the y variable.
+ *   - One context per host thread; calls on one context are not thread safe.
+ */
+#ifndef TDBEM_H
+#define TDBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdbem_ctx tdbem_ctx;
+
+typedef enum {
+    TDBEM_OK = 0,
+    TDBEM_NOT_CONVERGED = 1,     /* warning: the solve stopped at max_it above tol */
+    TDBEM_EINVAL = -1,           /* invalid argument (null pointer, bad size or option) */
+    TDBEM_EMESH = -2,            /* mesh rejected (bad index, degenerate triangle) */
+    TDBEM_EGRID = -3,            /* time grid rejected (t_0 != 0, not increasing, N < 2) */
+    TDBEM_ENOMEM = -4,           /* device allocation failed or the matrix exceeds the limit */
+    TDBEM_EHIP = -5,             /* HIP runtime error */
+    TDBEM_ESTATE = -6            /* call out of order (e.g. matvec before assemble) */
+} tdbem_status;
+
+typedef enum {
+    TDBEM_CUTOFF_BUMP = 0,       /* F(u) = beta(u-1)/(beta(u-1)+beta(u)), beta = exp(-1/(1-s^2)) */
+    TDBEM_CUTOFF_ERF = 1         /* the paper's f(s) = erf(2 artanh s)/2 + 1/2, F(u) = f(2u-1) */
+} tdbem_cutoff;
+
+typedef enum {
+    TDBEM_FP64 = 0,              /* FP64 quadrature and FP64 matrix storage */
+    TDBEM_MIXED = 1              /* FP32 regular far-field quadrature, FP32 matrix storage;
+                                    FP64 singular pairs, tables, solver vectors and sums */
+} tdbem_precision;
+
+typedef struct {
+    int32_t device;              /* HIP device ordinal */
+    void *stream;                /* hipStream_t to run on; NULL: the library creates one */
+    int32_t ss_order;            /* Gauss points per direction of the Sauter-Schwab rules (4) */
+} tdbem_options;
+
+typedef struct {
+    int64_t quad_evals;          /* (x_q, y_q', k, i) with r inside supp psi_{k,i}, unordered pairs */
+    int64_t pairs_regular;       /* unordered triangle pairs without a common vertex */
+    int64_t pairs_coincident, pairs_edge, pairs_vertex;
+    int64_t table_functions;     /* (k, i) kernels tabulated */
+    int64_t bytes_matrix;        /* device bytes of the assembled blocks */
+    double ms_tables, ms_layout, ms_regular, ms_singular, ms_total;
+} tdbem_assembly_report;
+
+typedef struct {
+    int32_t restart;             /* Krylov dimension between restarts (30) */
+    double tol;                  /* relative residual ||g - A alpha|| / ||g|| to reach (1e-8) */
+    int32_t max_it;              /* outer iteration limit */
+    int32_t precond_levels;      /* 0: none; r > 0: Algorithm 1 with r recursion levels */
+    int32_t precond_inner[8];    /* inner FGMRES iterations on each level, e.g. {2, 10} */
+} tdbem_solve_opts;
+
+typedef struct {
+    int32_t iterations;          /* outer FGMRES iterations */
+    int64_t matvecs;             /* block-operator products of any size, outer and inner */
+    double rel_residual;         /* true ||g - A alpha|| / ||g|| at return */
+    double ms;                   /* wall time of the solve */
+} tdbem_solve_report;
+
+/* Create a context on opt->device (opt may be NULL: device 0, own stream, ss_order 4). */
+tdbem_status tdbem_create(tdbem_ctx **out, const tdbem_options *opt);
+
+/* Release everything the context owns.  NULL is accepted. */
+void tdbem_destroy(tdbem_ctx *ctx);
+
+/* Message of the last error on ctx ("" if none); valid until the next call on ctx. */
+const char *tdbem_last_error(const tdbem_ctx *ctx);
+
+/* Surface mesh Gamma (Section 3): M vertices xyz[3*v + c] (host, float64) and E flat
+ * triangles tri[3*e + a] (host, int32, 0-based, counter-clockwise seen from the side the
+ * normal n of eq. (FullProblem) points to).  Resets any assembled matrix.
+ * TDBEM_EMESH for an index out of range, a repeated vertex in a triangle or a zero area. */
+tdbem_status tdbem_set_mesh(tdbem_ctx *ctx, const double *xyz, int64_t M, const int32_t *tri, int64_t E);
+
+/* Time grid 0 = t_0 < t_1 < ... < t_{N-1} = T (host, float64), one temporal basis per node
+ * (Section 3: mu_i from the cutoff, b_0 with the causal factor 8 (t/h_1)^2).  Resets any
+ * assembled matrix.  TDBEM_EGRID unless N >= 2, t_0 = 0 and t strictly increasing. */
+tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdbem_cutoff cutoff);
+
+/* Assemble every block A_{k,i} of eq. (MatrixEntries) on the device (Section 3): kernels
+ * psi_{k,i}, tilde psi_{k,i} of eq. (psis) tabulated as piecewise Chebyshev series
+ * (Section 3.1), 7-point rule for pairs without a common vertex, Sauter-Schwab rules for
+ * coincident, edge and vertex pairs, entries kept where supp psi_{k,i} meets the distance
+ * range of the two hats (eq. (SparsitySmallBlock)).  rep may be NULL.
+ * TDBEM_ESTATE without mesh and grid, TDBEM_ENOMEM if the storage does not fit. */
+tdbem_status tdbem_assemble(tdbem_ctx *ctx, tdbem_precision prec, tdbem_assembly_report *rep);
+
+/* Copy selected entries to the host: out[s] = A_{k[s], i[s]}(j[s], l[s]) for s < n (host
+ * arrays).  Entries outside the stored band are zero by eq. (SparsitySmallBlock). */
+tdbem_status tdbem_get_entries(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,
+                               const int32_t *j, const int32_t *l, double *out);
+
+/* Evaluate the tabulated time kernels used by the assembly: psi[s] = psi_{k[s],i[s]}(r[s]) and
+ * tpsi[s] = tilde psi_{k[s],i[s]}(r[s]) of eq. (psis) for n host points (host arrays), 0 outside
+ * the open support (Section 3.2).  Requires a completed tdbem_assemble. */
+tdbem_status tdbem_eval_kernels(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,
+                                const double *r, double *psi, double *tpsi);
+
+/* Right-hand side g_k(l) = int_0^T int_Gamma g phi_l b_k' (Section 3) of the plane Gaussian
+ * pulse u_inc = exp(-((t - t0 - d.x)/width)^2), g = -d u_inc/d n, written to the device
+ * vector g (N*M float64).  d is the propagation direction, a host array of 3 doubles used as
+ * given (a unit vector for a plane wave of speed 1). */
+tdbem_status tdbem_rhs_plane_pulse(tdbem_ctx *ctx, const double d[3], double t0, double width, double *g);
+
+/* y = A x for device vectors x, y of N*M float64 (the block matvec of Section 3.2). */
+tdbem_status tdbem_matvec(tdbem_ctx *ctx, const double *x, double *y);
+
+/* y = A[k0:k1, i0:i1] x for the time-block sub-operator: x holds blocks i0..i1-1
+ * ((i1-i0)*M values), y receives blocks k0..k1-1 ((k1-k0)*M values).  Used by Algorithm 1. */
+tdbem_status tdbem_matvec_range(tdbem_ctx *ctx, int32_t k0, int32_t k1, int32_t i0, int32_t i1,
+                                const double *x, double *y);
+
+/* Solve A alpha = g (device vectors, N*M float64) with FGMRES(restart) (Saad 1993) from
+ * alpha = 0, right-preconditioned by Algorithm 1 when opts->precond_levels > 0.  On return
+ * alpha holds the iterate; TDBEM_NOT_CONVERGED if the true relative residual is above tol
+ * after max_it outer iterations.  rep may be NULL. */
+tdbem_status tdbem_solve(tdbem_ctx *ctx, const double *g, double *alpha, const tdbem_solve_opts *opts,
+                         tdbem_solve_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDBEM_H */

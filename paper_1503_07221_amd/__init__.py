@@ -1,0 +1,215 @@
+"""Python binding of libtdbem, the MI355X space-time Galerkin TDBIE library (arXiv:1503.07221).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``csrc/`` behind the C ABI of ``include/tdbem.h``.  PyTorch provides device memory and the
+stream; there is no CPU fallback, and a missing or unloadable library raises at import of the
+context.
+
+Vector layout (eq. (A) block partition): ``x[i*M + j]`` multiplies ``b_i(t) phi_j(x)``.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB_PATH, build_library
+
+__all__ = ["Context", "TdbemError", "load_library", "build_library", "LIB_PATH", "EXPORTED_SYMBOLS",
+           "FP64", "MIXED", "CUTOFF_BUMP", "CUTOFF_ERF"]
+
+FP64, MIXED = 0, 1
+CUTOFF_BUMP, CUTOFF_ERF = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -4: "ENOMEM", -5: "EHIP",
+          -6: "ESTATE"}
+
+EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
+                    "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
+                    "tdbem_matvec", "tdbem_matvec_range", "tdbem_solve"]
+
+
+class TdbemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tdbem {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("ss_order", ctypes.c_int32)]
+
+
+class AssemblyReport(ctypes.Structure):
+    _fields_ = [("quad_evals", ctypes.c_int64), ("pairs_regular", ctypes.c_int64),
+                ("pairs_coincident", ctypes.c_int64), ("pairs_edge", ctypes.c_int64),
+                ("pairs_vertex", ctypes.c_int64), ("table_functions", ctypes.c_int64),
+                ("bytes_matrix", ctypes.c_int64), ("ms_tables", ctypes.c_double), ("ms_layout", ctypes.c_double),
+                ("ms_regular", ctypes.c_double), ("ms_singular", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
+                ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("matvecs", ctypes.c_int64), ("rel_residual", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libtdbem.so (built in-tree by build_library())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtdbem.so not found at {path}; run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.tdbem_create.argtypes = [P(vp), P(_Options)]
+    L.tdbem_destroy.argtypes = [vp]
+    L.tdbem_destroy.restype = None
+    L.tdbem_last_error.argtypes = [vp]
+    L.tdbem_last_error.restype = ctypes.c_char_p
+    L.tdbem_set_mesh.argtypes = [vp, P(dp), i64, P(i32), i64]
+    L.tdbem_set_time_grid.argtypes = [vp, P(dp), i32, ctypes.c_int]
+    L.tdbem_assemble.argtypes = [vp, ctypes.c_int, P(AssemblyReport)]
+    L.tdbem_get_entries.argtypes = [vp, i64, P(i32), P(i32), P(i32), P(i32), P(dp)]
+    L.tdbem_eval_kernels.argtypes = [vp, i64, P(i32), P(i32), P(dp), P(dp), P(dp)]
+    L.tdbem_rhs_plane_pulse.argtypes = [vp, P(dp), dp, dp, vp]
+    L.tdbem_matvec.argtypes = [vp, vp, vp]
+    L.tdbem_matvec_range.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
+    for name in EXPORTED_SYMBOLS:
+        if name not in ("tdbem_destroy", "tdbem_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Context:
+    """One library context on a HIP device, running on torch's current stream of that device."""
+
+    def __init__(self, device=0, ss_order=4):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("tdbem needs a HIP device (torch.cuda.is_available() is False)")
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.current_stream(self.device)
+        opt = _Options(device, ctypes.c_void_p(self.stream.cuda_stream), ss_order)
+        h = ctypes.c_void_p()
+        st = self.lib.tdbem_create(ctypes.byref(h), ctypes.byref(opt))
+        if st != 0:
+            raise TdbemError(st, "context creation failed")
+        self.h = h
+        self.M = self.E = self.N = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdbem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st < 0 or st > 1:
+            raise TdbemError(st, self.lib.tdbem_last_error(self.h).decode())
+        return st
+
+    def set_mesh(self, xyz, tri):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self._check(self.lib.tdbem_set_mesh(self.h, _dptr(xyz), xyz.shape[0], _iptr(tri), tri.shape[0]))
+        self.M, self.E = xyz.shape[0], tri.shape[0]
+
+    def set_time_grid(self, t, cutoff="bump"):
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        c = {"bump": CUTOFF_BUMP, "erf": CUTOFF_ERF}[cutoff] if isinstance(cutoff, str) else int(cutoff)
+        self._check(self.lib.tdbem_set_time_grid(self.h, _dptr(t), len(t), c))
+        self.N = len(t)
+
+    def assemble(self, precision=FP64):
+        rep = AssemblyReport()
+        self._check(self.lib.tdbem_assemble(self.h, int(precision), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def get_entries(self, k, i, j, l):
+        k, i, j, l = (np.ascontiguousarray(np.broadcast_to(a, np.broadcast(k, i, j, l).shape).ravel(), dtype=np.int32)
+                      for a in (k, i, j, l))
+        out = np.zeros(len(k))
+        self._check(self.lib.tdbem_get_entries(self.h, len(k), _iptr(k), _iptr(i), _iptr(j), _iptr(l), _dptr(out)))
+        return out
+
+    def eval_kernels(self, k, i, r):
+        k = np.ascontiguousarray(k, dtype=np.int32).ravel()
+        i = np.ascontiguousarray(i, dtype=np.int32).ravel()
+        r = np.ascontiguousarray(r, dtype=np.float64).ravel()
+        ps = np.zeros(len(r)); pt = np.zeros(len(r))
+        self._check(self.lib.tdbem_eval_kernels(self.h, len(r), _iptr(k), _iptr(i), _dptr(r), _dptr(ps), _dptr(pt)))
+        return ps, pt
+
+    def _vec(self, n=None):
+        return self.torch.empty(self.N * self.M if n is None else n, dtype=self.torch.float64, device=self.device)
+
+    def _dev(self, x, n):
+        if not (x.is_cuda and x.dtype == self.torch.float64 and x.is_contiguous() and x.numel() == n):
+            raise ValueError(f"expected a contiguous float64 device tensor of {n} values")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def rhs_plane_pulse(self, direction, t0, width, out=None):
+        d = np.ascontiguousarray(direction, dtype=np.float64)
+        g = self._vec() if out is None else out
+        self._check(self.lib.tdbem_rhs_plane_pulse(self.h, _dptr(d), float(t0), float(width),
+                                                   self._dev(g, self.N * self.M)))
+        return g
+
+    def matvec(self, x, out=None):
+        y = self._vec() if out is None else out
+        n = self.N * self.M
+        self._check(self.lib.tdbem_matvec(self.h, self._dev(x, n), self._dev(y, n)))
+        return y
+
+    def matvec_range(self, k0, k1, i0, i1, x, out=None):
+        y = self._vec((k1 - k0) * self.M) if out is None else out
+        self._check(self.lib.tdbem_matvec_range(self.h, k0, k1, i0, i1, self._dev(x, (i1 - i0) * self.M),
+                                                self._dev(y, (k1 - k0) * self.M)))
+        return y
+
+    def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None):
+        """FGMRES(restart) from 0 to ||g - A alpha|| <= tol ||g||, with Algorithm 1 when
+        precond_inner lists inner iterations per level (e.g. (2, 10))."""
+        n = self.N * self.M
+        alpha = self._vec() if out is None else out
+        o = SolveOpts()
+        o.restart, o.tol, o.max_it = int(restart), float(tol), int(max_it)
+        o.precond_levels = len(precond_inner)
+        for s, v in enumerate(precond_inner):
+            o.precond_inner[s] = int(v)
+        rep = SolveReport()
+        st = self._check(self.lib.tdbem_solve(self.h, self._dev(g, n), self._dev(alpha, n), ctypes.byref(o),
+                                              ctypes.byref(rep)))
+        d = rep.as_dict()
+        d["converged"] = st == 0
+        return alpha, d

@@ -1,0 +1,923 @@
+// Host runtime and C ABI of libtdbem (see include/tdbem.h).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tdbem.h"
+#include "tdbem_internal.hpp"
+
+using namespace tdbem;
+
+namespace {
+
+// Owned device allocation.
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b)
+    {
+        release();
+        if (b == 0) b = 8;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) p = nullptr;
+        else bytes = b;
+        return e;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton's method on the three-term recurrence.
+void gauss_legendre(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                const double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int m = 2; m <= n; ++m) {
+            const double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = -z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Graded partition of [0, 1] used for every tabulated interval: geometric with ratio 1.6 from
+// 0.004 until a piece would exceed 1/8, uniform pieces of width <= 1/8 in the middle, mirrored.
+PieceTable make_piece_table()
+{
+    const double q = 1.6, fmin = 0.004, wmax = 1.0 / 8.0;
+    std::vector<double> left{fmin};
+    double x = fmin;
+    while (x * (q - 1.0) < wmax) {
+        x *= q;
+        left.push_back(x);
+    }
+    const double xs = left.back();
+    const int nm = (int)std::ceil((1.0 - 2.0 * xs) / wmax - 1e-12);
+    std::vector<double> e{0.0};
+    for (size_t s = 0; s + 1 < left.size(); ++s) e.push_back(left[s]);
+    for (int s = 0; s <= nm; ++s) e.push_back(xs + (1.0 - 2.0 * xs) * s / nm);
+    for (size_t s = left.size() - 1; s-- > 0;) e.push_back(1.0 - left[s]);
+    e.push_back(1.0);
+    PieceTable pt;
+    if ((int)e.size() != kPieces + 1) {
+        std::fprintf(stderr, "tdbem: piece partition has %zu edges, expected %d\n", e.size(), kPieces + 1);
+    }
+    for (int s = 0; s <= kPieces; ++s) pt.edge[s] = e[std::min<size_t>(s, e.size() - 1)];
+    for (int s = 0; s < kPieces; ++s) pt.inv_width[s] = 1.0 / (pt.edge[s + 1] - pt.edge[s]);
+    return pt;
+}
+
+// Sauter-Schwab regions on the reference triangle {0 <= x2 <= x1 <= 1} (Sauter & Schwab,
+// Boundary Element Methods, Sec. 5.2): identical (6 regions, J = xi^3 e1^2 e2), common edge A-B
+// (5 regions, J = xi^3 e1^2 for the first, xi^3 e1^2 e2 for the others), common vertex A
+// (2 regions, J = xi^3 e2).  Rows (x1, x2, y1, y2, weight) for an n^4 Gauss rule per region.
+void ss_point(int kind, int reg, double xi, double e1, double e2, double e3, double* o)
+{
+    double J;
+    if (kind == 0) {
+        J = xi * xi * xi * e1 * e1 * e2;
+        const double A = xi, B1 = xi * (1 - e1 + e1 * e2), C1 = xi * (1 - e1 * e2 * e3), D1 = xi * (1 - e1);
+        const double B2 = xi * e1 * (1 - e2 + e2 * e3), C2 = xi * (1 - e1 * e2), D2 = xi * e1 * (1 - e2);
+        const double C3 = xi * (1 - e1 * e2 * e3), D3 = xi * e1 * (1 - e2 * e3);
+        switch (reg) {
+        case 0: o[0] = A; o[1] = B1; o[2] = C1; o[3] = D1; break;
+        case 1: o[0] = C1; o[1] = D1; o[2] = A; o[3] = B1; break;
+        case 2: o[0] = A; o[1] = B2; o[2] = C2; o[3] = D2; break;
+        case 3: o[0] = C2; o[1] = D2; o[2] = A; o[3] = B2; break;
+        case 4: o[0] = C3; o[1] = D3; o[2] = A; o[3] = D2; break;
+        default: o[0] = A; o[1] = D2; o[2] = C3; o[3] = D3; break;
+        }
+    } else if (kind == 1) {
+        J = xi * xi * xi * e1 * e1 * (reg == 0 ? 1.0 : e2);
+        switch (reg) {
+        case 0: o[0] = xi; o[1] = xi * e1 * e3; o[2] = xi * (1 - e1 * e2); o[3] = xi * e1 * (1 - e2); break;
+        case 1: o[0] = xi; o[1] = xi * e1; o[2] = xi * (1 - e1 * e2 * e3); o[3] = xi * e1 * e2 * (1 - e3); break;
+        case 2: o[0] = xi * (1 - e1 * e2); o[1] = xi * e1 * (1 - e2); o[2] = xi; o[3] = xi * e1 * e2 * e3; break;
+        case 3: o[0] = xi * (1 - e1 * e2 * e3); o[1] = xi * e1 * e2 * (1 - e3); o[2] = xi; o[3] = xi * e1; break;
+        default: o[0] = xi * (1 - e1 * e2 * e3); o[1] = xi * e1 * (1 - e2 * e3); o[2] = xi; o[3] = xi * e1 * e2; break;
+        }
+    } else {
+        J = xi * xi * xi * e2;
+        if (reg == 0) { o[0] = xi; o[1] = xi * e1; o[2] = xi * e2; o[3] = xi * e2 * e3; }
+        else { o[0] = xi * e2; o[1] = xi * e2 * e3; o[2] = xi; o[3] = xi * e1; }
+    }
+    o[4] = J;
+}
+
+}  // namespace
+
+struct tdbem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int ss_order = 4;
+    std::string err;
+
+    int M = 0, E = 0, N = 0, cut = 0;
+    std::vector<double> xyz, t;
+    std::vector<int32_t> tri;
+    double diam = 0.0;
+    bool have_mesh = false, have_grid = false;
+
+    // mesh on the device
+    DBuf d_xyz, d_tri, d_rho, g_P, g_n, g_area, g_curl, g_qp, g_v, d_pairs, d_rules, d_roff, d_rcnt;
+    int64_t npairs = 0, npairs_kind[3] = {0, 0, 0};
+    // time grid
+    DBuf d_t;
+    TimeRule rule{};
+    PieceTable pieces{};
+    // tables
+    DBuf d_desc, d_fid, d_ivl, d_coef, d_fk, d_fi;
+    int64_t nfunc = 0;
+    // band storage
+    DBuf d_ilo, d_B, d_voff, d_val, d_counter;
+    std::vector<int32_t> Bk;
+    std::vector<int64_t> voff;
+    int64_t nvals = 0;
+    bool assembled = false;
+    int prec = 0;
+    // solver workspaces, one per recursion depth
+    struct Level {
+        DBuf V, Z, w, tmp, partial, h;
+        int m = 0;
+        int64_t n = 0;
+    };
+    std::vector<Level> levels;
+    int64_t matvecs = 0;
+
+    GeomView geom() const
+    {
+        GeomView g;
+        g.v = g_v.as<int32_t>();
+        g.P = g_P.as<double>();
+        g.n = g_n.as<double>();
+        g.area = g_area.as<double>();
+        g.curl = g_curl.as<double>();
+        g.qp = g_qp.as<double>();
+        g.E = E;
+        return g;
+    }
+    TableView tables() const
+    {
+        TableView tv;
+        tv.desc = d_desc.as<KernelDesc>();
+        tv.fid = d_fid.as<int32_t>();
+        tv.ivl = d_ivl.as<double>();
+        tv.coef = d_coef.as<double2>();
+        tv.N = N;
+        tv.pt = pieces;
+        return tv;
+    }
+    BandView band() const
+    {
+        BandView b;
+        b.ilo = d_ilo.as<int16_t>();
+        b.B = d_B.as<int32_t>();
+        b.voff = d_voff.as<int64_t>();
+        b.M = M;
+        b.N = N;
+        return b;
+    }
+    const double* valf64() const { return prec == TDBEM_FP64 ? d_val.as<double>() : nullptr; }
+    const float* valf32() const { return prec == TDBEM_FP64 ? nullptr : d_val.as<float>(); }
+};
+
+#define FAIL(ctx, code, ...)                                                                  \
+    do {                                                                                      \
+        char _b[512];                                                                         \
+        std::snprintf(_b, sizeof(_b), __VA_ARGS__);                                           \
+        (ctx)->err = _b;                                                                      \
+        return code;                                                                          \
+    } while (0)
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) FAIL(ctx, TDBEM_EHIP, "%s: %s", #expr, hipGetErrorString(_e));  \
+    } while (0)
+
+#define ALLOC(ctx, buf, bytes)                                                                \
+    do {                                                                                      \
+        if ((buf).alloc(bytes) != hipSuccess) {                                               \
+            (void)hipGetLastError();                                                          \
+            FAIL(ctx, TDBEM_ENOMEM, "device allocation of %zu bytes failed", (size_t)(bytes)); \
+        }                                                                                     \
+    } while (0)
+
+static tdbem_status set_device(tdbem_ctx* c)
+{
+    HIPCHK(c, hipSetDevice(c->device));
+    return TDBEM_OK;
+}
+
+template <typename T>
+static tdbem_status upload(tdbem_ctx* c, DBuf& buf, const T* host, size_t n)
+{
+    ALLOC(c, buf, sizeof(T) * n);
+    if (n) HIPCHK(c, hipMemcpyAsync(buf.p, host, sizeof(T) * n, hipMemcpyHostToDevice, c->stream));
+    return TDBEM_OK;
+}
+
+#define TRY(expr)                                   \
+    do {                                            \
+        tdbem_status _s = (expr);                   \
+        if (_s != TDBEM_OK) return _s;              \
+    } while (0)
+
+extern "C" {
+
+tdbem_status tdbem_create(tdbem_ctx** out, const tdbem_options* opt)
+{
+    if (!out) return TDBEM_EINVAL;
+    *out = nullptr;
+    tdbem_ctx* c = new tdbem_ctx();
+    c->device = opt ? opt->device : 0;
+    c->ss_order = opt && opt->ss_order > 0 ? opt->ss_order : 4;
+    if (c->ss_order > 12) { delete c; return TDBEM_EINVAL; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
+        (void)hipGetLastError();
+        delete c;
+        return TDBEM_EHIP;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) { delete c; return TDBEM_EHIP; }
+    if (opt && opt->stream) {
+        c->stream = static_cast<hipStream_t>(opt->stream);
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return TDBEM_EHIP; }
+        c->own_stream = true;
+    }
+    double x[kTimeGauss], w[kTimeGauss];
+    gauss_legendre(kTimeGauss, x, w);
+    for (int q = 0; q < kTimeGauss; ++q) { c->rule.x[q] = x[q]; c->rule.w[q] = w[q]; }
+    c->pieces = make_piece_table();
+    *out = c;
+    return TDBEM_OK;
+}
+
+void tdbem_destroy(tdbem_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->levels.clear();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* tdbem_last_error(const tdbem_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const int32_t* tri, int64_t E)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!xyz || !tri || M < 3 || E < 1) FAIL(c, TDBEM_EINVAL, "mesh needs M >= 3 vertices and E >= 1 triangles");
+    if (M > 32767 * 2048LL || E > (1LL << 30)) FAIL(c, TDBEM_EINVAL, "mesh too large");
+    for (int64_t v = 0; v < 3 * M; ++v)
+        if (!std::isfinite(xyz[v])) FAIL(c, TDBEM_EMESH, "vertex coordinate %lld is not finite", (long long)v);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t a = tri[3 * e], b = tri[3 * e + 1], d = tri[3 * e + 2];
+        if (a < 0 || b < 0 || d < 0 || a >= M || b >= M || d >= M)
+            FAIL(c, TDBEM_EMESH, "triangle %lld has a vertex index out of range", (long long)e);
+        if (a == b || b == d || a == d) FAIL(c, TDBEM_EMESH, "triangle %lld repeats a vertex", (long long)e);
+        const double* P = xyz + 3 * a;
+        const double* Q = xyz + 3 * b;
+        const double* R = xyz + 3 * d;
+        const double u[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]}, w[3] = {R[0] - P[0], R[1] - P[1], R[2] - P[2]};
+        const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double ar = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double sc = u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        if (!(ar > 1e-14 * sc)) FAIL(c, TDBEM_EMESH, "triangle %lld is degenerate", (long long)e);
+    }
+    TRY(set_device(c));
+    c->assembled = false;
+    c->have_mesh = false;
+    c->M = (int)M;
+    c->E = (int)E;
+    c->xyz.assign(xyz, xyz + 3 * M);
+    c->tri.assign(tri, tri + 3 * E);
+    // diameter bound: bounding box diagonal
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < M; ++v)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], xyz[3 * v + d]);
+            hi[d] = std::max(hi[d], xyz[3 * v + d]);
+        }
+    c->diam = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                        (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    // patch radius of every vertex: farthest vertex of its triangles
+    std::vector<double> rho(M, 0.0);
+    std::vector<std::vector<int32_t>> vt(M);
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = tri[3 * e + a];
+            vt[v].push_back((int32_t)e);
+            for (int b = 0; b < 3; ++b) {
+                const int32_t u = tri[3 * e + b];
+                const double dx = xyz[3 * v] - xyz[3 * u], dy = xyz[3 * v + 1] - xyz[3 * u + 1],
+                             dz = xyz[3 * v + 2] - xyz[3 * u + 2];
+                rho[v] = std::max(rho[v], std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+        }
+    // singular pairs {tau <= sigma} sharing at least one vertex, grouped by kind
+    std::vector<int32_t> pk[3];
+    for (int64_t tau = 0; tau < E; ++tau) {
+        std::vector<int32_t> cand;
+        for (int a = 0; a < 3; ++a)
+            for (int32_t s : vt[tri[3 * tau + a]])
+                if (s >= tau) cand.push_back(s);
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        for (int32_t sig : cand) {
+            int sa[3], sb[3], ns = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    if (tri[3 * tau + a] == tri[3 * sig + b]) { sa[ns] = a; sb[ns] = b; ++ns; }
+            int kind, px[3], py[3];
+            if (ns == 3) {
+                kind = 0;
+                for (int a = 0; a < 3; ++a) px[a] = py[a] = a;
+            } else if (ns == 2) {
+                kind = 1;
+                int a0 = sa[0], a1 = sa[1], b0 = sb[0], b1 = sb[1];
+                if (tri[3 * tau + a0] > tri[3 * tau + a1]) { std::swap(a0, a1); std::swap(b0, b1); }
+                px[0] = a0; px[1] = a1; px[2] = 3 - a0 - a1;
+                py[0] = b0; py[1] = b1; py[2] = 3 - b0 - b1;
+            } else {
+                kind = 2;
+                for (int a = 0; a < 3; ++a) { px[a] = (sa[0] + a) % 3; py[a] = (sb[0] + a) % 3; }
+            }
+            const int32_t row[9] = {(int32_t)tau, sig, kind, px[0], px[1], px[2], py[0], py[1], py[2]};
+            pk[kind].insert(pk[kind].end(), row, row + 9);
+        }
+    }
+    std::vector<int32_t> pairs;
+    for (int kd = 0; kd < 3; ++kd) {
+        c->npairs_kind[kd] = (int64_t)pk[kd].size() / 9;
+        pairs.insert(pairs.end(), pk[kd].begin(), pk[kd].end());
+    }
+    c->npairs = (int64_t)pairs.size() / 9;
+    // Sauter-Schwab rules
+    const int n = c->ss_order;
+    std::vector<double> gx(n), gw(n);
+    gauss_legendre(n, gx.data(), gw.data());
+    for (int q = 0; q < n; ++q) { gx[q] = 0.5 * (gx[q] + 1.0); gw[q] *= 0.5; }
+    std::vector<double> rules;
+    int32_t roff[3], rcnt[3];
+    const int nreg[3] = {6, 5, 2};
+    for (int kd = 0; kd < 3; ++kd) {
+        roff[kd] = (int32_t)(rules.size() / 5);
+        for (int reg = 0; reg < nreg[kd]; ++reg)
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b)
+                    for (int d = 0; d < n; ++d)
+                        for (int f = 0; f < n; ++f) {
+                            double o[5];
+                            ss_point(kd, reg, gx[a], gx[b], gx[d], gx[f], o);
+                            o[4] *= gw[a] * gw[b] * gw[d] * gw[f];
+                            rules.insert(rules.end(), o, o + 5);
+                        }
+        rcnt[kd] = (int32_t)(rules.size() / 5) - roff[kd];
+    }
+    TRY(upload(c, c->d_xyz, c->xyz.data(), c->xyz.size()));
+    TRY(upload(c, c->d_tri, c->tri.data(), c->tri.size()));
+    TRY(upload(c, c->d_rho, rho.data(), rho.size()));
+    TRY(upload(c, c->d_pairs, pairs.data(), pairs.size()));
+    TRY(upload(c, c->d_rules, rules.data(), rules.size()));
+    TRY(upload(c, c->d_roff, roff, 3));
+    TRY(upload(c, c->d_rcnt, rcnt, 3));
+    ALLOC(c, c->g_P, sizeof(double) * 9 * E);
+    ALLOC(c, c->g_n, sizeof(double) * 3 * E);
+    ALLOC(c, c->g_area, sizeof(double) * E);
+    ALLOC(c, c->g_curl, sizeof(double) * 9 * E);
+    ALLOC(c, c->g_qp, sizeof(double) * 21 * E);
+    ALLOC(c, c->g_v, sizeof(int32_t) * 3 * E);
+    launch_geometry(c->d_xyz.as<double>(), c->d_tri.as<int32_t>(), c->E, c->g_P.as<double>(), c->g_n.as<double>(),
+                    c->g_area.as<double>(), c->g_curl.as<double>(), c->g_qp.as<double>(), c->g_v.as<int32_t>(),
+                    c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_mesh = true;
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem_cutoff cutoff)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!t) FAIL(c, TDBEM_EINVAL, "null time grid");
+    if (cutoff != TDBEM_CUTOFF_BUMP && cutoff != TDBEM_CUTOFF_ERF) FAIL(c, TDBEM_EINVAL, "unknown cutoff %d", (int)cutoff);
+    if (N < 2 || N > 4096) FAIL(c, TDBEM_EGRID, "need 2 <= N <= 4096 time nodes, got %d", N);
+    if (t[0] != 0.0) FAIL(c, TDBEM_EGRID, "t_0 must be 0");
+    for (int s = 0; s < N; ++s)
+        if (!std::isfinite(t[s])) FAIL(c, TDBEM_EGRID, "t_%d is not finite", s);
+    for (int s = 1; s < N; ++s)
+        if (!(t[s] > t[s - 1])) FAIL(c, TDBEM_EGRID, "time grid not strictly increasing at %d", s);
+    TRY(set_device(c));
+    c->assembled = false;
+    c->have_grid = false;
+    c->N = N;
+    c->cut = (int)cutoff;
+    c->t.assign(t, t + N);
+    TRY(upload(c, c->d_t, c->t.data(), c->t.size()));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_grid = true;
+    return TDBEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Assembly
+// ---------------------------------------------------------------------------------------------
+static tdbem_status build_tables(tdbem_ctx* c)
+{
+    const int N = c->N;
+    const double* t = c->t.data();
+    const double rcap = c->diam * (1.0 + 1e-9) + 1e-12;
+    std::vector<KernelDesc> desc;
+    std::vector<int32_t> fid((size_t)N * N, -1), fk, fi;
+    std::vector<double> ivl;
+    std::vector<int32_t> pc_f, pc_j, pc_p;
+    int64_t coef_off = 0;
+    for (int k = 0; k < N; ++k)
+        for (int i = 0; i < N; ++i) {
+            double lo, hi;
+            kernel_support(t, N, k, i, lo, hi);
+            if (!(hi > lo) || !(lo < rcap)) continue;
+            // node differences t_c - t_a inside the support split it into analytic intervals
+            std::vector<double> bp{lo};
+            for (int cc = k - 1; cc <= k + 1; ++cc)
+                for (int a = i - 1; a <= i + 1; ++a) {
+                    if (cc < 0 || cc >= N || a < 0 || a >= N) continue;
+                    const double d = t[cc] - t[a];
+                    if (d > lo && d < hi) bp.push_back(d);
+                }
+            std::sort(bp.begin(), bp.end());
+            const double tol = 1e-13 * (1.0 + t[N - 1]);
+            std::vector<double> uniq;
+            for (double b : bp)
+                if (uniq.empty() || b - uniq.back() > tol) uniq.push_back(b);
+            const double end = std::min(hi, rcap);
+            while (uniq.size() > 1 && uniq.back() >= end - tol) uniq.pop_back();
+            KernelDesc kd;
+            kd.lo = lo;
+            kd.hi = hi;
+            kd.nint = (int32_t)uniq.size();
+            kd.bp_off = (int32_t)ivl.size();
+            kd.coef_off = coef_off;
+            for (size_t s = 0; s < uniq.size(); ++s) {
+                const double a = uniq[s], b = s + 1 < uniq.size() ? uniq[s + 1] : end;
+                ivl.push_back(a);
+                ivl.push_back(1.0 / (b - a));
+            }
+            const int f = (int)desc.size();
+            fid[(size_t)k * N + i] = f;
+            desc.push_back(kd);
+            fk.push_back(k);
+            fi.push_back(i);
+            for (int j = 0; j < kd.nint; ++j)
+                for (int p = 0; p < kPieces; ++p) {
+                    pc_f.push_back(f);
+                    pc_j.push_back(j);
+                    pc_p.push_back(p);
+                }
+            coef_off += (int64_t)kd.nint * kPieces * kNc;
+        }
+    c->nfunc = (int64_t)desc.size();
+    const int64_t npieces = (int64_t)pc_f.size();
+    TRY(upload(c, c->d_desc, desc.data(), desc.size()));
+    TRY(upload(c, c->d_fid, fid.data(), fid.size()));
+    TRY(upload(c, c->d_ivl, ivl.data(), ivl.size()));
+    TRY(upload(c, c->d_fk, fk.data(), fk.size()));
+    TRY(upload(c, c->d_fi, fi.data(), fi.size()));
+    DBuf d_pcf, d_pcj, d_pcp, d_values;
+    TRY(upload(c, d_pcf, pc_f.data(), pc_f.size()));
+    TRY(upload(c, d_pcj, pc_j.data(), pc_j.size()));
+    TRY(upload(c, d_pcp, pc_p.data(), pc_p.size()));
+    ALLOC(c, d_values, sizeof(double2) * (size_t)npieces * kNc);
+    ALLOC(c, c->d_coef, sizeof(double2) * (size_t)npieces * kNc);
+    launch_table_values(c->d_t.as<double>(), N, c->cut, c->rule, c->pieces, d_pcf.as<int32_t>(), d_pcj.as<int32_t>(),
+                        d_pcp.as<int32_t>(), npieces, c->d_fk.as<int32_t>(), c->d_fi.as<int32_t>(),
+                        c->d_desc.as<KernelDesc>(), c->d_ivl.as<double>(), d_values.as<double2>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    launch_table_coefs(d_values.as<double2>(), npieces, c->d_coef.as<double2>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // the temporaries are released on return
+    return TDBEM_OK;
+}
+
+static tdbem_status build_layout(tdbem_ctx* c, int prec)
+{
+    const int64_t M = c->M, N = c->N;
+    ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * M * M));
+    ALLOC(c, c->d_B, sizeof(int32_t) * N);
+    HIPCHK(c, hipMemsetAsync(c->d_B.p, 0, sizeof(int32_t) * N, c->stream));
+    launch_layout(c->d_xyz.as<double>(), c->d_rho.as<double>(), c->M, c->d_t.as<double>(), c->N,
+                  c->d_ilo.as<int16_t>(), c->d_B.as<int32_t>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    c->Bk.assign(N, 0);
+    HIPCHK(c, hipMemcpyAsync(c->Bk.data(), c->d_B.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->voff.assign(N, 0);
+    int64_t tot = 0;
+    for (int k = 0; k < N; ++k) {
+        c->voff[k] = tot;
+        tot += (int64_t)c->Bk[k] * M * M;
+    }
+    c->nvals = tot;
+    TRY(upload(c, c->d_voff, c->voff.data(), c->voff.size()));
+    const size_t esz = prec == TDBEM_FP64 ? sizeof(double) : sizeof(float);
+    size_t freeb = 0, totb = 0;
+    HIPCHK(c, hipMemGetInfo(&freeb, &totb));
+    const size_t need = esz * (size_t)std::max<int64_t>(tot, 1);
+    if (need + (size_t)(1ull << 30) > freeb) {
+        c->d_val.release();
+        FAIL(c, TDBEM_ENOMEM, "band storage needs %.2f GB, %.2f GB free on the device", need / 1e9, freeb / 1e9);
+    }
+    ALLOC(c, c->d_val, need);
+    HIPCHK(c, hipMemsetAsync(c->d_val.p, 0, need, c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid before assembling");
+    if (prec != TDBEM_FP64 && prec != TDBEM_MIXED) FAIL(c, TDBEM_EINVAL, "unknown precision %d", (int)prec);
+    TRY(set_device(c));
+    c->assembled = false;
+    c->prec = (int)prec;
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() { for (int s = 0; s < 5; ++s) (void)hipEventDestroy(e[s]); }
+    } guard{ev};
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    TRY(build_tables(c));
+    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    TRY(build_layout(c, (int)prec));
+    ALLOC(c, c->d_counter, sizeof(unsigned long long) * 2);
+    HIPCHK(c, hipMemsetAsync(c->d_counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
+    HIPCHK(c, hipEventRecord(ev[2], c->stream));
+    double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
+    float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
+    unsigned long long* cnt = c->d_counter.as<unsigned long long>();
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, cnt, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
+                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), v64, v32, cnt + 1,
+                    c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    unsigned long long counts[2];
+    HIPCHK(c, hipMemcpy(counts, c->d_counter.p, sizeof(counts), hipMemcpyDeviceToHost));
+    c->assembled = true;
+    if (rep) {
+        float ms[4];
+        for (int s = 0; s < 4; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
+        rep->quad_evals = (int64_t)(counts[0] + counts[1]);
+        const int64_t E = c->E;
+        rep->pairs_coincident = c->npairs_kind[0];
+        rep->pairs_edge = c->npairs_kind[1];
+        rep->pairs_vertex = c->npairs_kind[2];
+        rep->pairs_regular = E * (E - 1) / 2 - c->npairs_kind[1] - c->npairs_kind[2];
+        rep->table_functions = c->nfunc;
+        rep->bytes_matrix = (int64_t)c->d_val.bytes;
+        rep->ms_tables = ms[0];
+        rep->ms_layout = ms[1];
+        rep->ms_regular = ms[2];
+        rep->ms_singular = ms[3];
+        rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3];
+    }
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_get_entries(tdbem_ctx* c, int64_t n, const int32_t* k, const int32_t* i, const int32_t* j,
+                               const int32_t* l, double* out)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!k || !i || !j || !l || !out))) FAIL(c, TDBEM_EINVAL, "bad entry query");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before reading entries");
+    if (n == 0) return TDBEM_OK;
+    TRY(set_device(c));
+    DBuf dk, di, dj, dl, dout;
+    TRY(upload(c, dk, k, n));
+    TRY(upload(c, di, i, n));
+    TRY(upload(c, dj, j, n));
+    TRY(upload(c, dl, l, n));
+    ALLOC(c, dout, sizeof(double) * n);
+    launch_get_entries(c->band(), c->valf64(), c->valf32(), n, dk.as<int32_t>(), di.as<int32_t>(), dj.as<int32_t>(),
+                       dl.as<int32_t>(), dout.as<double>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out, dout.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_eval_kernels(tdbem_ctx* c, int64_t n, const int32_t* k, const int32_t* i, const double* r,
+                                double* psi, double* tpsi)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!k || !i || !r || !psi || !tpsi))) FAIL(c, TDBEM_EINVAL, "bad kernel query");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before evaluating the kernel tables");
+    if (n == 0) return TDBEM_OK;
+    TRY(set_device(c));
+    DBuf dk, di, dr, dp, dt;
+    TRY(upload(c, dk, k, n));
+    TRY(upload(c, di, i, n));
+    TRY(upload(c, dr, r, n));
+    ALLOC(c, dp, sizeof(double) * n);
+    ALLOC(c, dt, sizeof(double) * n);
+    launch_table_eval(c->tables(), n, dk.as<int32_t>(), di.as<int32_t>(), dr.as<double>(), dp.as<double>(),
+                      dt.as<double>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(psi, dp.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(tpsi, dt.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_rhs_plane_pulse(tdbem_ctx* c, const double d[3], double t0, double width, double* g)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!d || !g) FAIL(c, TDBEM_EINVAL, "null argument");
+    if (!(width > 0.0) || !std::isfinite(t0)) FAIL(c, TDBEM_EINVAL, "pulse width must be > 0 and t0 finite");
+    if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
+    TRY(set_device(c));
+    launch_rhs(c->geom(), c->d_t.as<double>(), c->N, c->cut, c->rule, d[0], d[1], d[2], t0, width, c->M, g, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+static tdbem_status matvec_range(tdbem_ctx* c, int k0, int k1, int i0, int i1, const double* x, double* y)
+{
+    launch_matvec(c->band(), c->valf64(), c->valf32(), k0, k1, i0, i1, x, y, c->stream);
+    HIPCHK(c, hipGetLastError());
+    ++c->matvecs;
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_matvec_range(tdbem_ctx* c, int32_t k0, int32_t k1, int32_t i0, int32_t i1, const double* x,
+                                double* y)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!x || !y) FAIL(c, TDBEM_EINVAL, "null vector");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before the matvec");
+    if (k0 < 0 || k1 > c->N || k0 >= k1 || i0 < 0 || i1 > c->N || i0 >= i1)
+        FAIL(c, TDBEM_EINVAL, "bad block range [%d,%d) x [%d,%d)", k0, k1, i0, i1);
+    TRY(set_device(c));
+    TRY(matvec_range(c, k0, k1, i0, i1, x, y));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_matvec(tdbem_ctx* c, const double* x, double* y)
+{
+    if (!c) return TDBEM_EINVAL;
+    return tdbem_matvec_range(c, 0, c->N, 0, c->N, x, y);
+}
+
+// ---------------------------------------------------------------------------------------------
+// FGMRES (Saad 1993) with the recursive block-Hessenberg preconditioner (Section 4.2, Alg. 1)
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct SolveCtx {
+    tdbem_ctx* c;
+    double tol;
+    int restart;
+    int levels;
+    const int32_t* inner;
+};
+
+tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
+                    int* its_out, double* rel_out);
+
+// y ~ M^{-1} v for the time-block range [a, b) at recursion level `level` (1-based): split at
+// h = a + ceil((b - a)/2), y1 ~ M11^{-1} v1, y2 ~ M22^{-1} (v2 - M21 y1) by inner FGMRES.
+tdbem_status apply_precond(SolveCtx& S, int depth, int level, int a, int b, const double* v, double* y)
+{
+    tdbem_ctx* c = S.c;
+    const int64_t M = c->M;
+    const int h = a + (b - a + 1) / 2;
+    const int m_it = S.inner[level - 1];
+    int its;
+    double rel;
+    TRY(fgmres(S, depth, a, h, v, y, m_it, true, &its, &rel));
+    if (b > h) {
+        tdbem_ctx::Level& L = c->levels[depth];
+        double* tmp = L.tmp.as<double>();
+        TRY(matvec_range(c, h, b, a, h, y, tmp));                                    // M21 y1
+        launch_axpby(tmp, v + (int64_t)(h - a) * M, 1.0, -1.0, (int64_t)(b - h) * M, c->stream);   // v2 - M21 y1
+        HIPCHK(c, hipGetLastError());
+        TRY(fgmres(S, depth, h, b, tmp, y + (int64_t)(h - a) * M, m_it, true, &its, &rel));
+    }
+    return TDBEM_OK;
+}
+
+// Solve A[a:b, a:b] x = rhs.  depth indexes the workspace; the preconditioner of a solve at
+// depth d (level d in Algorithm 1 numbering, the outer solve being depth 0) runs its inner
+// solves at depth d + 1.
+tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
+                    int* its_out, double* rel_out)
+{
+    tdbem_ctx* c = S.c;
+    hipStream_t st = c->stream;
+    const int64_t n = (int64_t)(b - a) * c->M;
+    tdbem_ctx::Level& L = c->levels[depth];
+    const bool precond = depth < S.levels && (b - a) > 1;
+    const int m = inner ? max_it : std::min(S.restart, max_it);
+    double* V = L.V.as<double>();
+    double* Z = precond ? L.Z.as<double>() : V;
+    double* dbuf = L.h.as<double>();          // [0, m+1): h1, [m+1, 2m+2): h2, [2m+2]: |w|^2
+    double* part = L.partial.as<double>();
+    *its_out = 0;
+    // ||rhs||
+    launch_dots(rhs, 1, n, n, rhs, part, dbuf + 2 * (m + 1), st);
+    double bn2;
+    HIPCHK(c, hipMemcpyAsync(&bn2, dbuf + 2 * (m + 1), sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(bn2);
+    launch_fill(x, 0.0, n, st);
+    if (bnorm == 0.0) {
+        *rel_out = 0.0;
+        return TDBEM_OK;
+    }
+    double beta = bnorm;
+    const double* r = rhs;   // residual of x = 0
+    double* wres = L.w.as<double>();
+    int its = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), hbuf(2 * (m + 1) + 1);
+    while (true) {
+        const int mm = inner ? max_it - its : std::min(m, max_it - its);
+        if (mm <= 0 || beta <= S.tol * bnorm) break;
+        launch_scale_copy(V, r, 1.0 / beta, n, st);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jdone = 0;
+        bool done = false;
+        for (int j = 0; j < mm; ++j) {
+            double* vj = V + (int64_t)j * n;
+            double* zj = Z + (int64_t)j * n;
+            if (precond) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
+            double* w = V + (int64_t)(j + 1) * n;
+            TRY(matvec_range(c, a, b, a, b, zj, w));
+            // classical Gram-Schmidt, twice
+            launch_dots(V, j + 1, n, n, w, part, dbuf, st);
+            launch_sub_combination(w, V, j + 1, n, n, dbuf, -1.0, st);
+            launch_dots(V, j + 1, n, n, w, part, dbuf + (m + 1), st);
+            launch_sub_combination(w, V, j + 1, n, n, dbuf + (m + 1), -1.0, st);
+            launch_dots(w, 1, n, n, w, part, dbuf + 2 * (m + 1), st);
+            launch_scale_inv_sqrt(w, w, dbuf + 2 * (m + 1), n, st);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipMemcpyAsync(hbuf.data(), dbuf, sizeof(double) * (2 * (m + 1) + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (int q = 0; q <= j; ++q) H[(size_t)q * m + j] = hbuf[q] + hbuf[m + 1 + q];
+            const double hn = std::sqrt(std::max(hbuf[2 * (m + 1)], 0.0));
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int q = 0; q < j; ++q) {
+                const double t1 = cs[q] * H[(size_t)q * m + j] + sn[q] * H[(size_t)(q + 1) * m + j];
+                H[(size_t)(q + 1) * m + j] = -sn[q] * H[(size_t)q * m + j] + cs[q] * H[(size_t)(q + 1) * m + j];
+                H[(size_t)q * m + j] = t1;
+            }
+            const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+            cs[j] = den != 0.0 ? H[(size_t)j * m + j] / den : 1.0;
+            sn[j] = den != 0.0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
+            H[(size_t)j * m + j] = cs[j] * H[(size_t)j * m + j] + sn[j] * H[(size_t)(j + 1) * m + j];
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            ++its;
+            jdone = j + 1;
+            if (std::fabs(gv[j + 1]) <= S.tol * bnorm || hn == 0.0) { done = true; break; }
+        }
+        // y = H^{-1} g (upper triangular), x += Z y
+        std::vector<double> y(jdone);
+        for (int q = jdone - 1; q >= 0; --q) {
+            double s = gv[q];
+            for (int u = q + 1; u < jdone; ++u) s -= H[(size_t)q * m + u] * y[u];
+            y[q] = s / H[(size_t)q * m + q];
+        }
+        HIPCHK(c, hipMemcpyAsync(dbuf, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
+        launch_sub_combination(x, Z, jdone, n, n, dbuf, 1.0, st);
+        HIPCHK(c, hipGetLastError());
+        if (inner) {
+            HIPCHK(c, hipStreamSynchronize(st));
+            break;
+        }
+        // true residual
+        TRY(matvec_range(c, a, b, a, b, x, wres));
+        launch_axpby(wres, rhs, 1.0, -1.0, n, st);        // rhs - A x
+        launch_dots(wres, 1, n, n, wres, part, dbuf + 2 * (m + 1), st);
+        double r2;
+        HIPCHK(c, hipMemcpyAsync(&r2, dbuf + 2 * (m + 1), sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        beta = std::sqrt(r2);
+        r = wres;
+        (void)done;
+        if (beta <= S.tol * bnorm || its >= max_it) break;
+    }
+    *its_out = its;
+    *rel_out = beta / bnorm;
+    return TDBEM_OK;
+}
+
+}  // namespace
+
+tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdbem_solve_opts* o,
+                         tdbem_solve_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!g || !alpha || !o) FAIL(c, TDBEM_EINVAL, "null argument");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before solving");
+    if (o->restart < 1 || o->restart > 1000 || !(o->tol > 0.0) || o->max_it < 1 || o->precond_levels < 0 ||
+        o->precond_levels > 8)
+        FAIL(c, TDBEM_EINVAL, "bad solver options");
+    for (int s = 0; s < o->precond_levels; ++s)
+        if (o->precond_inner[s] < 1 || o->precond_inner[s] > 1000) FAIL(c, TDBEM_EINVAL, "bad inner iteration count");
+    TRY(set_device(c));
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t M = c->M;
+    // workspaces: depth 0 is the outer solve; depth d >= 1 holds ranges of <= ceil(N / 2^(d-1)) blocks
+    const int depths = o->precond_levels + 1;
+    if ((int)c->levels.size() < depths) c->levels.resize(depths);
+    int blocks = c->N;
+    for (int d = 0; d < depths; ++d) {
+        const int m = d == 0 ? o->restart : o->precond_inner[d - 1];
+        const int64_t n = (int64_t)blocks * M;
+        tdbem_ctx::Level& L = c->levels[d];
+        if (L.m < m || L.n < n) {
+            ALLOC(c, L.V, sizeof(double) * (size_t)(m + 1) * n);
+            ALLOC(c, L.Z, sizeof(double) * (size_t)m * n);
+            ALLOC(c, L.w, sizeof(double) * n);
+            ALLOC(c, L.tmp, sizeof(double) * n);
+            ALLOC(c, L.partial, sizeof(double) * (size_t)(m + 2) * dots_partial_blocks(n));
+            ALLOC(c, L.h, sizeof(double) * (2 * (m + 1) + 2));
+            L.m = m;
+            L.n = n;
+        }
+        blocks = (blocks + 1) / 2;
+    }
+    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner};
+    c->matvecs = 0;
+    int its = 0;
+    double rel = 0.0;
+    TRY(fgmres(S, 0, 0, c->N, g, alpha, o->max_it, false, &its, &rel));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (rep) {
+        rep->iterations = its;
+        rep->matvecs = c->matvecs;
+        rep->rel_residual = rel;
+        rep->ms = ms;
+    }
+    if (!(rel <= o->tol)) {
+        char b[160];
+        std::snprintf(b, sizeof(b), "not converged: relative residual %.3e after %d iterations", rel, its);
+        c->err = b;
+        return TDBEM_NOT_CONVERGED;
+    }
+    return TDBEM_OK;
+}
+
+}  // extern "C"

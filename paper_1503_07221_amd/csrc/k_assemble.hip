@@ -1,0 +1,480 @@
+// Assembly of the blocks A_{k,i} (eq. (MatrixEntries)) on gfx950.
+//
+//   k_geometry   per-triangle structure of arrays (normal, area, surface curls, 7 points)
+//   k_layout     band layout: per (k, l, j) the first trial index i whose kernel support meets
+//                the conservative distance range of the two hats (eq. (SparsitySmallBlock))
+//   k_regular    pairs without a common vertex: 7 x 7 point pairs, all (k, i) with r in supp
+//   k_singular   coincident / common-edge / common-vertex pairs: Sauter-Schwab rules
+// Every unordered pair {tau < sigma} is integrated once with tau as the x-triangle and its local
+// 3 x 3 block is added to A(v_b(sigma), v_a(tau)) and, by the symmetry of the kernel in
+// x <-> y, to A(v_a(tau), v_b(sigma)); a coincident pair adds its symmetrised block once.
+#include "tdbem_internal.hpp"
+
+namespace tdbem {
+
+// 7-point degree-5 rule (Radon; Stroud T2:5-1): centroid weight 9/40, orbits (a,a,1-2a) with
+// a = (6 -/+ sqrt 15)/21 and weights (155 -/+ sqrt 15)/1200 (weights sum to 1).
+__host__ __device__ inline void rule7_point(int q, double& l0, double& l1, double& l2, double& w)
+{
+    const double s15 = 3.872983346207416885;
+    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    const double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+    switch (q) {
+    case 0: l0 = 1.0 / 3.0; l1 = 1.0 / 3.0; l2 = 1.0 / 3.0; w = 9.0 / 40.0; break;
+    case 1: l0 = a1; l1 = a1; l2 = 1.0 - 2.0 * a1; w = w1; break;
+    case 2: l0 = a1; l1 = 1.0 - 2.0 * a1; l2 = a1; w = w1; break;
+    case 3: l0 = 1.0 - 2.0 * a1; l1 = a1; l2 = a1; w = w1; break;
+    case 4: l0 = a2; l1 = a2; l2 = 1.0 - 2.0 * a2; w = w2; break;
+    case 5: l0 = a2; l1 = 1.0 - 2.0 * a2; l2 = a2; w = w2; break;
+    default: l0 = 1.0 - 2.0 * a2; l1 = a2; l2 = a2; w = w2; break;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_geometry(const double* __restrict__ xyz, const int32_t* __restrict__ tri, int E, double* __restrict__ P,
+           double* __restrict__ nrm, double* __restrict__ area, double* __restrict__ curl,
+           double* __restrict__ qp, int32_t* __restrict__ vid)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double X[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const int v = tri[3 * e + a];
+        vid[a * E + e] = v;
+        for (int c = 0; c < 3; ++c) {
+            X[a][c] = xyz[3 * v + c];
+            P[(3 * a + c) * E + e] = X[a][c];
+        }
+    }
+    const double u0 = X[1][0] - X[0][0], u1 = X[1][1] - X[0][1], u2 = X[1][2] - X[0][2];
+    const double w0 = X[2][0] - X[0][0], w1 = X[2][1] - X[0][1], w2 = X[2][2] - X[0][2];
+    const double c0 = u1 * w2 - u2 * w1, c1 = u2 * w0 - u0 * w2, c2 = u0 * w1 - u1 * w0;
+    const double len = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    nrm[e] = c0 / len;
+    nrm[E + e] = c1 / len;
+    nrm[2 * E + e] = c2 / len;
+    const double ar = 0.5 * len;
+    area[e] = ar;
+    for (int a = 0; a < 3; ++a) {
+        const int p = (a + 1) % 3, q = (a + 2) % 3;
+        for (int c = 0; c < 3; ++c) curl[(3 * a + c) * E + e] = -(X[q][c] - X[p][c]) / (2.0 * ar);
+    }
+    for (int q = 0; q < 7; ++q) {
+        double l0, l1, l2, w;
+        rule7_point(q, l0, l1, l2, w);
+        for (int c = 0; c < 3; ++c) qp[(3 * q + c) * E + e] = l0 * X[0][c] + l1 * X[1][c] + l2 * X[2][c];
+    }
+}
+
+// Band of trial indices i for the time row k and a distance range (dmin, dmax): those with
+// lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).
+__global__ void __launch_bounds__(256)
+k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, const double* __restrict__ t,
+         int N, int16_t* __restrict__ ilo, int32_t* __restrict__ Bk)
+{
+    extern __shared__ int32_t sB[];
+    for (int k = threadIdx.x; k < N; k += blockDim.x) sB[k] = 0;
+    __syncthreads();
+    const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pid < (int64_t)M * M) {
+        const int l = (int)(pid / M), j = (int)(pid - (int64_t)l * M);
+        const double dx = xyz[3 * l] - xyz[3 * j], dy = xyz[3 * l + 1] - xyz[3 * j + 1], dz = xyz[3 * l + 2] - xyz[3 * j + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double slack = 1e-12 * (1.0 + t[N - 1]);
+        const double dmax = d + rho[l] + rho[j] + slack;
+        double dmin = d - rho[l] - rho[j] - slack;
+        dmin = dmin > 0.0 ? dmin : 0.0;
+        int ia = 0, ib = -1;
+        for (int k = 0; k < N; ++k) {
+            // first i with lo_{k,i} < dmax
+            while (ia < N) {
+                double lo, hi;
+                kernel_support(t, N, k, ia, lo, hi);
+                if (lo < dmax) break;
+                ++ia;
+            }
+            // last i with hi_{k,i} > dmin
+            while (ib + 1 < N) {
+                double lo, hi;
+                kernel_support(t, N, k, ib + 1, lo, hi);
+                if (!(hi > dmin)) break;
+                ++ib;
+            }
+            const int first = ia < N ? ia : N - 1;
+            ilo[((int64_t)k * M + l) * M + j] = (int16_t)first;
+            const int cnt = ib - ia + 1;
+            if (cnt > 0) atomicMax(&sB[k], cnt);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < N; k += blockDim.x)
+        if (sB[k] > 0) atomicMax(&Bk[k], sB[k]);
+}
+
+// Add one local 3 x 3 block of the time pair (k, i) to the band storage.
+__device__ inline void scatter_add(const BandView& band, double* val, float* valf, int k, int i, int l, int j,
+                                   double v)
+{
+    const int64_t M = band.M;
+    const int s = i - (int)band.ilo[((int64_t)k * M + l) * M + j];
+    const int B = band.B[k];
+    if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
+    const int64_t idx = band.voff[k] + ((int64_t)l * B + s) * M + j;
+    if (valf) atomicAdd(valf + idx, (float)v);
+    else atomicAdd(val + idx, v);
+}
+
+__device__ inline double wave_min(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Regular pairs.  Block (tau, 256 consecutive sigma); one lane per unordered pair tau < sigma
+// without a common vertex.  The 49 distances are computed once; the (k, i) loop runs over the
+// union of the lanes' bands (wave-uniform, so kernel descriptors are scalar loads) and each lane
+// evaluates only the point pairs inside the open support.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_regular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
+          unsigned long long* counter)
+{
+    const int E = g.E;
+    const int tau = blockIdx.y;
+    if ((int)(blockIdx.x * 256 + 255) <= tau) return;
+    const int sig = blockIdx.x * 256 + threadIdx.x;
+    const int N = tv.N;
+    const int tv0 = g.v[tau], tv1 = g.v[E + tau], tv2 = g.v[2 * E + tau];
+    bool active = sig > tau && sig < E;
+    int sv0 = 0, sv1 = 0, sv2 = 0;
+    if (active) {
+        sv0 = g.v[sig]; sv1 = g.v[E + sig]; sv2 = g.v[2 * E + sig];
+        if (sv0 == tv0 || sv0 == tv1 || sv0 == tv2 || sv1 == tv0 || sv1 == tv1 || sv1 == tv2 ||
+            sv2 == tv0 || sv2 == tv1 || sv2 == tv2)
+            active = false;
+    }
+    const int sg = active ? sig : tau;   // inactive lanes read valid memory and do no work
+    double r[49], ir[49];
+    double rmin = 1e300, rmax = -1e300;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const double x0 = g.qp[(3 * q) * E + tau], x1 = g.qp[(3 * q + 1) * E + tau], x2 = g.qp[(3 * q + 2) * E + tau];
+#pragma unroll
+        for (int p = 0; p < 7; ++p) {
+            const double d0 = x0 - g.qp[(3 * p) * E + sg], d1 = x1 - g.qp[(3 * p + 1) * E + sg],
+                         d2 = x2 - g.qp[(3 * p + 2) * E + sg];
+            const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            r[7 * q + p] = rr;
+            ir[7 * q + p] = 1.0 / rr;
+            rmin = fmin(rmin, rr);
+            rmax = fmax(rmax, rr);
+        }
+    }
+    if (!active) { rmin = 1e300; rmax = -1e300; }
+    const double wmin = wave_min(rmin), wmax = wave_max(rmax);
+    if (wmax < wmin) return;   // no active lane in this wave
+
+    // pair constants: n_tau . n_sigma, curl products, |tau||sigma|/(4 pi)
+    const double nn = g.n[tau] * g.n[sg] + g.n[E + tau] * g.n[E + sg] + g.n[2 * E + tau] * g.n[2 * E + sg];
+    double C[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            C[a][b] = g.curl[(3 * a) * E + tau] * g.curl[(3 * b) * E + sg] +
+                      g.curl[(3 * a + 1) * E + tau] * g.curl[(3 * b + 1) * E + sg] +
+                      g.curl[(3 * a + 2) * E + tau] * g.curl[(3 * b + 2) * E + sg];
+    const double scale = g.area[tau] * g.area[sg] * 0.07957747154594767;   // 1/(4 pi)
+    const int vt[3] = {tv0, tv1, tv2};
+    const int vs[3] = {sv0, sv1, sv2};
+    unsigned long long nq = 0;
+
+    int ia = 0, ib = -1;
+    for (int k = 0; k < N; ++k) {
+        while (ia < N) {
+            double lo, hi;
+            kernel_support(t, N, k, ia, lo, hi);
+            if (lo < wmax) break;
+            ++ia;
+        }
+        while (ib + 1 < N) {
+            double lo, hi;
+            kernel_support(t, N, k, ib + 1, lo, hi);
+            if (!(hi > wmin)) break;
+            ++ib;
+        }
+        for (int i = ia; i <= ib; ++i) {
+            const int f = tv.fid[k * N + i];
+            if (f < 0) continue;
+            const KernelDesc kd = tv.desc[f];
+            if (!active || !(rmax > kd.lo && rmin < kd.hi)) continue;
+            double S1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            double S2 = 0.0;
+            int hits = 0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                double la0, la1, la2, wq;
+                rule7_point(q, la0, la1, la2, wq);
+                double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+#pragma unroll
+                for (int p = 0; p < 7; ++p) {
+                    double lb0, lb1, lb2, wp;
+                    rule7_point(p, lb0, lb1, lb2, wp);
+                    double ps, pt;
+                    if (table_eval(kd, tv.ivl, tv.coef, tv.pt, r[7 * q + p], ps, pt)) {
+                        ++hits;
+                        const double c = wp * ir[7 * q + p];
+                        const double f1 = ps * c;
+                        R0 = fma(f1, lb0, R0);
+                        R1 = fma(f1, lb1, R1);
+                        R2 = fma(f1, lb2, R2);
+                        S2 = fma(wq * c, pt, S2);
+                    }
+                }
+                S1[0][0] = fma(wq * la0, R0, S1[0][0]); S1[0][1] = fma(wq * la0, R1, S1[0][1]); S1[0][2] = fma(wq * la0, R2, S1[0][2]);
+                S1[1][0] = fma(wq * la1, R0, S1[1][0]); S1[1][1] = fma(wq * la1, R1, S1[1][1]); S1[1][2] = fma(wq * la1, R2, S1[1][2]);
+                S1[2][0] = fma(wq * la2, R0, S1[2][0]); S1[2][1] = fma(wq * la2, R1, S1[2][1]); S1[2][2] = fma(wq * la2, R2, S1[2][2]);
+            }
+            if (hits == 0) continue;
+            nq += hits;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const double v = (nn * S1[a][b] + C[a][b] * S2) * scale;
+                    scatter_add(band, val, valf, k, i, vt[a], vs[b], v);   // A(v_b(sigma), v_a(tau)) at row l = v_a(tau)
+                    scatter_add(band, val, valf, k, i, vs[b], vt[a], v);   // mirror: row l = v_b(sigma)
+                }
+        }
+    }
+    const unsigned long long tot = wave_sum_u64(nq);
+    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(counter, tot);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Singular pairs.  One lane per (pair, k).  pairs[9*s..]: tau, sigma, kind (0 coincident,
+// 1 edge, 2 vertex), the local indices of the reference vertices (A, B, C) in tau and in sigma.
+// The rule rows are (x1, x2, y1, y2, w) on the reference triangle {0 <= x2 <= x1 <= 1}, the
+// physical point A + x1 (B - A) + x2 (C - B) with barycentrics (1 - x1, x1 - x2, x2).
+// ---------------------------------------------------------------------------------------------
+constexpr int kSingBand = 6;
+
+__global__ void __launch_bounds__(128)
+k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, const int32_t* __restrict__ pairs,
+           int64_t npairs, const double* __restrict__ rules, const int32_t* __restrict__ roff,
+           const int32_t* __restrict__ rcnt, double* val, float* valf, unsigned long long* counter)
+{
+    const int N = tv.N;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long nq = 0;
+    if (gid < npairs * N) {
+        const int64_t s = gid / N;
+        const int k = (int)(gid - s * N);
+        const int E = g.E;
+        const int32_t* pr = pairs + 9 * s;
+        const int tau = pr[0], sig = pr[1], kind = pr[2];
+        int px[3] = {pr[3], pr[4], pr[5]}, py[3] = {pr[6], pr[7], pr[8]};
+        double X[3][3], Y[3][3];   // reference vertices A, B, C
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) {
+                X[a][c] = g.P[(3 * px[a] + c) * E + tau];
+                Y[a][c] = g.P[(3 * py[a] + c) * E + sig];
+            }
+        double rmax = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double d0 = X[a][0] - Y[b][0], d1 = X[a][1] - Y[b][1], d2 = X[a][2] - Y[b][2];
+                rmax = fmax(rmax, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+            }
+        rmax *= 1.0 + 1e-12;
+        int ia = 0;
+        while (ia < N) {
+            double lo, hi;
+            kernel_support(t, N, k, ia, lo, hi);
+            if (lo < rmax) break;
+            ++ia;
+        }
+        int ib = ia - 1;
+        while (ib + 1 < N) {
+            double lo, hi;
+            kernel_support(t, N, k, ib + 1, lo, hi);
+            if (!(hi > 0.0)) break;
+            ++ib;
+        }
+        const double nn = g.n[tau] * g.n[sig] + g.n[E + tau] * g.n[E + sig] + g.n[2 * E + tau] * g.n[2 * E + sig];
+        const double jac = 4.0 * g.area[tau] * g.area[sig];
+        const double scale = 0.07957747154594767;   // 1/(4 pi)
+        // reference-order vertex ids and curl products (static register indices below)
+        int vtr[3], vsr[3];
+        double Cr[3][3];
+        for (int al = 0; al < 3; ++al) {
+            vtr[al] = g.v[px[al] * E + tau];
+            vsr[al] = g.v[py[al] * E + sig];
+        }
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be)
+                Cr[al][be] = g.curl[(3 * px[al]) * E + tau] * g.curl[(3 * py[be]) * E + sig] +
+                             g.curl[(3 * px[al] + 1) * E + tau] * g.curl[(3 * py[be] + 1) * E + sig] +
+                             g.curl[(3 * px[al] + 2) * E + tau] * g.curl[(3 * py[be] + 2) * E + sig];
+        const int npts = rcnt[kind];
+        const double* rule = rules + 5 * (int64_t)roff[kind];
+        for (int i0 = ia; i0 <= ib; i0 += kSingBand) {
+            const int nb = (ib - i0 + 1) < kSingBand ? (ib - i0 + 1) : kSingBand;
+            KernelDesc kd[kSingBand];
+            bool have[kSingBand];
+#pragma unroll
+            for (int u = 0; u < kSingBand; ++u) {
+                const int f = u < nb ? tv.fid[k * N + i0 + u] : -1;
+                have[u] = f >= 0;
+                if (have[u]) kd[u] = tv.desc[f];
+                else { kd[u].lo = 1.0; kd[u].hi = 0.0; kd[u].nint = 0; kd[u].bp_off = 0; kd[u].coef_off = 0; }
+            }
+            double S1[kSingBand][9], S2[kSingBand];
+#pragma unroll
+            for (int u = 0; u < kSingBand; ++u) {
+                S2[u] = 0.0;
+#pragma unroll
+                for (int m = 0; m < 9; ++m) S1[u][m] = 0.0;
+            }
+            for (int q = 0; q < npts; ++q) {
+                const double* R = rule + 5 * q;
+                const double x1 = R[0], x2 = R[1], y1 = R[2], y2 = R[3];
+                const double w = R[4] * jac;
+                const double lx0 = 1.0 - x1, lx1 = x1 - x2, lx2 = x2;
+                const double ly0 = 1.0 - y1, ly1 = y1 - y2, ly2 = y2;
+                double d2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double xc = lx0 * X[0][c] + lx1 * X[1][c] + lx2 * X[2][c];
+                    const double yc = ly0 * Y[0][c] + ly1 * Y[1][c] + ly2 * Y[2][c];
+                    d2 += (xc - yc) * (xc - yc);
+                }
+                const double rr = sqrt(d2);
+                const double wr = w / rr;
+#pragma unroll
+                for (int u = 0; u < kSingBand; ++u) {
+                    double ps, pt;
+                    if (have[u] && table_eval(kd[u], tv.ivl, tv.coef, tv.pt, rr, ps, pt)) {
+                        ++nq;
+                        const double f1 = ps * wr;
+                        const double R0 = f1 * ly0, R1 = f1 * ly1, R2 = f1 * ly2;
+                        S1[u][0] = fma(lx0, R0, S1[u][0]); S1[u][1] = fma(lx0, R1, S1[u][1]); S1[u][2] = fma(lx0, R2, S1[u][2]);
+                        S1[u][3] = fma(lx1, R0, S1[u][3]); S1[u][4] = fma(lx1, R1, S1[u][4]); S1[u][5] = fma(lx1, R2, S1[u][5]);
+                        S1[u][6] = fma(lx2, R0, S1[u][6]); S1[u][7] = fma(lx2, R1, S1[u][7]); S1[u][8] = fma(lx2, R2, S1[u][8]);
+                        S2[u] = fma(pt, wr, S2[u]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kSingBand; ++u) {
+                if (u >= nb || !have[u]) continue;
+                const int i = i0 + u;
+                double loc[3][3];
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) loc[al][be] = (nn * S1[u][3 * al + be] + Cr[al][be] * S2[u]) * scale;
+                if (kind == 0) {
+                    // identical triangles: reference order = local order; symmetrise in (a, b)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = a + 1; b < 3; ++b) {
+                            const double m = 0.5 * (loc[a][b] + loc[b][a]);
+                            loc[a][b] = m;
+                            loc[b][a] = m;
+                        }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) scatter_add(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            scatter_add(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
+                            scatter_add(band, val, valf, k, i, vsr[b], vtr[a], loc[a][b]);
+                        }
+                }
+            }
+        }
+    }
+    const unsigned long long tot = wave_sum_u64(nq);
+    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(counter, tot);
+}
+
+__global__ void __launch_bounds__(256)
+k_get_entries(BandView band, const double* __restrict__ val, const float* __restrict__ valf, int64_t n,
+              const int32_t* __restrict__ k, const int32_t* __restrict__ i, const int32_t* __restrict__ j,
+              const int32_t* __restrict__ l, double* __restrict__ out)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int kk = k[s], ii = i[s], jj = j[s], ll = l[s];
+    double v = 0.0;
+    if (kk >= 0 && kk < band.N && ii >= 0 && ii < band.N && jj >= 0 && jj < band.M && ll >= 0 && ll < band.M) {
+        const int64_t M = band.M;
+        const int B = band.B[kk];
+        const int sl = ii - (int)band.ilo[((int64_t)kk * M + ll) * M + jj];
+        if (sl >= 0 && sl < B) {
+            const int64_t idx = band.voff[kk] + ((int64_t)ll * B + sl) * M + jj;
+            v = valf ? (double)valf[idx] : val[idx];
+        }
+    }
+    out[s] = v;
+}
+
+static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P, double* geo_n, double* geo_area,
+                     double* geo_curl, double* geo_qp, int32_t* geo_v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_geometry, dim3(grid_for(E, 256)), dim3(256), 0, s, xyz, tri, E, geo_P, geo_n, geo_area,
+                       geo_curl, geo_qp, geo_v);
+}
+
+void launch_layout(const double* xyz, const double* rho, int M, const double* t, int N, int16_t* ilo, int32_t* Bk,
+                   hipStream_t s)
+{
+    const int64_t n = (int64_t)M * M;
+    hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 256)), dim3(256), sizeof(int32_t) * N, s, xyz, rho, M, t, N, ilo,
+                       Bk);
+}
+
+void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
+                    unsigned long long* counter, hipStream_t s)
+{
+    dim3 grid(grid_for(g.E, 256), g.E);
+    hipLaunchKernelGGL(k_regular, grid, dim3(256), 0, s, g, tv, t, band, val, valf, counter);
+}
+
+void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,
+                     const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt, double* val, float* valf,
+                     unsigned long long* counter, hipStream_t s)
+{
+    const int64_t n = npairs * tv.N;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_singular, dim3(grid_for(n, 128)), dim3(128), 0, s, g, tv, t, band, pairs, npairs, ss_rules,
+                       ss_off, ss_cnt, val, valf, counter);
+}
+
+void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,
+                        const int32_t* i, const int32_t* j, const int32_t* l, double* out, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_get_entries, dim3(grid_for(n, 256)), dim3(256), 0, s, band, val, valf, n, k, i, j, l, out);
+}
+
+}  // namespace tdbem

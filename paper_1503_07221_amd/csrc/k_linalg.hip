@@ -1,0 +1,233 @@
+// Right-hand side, block matvec and the vector kernels of the FGMRES solver.
+#include "tdbem_internal.hpp"
+
+namespace tdbem {
+
+// 7-point rule (identical definition to the assembly's; kept local to this translation unit).
+__device__ inline void rhs_rule7(int q, double& l0, double& l1, double& l2, double& w)
+{
+    const double s15 = 3.872983346207416885;
+    const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+    const double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+    switch (q) {
+    case 0: l0 = 1.0 / 3.0; l1 = 1.0 / 3.0; l2 = 1.0 / 3.0; w = 9.0 / 40.0; break;
+    case 1: l0 = a1; l1 = a1; l2 = 1.0 - 2.0 * a1; w = w1; break;
+    case 2: l0 = a1; l1 = 1.0 - 2.0 * a1; l2 = a1; w = w1; break;
+    case 3: l0 = 1.0 - 2.0 * a1; l1 = a1; l2 = a1; w = w1; break;
+    case 4: l0 = a2; l1 = a2; l2 = 1.0 - 2.0 * a2; w = w2; break;
+    case 5: l0 = a2; l1 = 1.0 - 2.0 * a2; l2 = a2; w = w2; break;
+    default: l0 = 1.0 - 2.0 * a2; l1 = a2; l2 = a2; w = w2; break;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill(double* __restrict__ x, double v, int64_t n)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) x[s] = v;
+}
+
+// g_k(l) = sum_tau |tau| sum_q w_q lam_a(q) (d.n_tau) int b_k'(t) G'(t - t0 - d.x_q) dt with
+// G(s) = exp(-(s/w)^2): one lane per (k, tau); the time integral over supp b_k' is split at t_k
+// and graded dyadically towards the split points like the kernel quadrature.
+__global__ void __launch_bounds__(256)
+k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
+      double t0, double width, int M, double* __restrict__ gvec)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int E = g.E;
+    if (gid >= (int64_t)N * E) return;
+    const int k = (int)(gid / E), e = (int)(gid - (int64_t)k * E);
+    double pts[3];
+    int np = 0;
+    pts[np++] = t[k > 0 ? k - 1 : 0];
+    if (k > 0 && k < N - 1) pts[np++] = t[k];
+    pts[np++] = t[k < N - 1 ? k + 1 : N - 1];
+    const double dn = d0 * g.n[e] + d1 * g.n[E + e] + d2 * g.n[2 * E + e];
+    const double iw2 = 1.0 / (width * width);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    for (int q = 0; q < 7; ++q) {
+        double l0, l1, l2, wq;
+        rhs_rule7(q, l0, l1, l2, wq);
+        const double dx = d0 * g.qp[(3 * q) * E + e] + d1 * g.qp[(3 * q + 1) * E + e] + d2 * g.qp[(3 * q + 2) * E + e];
+        double ti = 0.0;
+        for (int s = 0; s + 1 < np; ++s) {
+            const double a = pts[s], len = pts[s + 1] - a;
+            for (int gp = 0; gp < kTimePieces; ++gp) {
+                const double pa = a + len * time_grading_edge(gp), pb = a + len * time_grading_edge(gp + 1);
+                const double half = 0.5 * (pb - pa), mid = 0.5 * (pa + pb);
+                for (int m = 0; m < kTimeGauss; ++m) {
+                    const double tt = fma(half, rule.x[m], mid);
+                    const double sa = tt - t0 - dx;
+                    const double Gp = -2.0 * sa * iw2 * exp(-sa * sa * iw2);
+                    double bv, b1, b2;
+                    basis_eval(t, N, cut, k, tt, bv, b1, b2);
+                    ti = fma(half * rule.w[m] * Gp, b1, ti);
+                }
+            }
+        }
+        const double f = g.area[e] * wq * dn * ti;
+        acc0 = fma(f, l0, acc0);
+        acc1 = fma(f, l1, acc1);
+        acc2 = fma(f, l2, acc2);
+    }
+    atomicAdd(gvec + (int64_t)k * M + g.v[e], acc0);
+    atomicAdd(gvec + (int64_t)k * M + g.v[E + e], acc1);
+    atomicAdd(gvec + (int64_t)k * M + g.v[2 * E + e], acc2);
+}
+
+// y[(k-k0)*M + l] = sum_j sum_s A_{k, ilo+s}(j, l) x[(ilo+s-i0)*M + j] over i0 <= ilo+s < i1:
+// one wave per row (k, l), lanes stride over j (coalesced values and band starts).
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_matvec(BandView band, const VT* __restrict__ val, int k0, int k1, int i0, int i1, const double* __restrict__ x,
+         double* __restrict__ y)
+{
+    const int M = band.M;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= (int64_t)(k1 - k0) * M) return;
+    const int k = k0 + (int)(row / M);
+    const int l = (int)(row - (int64_t)(k - k0) * M);
+    const int B = band.B[k];
+    const VT* __restrict__ v = val + band.voff[k] + (int64_t)l * B * M;
+    const int16_t* __restrict__ il = band.ilo + ((int64_t)k * M + l) * M;
+    double acc = 0.0;
+    for (int j = lane; j < M; j += 64) {
+        const int ib = il[j];
+        for (int s = 0; s < B; ++s) {
+            const int i = ib + s;
+            if (i >= i0 && i < i1) acc = fma((double)v[(int64_t)s * M + j], x[(int64_t)(i - i0) * M + j], acc);
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) y[row] = acc;
+}
+
+// Partial dot products of w with nvec vectors V[q*ld + .]: block (b, q) sums its chunk.
+constexpr int kDotBlock = 256;
+constexpr int kDotChunk = 8192;
+
+__global__ void __launch_bounds__(kDotBlock)
+k_dots_partial(const double* __restrict__ V, int64_t n, int64_t ld, const double* __restrict__ w,
+               double* __restrict__ partial, int nb)
+{
+    const int q = blockIdx.y;
+    const int64_t begin = (int64_t)blockIdx.x * kDotChunk;
+    const int64_t end = begin + kDotChunk < n ? begin + kDotChunk : n;
+    const double* vq = V + (int64_t)q * ld;
+    double acc = 0.0;
+    for (int64_t s = begin + threadIdx.x; s < end; s += kDotBlock) acc = fma(vq[s], w[s], acc);
+    __shared__ double red[kDotBlock / 64];
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int u = 0; u < kDotBlock / 64; ++u) t += red[u];
+        partial[(int64_t)q * nb + blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(64)
+k_dots_final(const double* __restrict__ partial, int nb, double* __restrict__ out)
+{
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < nb; s += 64) acc += partial[(int64_t)q * nb + s];
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (threadIdx.x == 0) out[q] = acc;
+}
+
+// w += sign * sum_q h[q] V[q*ld + .]
+__global__ void __launch_bounds__(256)
+k_sub_combination(double* __restrict__ w, const double* __restrict__ V, int nvec, int64_t n, int64_t ld,
+                  const double* __restrict__ h, double sign)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double acc = 0.0;
+    for (int q = 0; q < nvec; ++q) acc = fma(h[q], V[(int64_t)q * ld + s], acc);
+    w[s] = fma(sign, acc, w[s]);
+}
+
+__global__ void __launch_bounds__(256)
+k_scale_copy(double* __restrict__ dst, const double* __restrict__ src, double a, int64_t n)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = a * src[s];
+}
+
+__global__ void __launch_bounds__(256)
+k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b, int64_t n)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) y[s] = b == 0.0 ? a * x[s] : fma(a, x[s], b * y[s]);
+}
+
+// dst = src / sqrt(*nrm2) (the normalisation of a new Krylov vector without a host round trip)
+__global__ void __launch_bounds__(256)
+k_scale_inv_sqrt(double* __restrict__ dst, const double* __restrict__ src, const double* __restrict__ nrm2, int64_t n)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double v = *nrm2;
+    if (s < n) dst[s] = v > 0.0 ? src[s] / sqrt(v) : 0.0;
+}
+
+static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_scale_inv_sqrt(double* dst, const double* src, const double* nrm2, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_inv_sqrt, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, nrm2, n);
+}
+
+void launch_fill(double* x, double v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, x, v, n);
+}
+
+void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2, double t0,
+                double width, int M, double* gvec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)N * M, 256)), dim3(256), 0, s, gvec, 0.0, (int64_t)N * M);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for((int64_t)N * g.E, 256)), dim3(256), 0, s, g, t, N, cut, rule, d0, d1, d2,
+                       t0, width, M, gvec);
+}
+
+void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
+                   const double* x, double* y, hipStream_t s)
+{
+    const int64_t rows = (int64_t)(k1 - k0) * band.M;
+    if (rows <= 0) return;
+    if (valf)
+        hipLaunchKernelGGL(k_matvec<float>, dim3(grid_for(rows, 4)), dim3(256), 0, s, band, valf, k0, k1, i0, i1, x, y);
+    else
+        hipLaunchKernelGGL(k_matvec<double>, dim3(grid_for(rows, 4)), dim3(256), 0, s, band, val, k0, k1, i0, i1, x, y);
+}
+
+int dots_partial_blocks(int64_t n) { return (int)((n + kDotChunk - 1) / kDotChunk); }
+
+void launch_dots(const double* V, int nvec, int64_t n, int64_t ld, const double* w, double* partial, double* out,
+                 hipStream_t s)
+{
+    const int nb = dots_partial_blocks(n);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, nvec), dim3(kDotBlock), 0, s, V, n, ld, w, partial, nb);
+    hipLaunchKernelGGL(k_dots_final, dim3(nvec), dim3(64), 0, s, partial, nb, out);
+}
+
+void launch_sub_combination(double* w, const double* V, int nvec, int64_t n, int64_t ld, const double* h, double sign,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n, 256)), dim3(256), 0, s, w, V, nvec, n, ld, h, sign);
+}
+
+void launch_scale_copy(double* dst, const double* src, double a, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, a, n);
+}
+
+void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n, 256)), dim3(256), 0, s, y, x, a, b, n);
+}
+
+}  // namespace tdbem

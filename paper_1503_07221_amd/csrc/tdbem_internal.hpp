@@ -1,0 +1,246 @@
+// Internal definitions shared by the HIP kernels and the host runtime of libtdbem.
+//
+// Notation (0-based): time nodes t_0 = 0 < ... < t_{N-1} = T with one temporal basis b_i per
+// node (p = 0), vertices j, l in [0, M), triangles in [0, E).  A_{k,i}(j, l) is the entry of
+// eq. (MatrixEntries): test pair (b_k, phi_l) in x, trial pair (b_i, phi_j) in y.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdbem {
+
+// ---------------------------------------------------------------------------------------------
+// Piecewise Chebyshev tables of psi_{k,i} and tilde psi_{k,i} (Section 3.1).
+// The support of each kernel is cut at every node difference t_c - t_a (the points where the
+// kernel stops being analytic) into "intervals"; every interval is cut by one fixed partition
+// of [0, 1] that is graded geometrically (ratio 1.6, down to 0.004) towards both ends, where
+// the kernels are flat, and uniform (width 1/8) in the middle: kPieces pieces.  On each piece
+// both kernels are interpolated at kNc Chebyshev points of the first kind (degree kDeg) and
+// evaluated with Clenshaw's recurrence.
+// ---------------------------------------------------------------------------------------------
+constexpr int kDeg = 14;
+constexpr int kNc = kDeg + 1;
+constexpr int kPieces = 24;
+constexpr int kMaxIntervals = 9;   // at most 3 x 3 node differences split a support
+
+struct KernelDesc {
+    double lo, hi;        // open support (lo, hi) of psi_{k,i} in r >= 0
+    int32_t nint;         // number of intervals
+    int32_t bp_off;       // interval starts and inverse lengths: ivl[bp_off + 2*j], ivl[bp_off + 2*j + 1]
+    int64_t coef_off;     // first double2 of this kernel: coef[coef_off + (j*kPieces + p)*kNc + m]
+};
+
+// Graded partition of [0, 1] into kPieces pieces: edges and inverse widths (constant memory).
+struct PieceTable {
+    double edge[kPieces + 1];
+    double inv_width[kPieces];
+};
+
+// ---------------------------------------------------------------------------------------------
+// Smooth cutoff F on [0, 1] with F', F'' (Section 3).
+//   bump: F(u) = beta(u-1) / (beta(u-1) + beta(u)), beta(s) = exp(-1/(1 - s^2)), i.e.
+//         F = 1 / (1 + e^g) with g(u) = 1/(u(2-u)) - 1/(1-u^2);
+//   erf:  F(u) = f(2u - 1), f(s) = erf(2 artanh s)/2 + 1/2.
+// ---------------------------------------------------------------------------------------------
+__host__ __device__ inline void cutoff_eval(int kind, double u, double& F, double& F1, double& F2)
+{
+    if (u <= 0.0) { F = 0.0; F1 = 0.0; F2 = 0.0; return; }
+    if (u >= 1.0) { F = 1.0; F1 = 0.0; F2 = 0.0; return; }
+    if (kind == 0) {
+        const double p = u * (2.0 - u);          // 1 - (u-1)^2
+        const double q = (1.0 - u) * (1.0 + u);  // 1 - u^2
+        const double dp = 2.0 - 2.0 * u, dq = -2.0 * u;
+        const double g = 1.0 / p - 1.0 / q;
+        const double g1 = dq / (q * q) - dp / (p * p);
+        // d/du (-p'/p^2) = (2 p + 2 p'^2)/p^3 since p'' = -2; same for q with the opposite sign
+        const double g2 = (2.0 * p + 2.0 * dp * dp) / (p * p * p) - (2.0 * q + 2.0 * dq * dq) / (q * q * q);
+        const double e = exp(-fabs(g));
+        const double f = g > 0.0 ? e / (1.0 + e) : 1.0 / (1.0 + e);
+        const double s = e / ((1.0 + e) * (1.0 + e));      // f (1 - f)
+        F = f;
+        F1 = -g1 * s;
+        F2 = -g2 * s + g1 * g1 * s * (1.0 - 2.0 * f);
+    } else {
+        const double s = 2.0 * u - 1.0;
+        const double om = (1.0 - s) * (1.0 + s);
+        const double at = 0.5 * log((1.0 + s) / (1.0 - s));
+        const double z = 2.0 * at;
+        const double d1 = 1.1283791670955126 * exp(-z * z) / om;   // f'(s), 2/sqrt(pi)
+        F = 0.5 + 0.5 * erf(z);
+        F1 = 2.0 * d1;
+        F2 = 4.0 * d1 * (2.0 * s - 8.0 * at) / om;
+    }
+}
+
+// Temporal basis b_j with first and second derivative (Section 3, eq. (BasisFunctions), p = 0):
+// mu_j from the cutoff on [t_{j-1}, t_j] (rising) and [t_j, t_{j+1}] (falling), mu_{N-1} = 1 after
+// T, every basis 0 for negative arguments (causality), b_0 = 8 (t/h_1)^2 mu_0.
+__host__ __device__ inline void basis_eval(const double* t, int N, int cut, int j, double x,
+                                           double& v, double& d1, double& d2)
+{
+    v = 0.0; d1 = 0.0; d2 = 0.0;
+    if (x < 0.0) return;
+    double F, F1, F2;
+    if (j > 0 && x > t[j - 1] && x <= t[j]) {
+        const double h = t[j] - t[j - 1], ih = 1.0 / h;
+        cutoff_eval(cut, (x - t[j - 1]) * ih, F, F1, F2);
+        v = F; d1 = F1 * ih; d2 = F2 * ih * ih;
+    } else if (j < N - 1 && x >= t[j] && x < t[j + 1]) {
+        const double h = t[j + 1] - t[j], ih = 1.0 / h;
+        cutoff_eval(cut, (x - t[j]) * ih, F, F1, F2);
+        v = 1.0 - F; d1 = -F1 * ih; d2 = -F2 * ih * ih;
+    } else if (j == N - 1 && x > t[N - 1]) {
+        v = 1.0;
+    }
+    if (j == 0) {
+        if (x <= 0.0) { v = d1 = d2 = 0.0; return; }
+        const double ih = 1.0 / (t[1] - t[0]);
+        const double u = x * ih;
+        const double c = 8.0 * u * u, c1 = 16.0 * u * ih, c2 = 16.0 * ih * ih;
+        const double nv = c * v, nd1 = c1 * v + c * d1, nd2 = c2 * v + 2.0 * c1 * d1 + c * d2;
+        v = nv; d1 = nd1; d2 = nd2;
+    }
+}
+
+// Open support of psi_{k,i} (Section 3.2): (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) cap r > 0 with
+// t_{-1} := 0 and t_N := T.
+__host__ __device__ inline void kernel_support(const double* t, int N, int k, int i, double& lo, double& hi)
+{
+    const double tkm = t[k > 0 ? k - 1 : 0], tkp = t[k < N - 1 ? k + 1 : N - 1];
+    const double tim = t[i > 0 ? i - 1 : 0], tip = t[i < N - 1 ? i + 1 : N - 1];
+    lo = tkm - tip > 0.0 ? tkm - tip : 0.0;
+    hi = tkp - tim;
+}
+
+// Clenshaw evaluation of two Chebyshev series with interleaved coefficients c[m] = (psi, tpsi).
+__device__ inline void clenshaw2(const double2* __restrict__ c, double x, double& ps, double& pt)
+{
+    const double x2 = 2.0 * x;
+    double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int m = kDeg; m >= 1; --m) {
+        const double2 cm = c[m];
+        const double a0 = fma(x2, a1, cm.x - a2);
+        const double b0 = fma(x2, b1, cm.y - b2);
+        a2 = a1; a1 = a0; b2 = b1; b1 = b0;
+    }
+    const double2 c0 = c[0];
+    ps = fma(x, a1, c0.x - a2);
+    pt = fma(x, b1, c0.y - b2);
+}
+
+// Device-side table handle (passed by value as a kernel argument).
+struct TableView {
+    const KernelDesc* desc;   // one per tabulated (k, i)
+    const int32_t* fid;       // fid[k*N + i]: index into desc or -1 (identically zero kernel)
+    const double* ivl;        // interval starts and inverse lengths
+    const double2* coef;      // Chebyshev coefficients (psi, tpsi)
+    int32_t N;
+    PieceTable pt;
+};
+
+// Gauss-Legendre rule on [-1, 1] used for every time integral of the library.
+constexpr int kTimeGauss = 20;
+struct TimeRule {
+    double x[kTimeGauss];
+    double w[kTimeGauss];
+};
+// Dyadic grading of a smooth sub-interval towards both ends (the integrands are flat there):
+// pieces [0,1/64], [1/64,1/32], ..., [1/4,1/2] and mirrored, 12 pieces.
+__host__ __device__ inline double time_grading_edge(int g)
+{
+    // g = 0..12
+    const double e[13] = {0.0, 1.0 / 64, 1.0 / 32, 1.0 / 16, 1.0 / 8, 1.0 / 4, 0.5,
+                          0.75, 0.875, 0.9375, 0.96875, 63.0 / 64, 1.0};
+    return e[g];
+}
+constexpr int kTimePieces = 12;
+
+// psi_{k,i}(r), tilde psi_{k,i}(r) from the tables; false (and zeros) outside the open support.
+__device__ inline bool table_eval(const KernelDesc& kd, const double* __restrict__ ivl,
+                                  const double2* __restrict__ coef, const PieceTable& pt,
+                                  double r, double& ps, double& tps)
+{
+    ps = 0.0; tps = 0.0;
+    if (!(r > kd.lo && r < kd.hi)) return false;
+    int j = 0;
+    const double* iv = ivl + kd.bp_off;
+    while (j + 1 < kd.nint && r >= iv[2 * (j + 1)]) ++j;
+    double fr = (r - iv[2 * j]) * iv[2 * j + 1];
+    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    int p = 0;
+#pragma unroll
+    for (int step = 16; step >= 1; step >>= 1)
+        if (p + step < kPieces && fr >= pt.edge[p + step]) p += step;
+    const double x = 2.0 * (fr - pt.edge[p]) * pt.inv_width[p] - 1.0;
+    clenshaw2(coef + kd.coef_off + (int64_t)(j * kPieces + p) * kNc, x, ps, tps);
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Triangle geometry, structure of arrays (lane = triangle).
+// ---------------------------------------------------------------------------------------------
+struct GeomView {
+    const int32_t* v;      // v[a*E + e]: global vertex a of triangle e
+    const double* P;       // P[(3*a + c)*E + e]: vertex coordinates
+    const double* n;       // n[c*E + e]: unit normal
+    const double* area;    // area[e]
+    const double* curl;    // curl[(3*a + c)*E + e] = -e_a / (2|tau|) (tangential rotation of lambda_a)
+    const double* qp;      // qp[(3*q + c)*E + e]: the 7 quadrature points
+    int32_t E;
+};
+
+// Band storage of the blocks: for every ordered vertex pair (l, j) and time row k, the
+// trial indices i = ilo[k][l][j] + s, s < B_k, that can be non-zero
+// (eq. (SparsitySmallBlock) with conservative patch distances), values at
+// val[voff[k] + (l*B_k + s)*M + j].
+struct BandView {
+    const int16_t* ilo;    // ilo[(k*M + l)*M + j]
+    const int32_t* B;      // B[k]
+    const int64_t* voff;   // voff[k]
+    int32_t M, N;
+};
+
+}  // namespace tdbem
+
+// ---------------------------------------------------------------------------------------------
+// Launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------------------------
+namespace tdbem {
+void launch_table_values(const double* t, int N, int cut, TimeRule rule, PieceTable pt, const int32_t* pc_f,
+                         const int32_t* pc_j, const int32_t* pc_p, int64_t npieces, const int32_t* f_k,
+                         const int32_t* f_i, const KernelDesc* desc, const double* ivl, double2* values,
+                         hipStream_t s);
+void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, hipStream_t s);
+void launch_table_eval(TableView tv, int64_t n, const int32_t* k, const int32_t* i, const double* r,
+                       double* ps, double* tps, hipStream_t s);
+
+void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P, double* geo_n,
+                     double* geo_area, double* geo_curl, double* geo_qp, int32_t* geo_v, hipStream_t s);
+void launch_layout(const double* xyz, const double* rho, int M, const double* t, int N, int16_t* ilo,
+                   int32_t* Bk, hipStream_t s);
+
+void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
+                    unsigned long long* counter, hipStream_t s);
+void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
+                     int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
+                     double* val, float* valf, unsigned long long* counter, hipStream_t s);
+void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,
+                        const int32_t* i, const int32_t* j, const int32_t* l, double* out, hipStream_t s);
+
+void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
+                double t0, double width, int M, double* gvec, hipStream_t s);
+void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
+                   const double* x, double* y, hipStream_t s);
+
+void launch_dots(const double* V, int nvec, int64_t n, int64_t ld, const double* w, double* partial,
+                 double* out, hipStream_t s);
+void launch_sub_combination(double* w, const double* V, int nvec, int64_t n, int64_t ld, const double* h,
+                            double sign, hipStream_t s);
+void launch_scale_copy(double* dst, const double* src, double a, int64_t n, hipStream_t s);
+void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
+int dots_partial_blocks(int64_t n);
+void launch_scale_inv_sqrt(double* dst, const double* src, const double* nrm2, int64_t n, hipStream_t s);
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+}  // namespace tdbem
