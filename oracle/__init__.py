@@ -63,6 +63,9 @@ def lib():
                                           dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_count_quad_evals.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int]
         L.orc_count_quad_evals.restype = ctypes.c_int64
+        L.orc_local_batch.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_local_batch.restype = ctypes.c_int64
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -194,6 +197,19 @@ def rhs_plane_pulse(xyz, tri, grid, direction, t0, width, kind="bump"):
 def count_quad_evals(xyz, tri, grid, ss_order=4):
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
     return int(lib().orc_count_quad_evals(xp, len(x), tp, len(t), gp, len(g), ss_order))
+
+
+def local_batch(xyz, tri, taus, sigmas, grid, kind="bump", ss_order=4):
+    """Local integrals of the ordered pairs (taus[s], sigmas[s]); returns (quad-evals, checksum)."""
+    x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
+    a, ap = _i(taus); b, bp = _i(sigmas)
+    chk = ctypes.c_double()
+    n = lib().orc_local_batch(xp, tp, len(a), ap, bp, gp, len(g), CUTOFF[kind], ss_order, ctypes.byref(chk))
+    return int(n), chk.value
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def system_matrix(blocks):

@@ -384,6 +384,7 @@ static void tri_build(const double *xyz, const int32_t *tri, int e, tri_t *T)
 typedef struct {
     const double *t;
     int N, cut, mode;
+    int64_t *count;   /* optional: number of (point pair, k, i) evaluated */
 } tctx_t;
 
 static void accumulate_point(const tctx_t *C, const double *lx, const double *ly,
@@ -405,6 +406,7 @@ static void accumulate_point(const tctx_t *C, const double *lx, const double *ly
             if (!(r > lo && r < hi)) continue;
             double ps[2];
             orc_psi(C->t, C->N, C->cut, k, i, r, ps);
+            if (C->count) ++*C->count;
             double f1 = C->mode == 4 ? 0.0 : wgt * ps[0] / r;
             double f2 = C->mode == 5 ? 0.0 : wgt * ps[1] / r;
             double *s1 = S1 + 9 * (k * nb + i);
@@ -527,7 +529,7 @@ static void pair_local(const tctx_t *C, const tri_t *X, const tri_t *Y, int ss_o
 void orc_pair_local(const double *xyz, const int32_t *tri, int ex, int ey, const double *t, int N,
                     int cut, int mode, int ss_order, double *loc)
 {
-    tctx_t C = {t, N, cut, mode};
+    tctx_t C = {t, N, cut, mode, NULL};
     tri_t X, Y;
     tri_build(xyz, tri, ex, &X);
     tri_build(xyz, tri, ey, &Y);
@@ -555,7 +557,7 @@ int orc_assemble_dense(const double *xyz, int M, const int32_t *tri, int E, cons
 #endif
     double *buf = (double *)calloc(total * (size_t)nthr, sizeof(double));
     if (!buf) return -1;
-    tctx_t C = {t, N, cut, mode};
+    tctx_t C = {t, N, cut, mode, NULL};
 #pragma omp parallel
     {
         int tid = 0;
@@ -600,7 +602,7 @@ int orc_assemble_entries(const double *xyz, int M, const int32_t *tri, int E, co
     int nb = (mode == 0 || mode >= 4) ? N : 1;
     (void)M;
     memset(out, 0, sizeof(double) * (size_t)nsel * nb * nb);
-    tctx_t C = {t, N, cut, mode};
+    tctx_t C = {t, N, cut, mode, NULL};
     /* vertex -> triangles */
     int *cnt = (int *)calloc(M, sizeof(int));
     for (int e = 0; e < 3 * E; ++e) cnt[tri[e]]++;
@@ -765,4 +767,42 @@ int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E
         free(rule);
     }
     return total;
+}
+
+/* Local integrals of a list of ordered pairs (CPU timing of the method on a sample of a
+ * workload): returns the number of (point pair, k, i) evaluations; *checksum receives the sum
+ * of all local entries so that nothing is optimised away. */
+int64_t orc_local_batch(const double *xyz, const int32_t *tri, int npairs, const int32_t *taus,
+                        const int32_t *sigmas, const double *t, int N, int cut, int ss_order,
+                        double *checksum)
+{
+    int64_t total = 0;
+    double sum = 0.0;
+#pragma omp parallel reduction(+ : total, sum)
+    {
+        int64_t mine = 0;
+        tctx_t C = {t, N, cut, 0, &mine};
+        double *loc = (double *)malloc(sizeof(double) * 9 * N * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int s = 0; s < npairs; ++s) {
+            tri_t X, Y;
+            tri_build(xyz, tri, taus[s], &X);
+            tri_build(xyz, tri, sigmas[s], &Y);
+            pair_local(&C, &X, &Y, ss_order, loc);
+            for (int m = 0; m < 9 * N * N; ++m) sum += loc[m];
+        }
+        total += mine;
+        free(loc);
+    }
+    *checksum = sum;
+    return total;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

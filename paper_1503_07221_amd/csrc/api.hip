@@ -95,6 +95,12 @@ PieceTable make_piece_table()
     }
     for (int s = 0; s <= kPieces; ++s) pt.edge[s] = e[std::min<size_t>(s, e.size() - 1)];
     for (int s = 0; s < kPieces; ++s) pt.inv_width[s] = 1.0 / (pt.edge[s + 1] - pt.edge[s]);
+    for (int cidx = 0; cidx < kLutCells; ++cidx) {
+        const double x = (double)cidx / kLutCells;
+        int p = 0;
+        while (p + 1 < kPieces && pt.edge[p + 1] <= x) ++p;
+        pt.lut[cidx] = (uint8_t)p;
+    }
     return pt;
 }
 
@@ -254,6 +260,16 @@ static tdbem_status upload(tdbem_ctx* c, DBuf& buf, const T* host, size_t n)
         tdbem_status _s = (expr);                   \
         if (_s != TDBEM_OK) return _s;              \
     } while (0)
+
+// Per-triangle structure of arrays (normals, areas, surface curls, quadrature points).
+static tdbem_status run_geometry(tdbem_ctx* c)
+{
+    launch_geometry(c->d_xyz.as<double>(), c->d_tri.as<int32_t>(), c->E, c->g_P.as<double>(), c->g_n.as<double>(),
+                    c->g_area.as<double>(), c->g_curl.as<double>(), c->g_qp.as<double>(), c->g_v.as<int32_t>(),
+                    c->stream);
+    HIPCHK(c, hipGetLastError());
+    return TDBEM_OK;
+}
 
 extern "C" {
 
@@ -423,10 +439,7 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     ALLOC(c, c->g_curl, sizeof(double) * 9 * E);
     ALLOC(c, c->g_qp, sizeof(double) * 21 * E);
     ALLOC(c, c->g_v, sizeof(int32_t) * 3 * E);
-    launch_geometry(c->d_xyz.as<double>(), c->d_tri.as<int32_t>(), c->E, c->g_P.as<double>(), c->g_n.as<double>(),
-                    c->g_area.as<double>(), c->g_curl.as<double>(), c->g_qp.as<double>(), c->g_v.as<int32_t>(),
-                    c->stream);
-    HIPCHK(c, hipGetLastError());
+    TRY(run_geometry(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_mesh = true;
     return TDBEM_OK;
@@ -585,6 +598,7 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         ~EvGuard() { for (int s = 0; s < 5; ++s) (void)hipEventDestroy(e[s]); }
     } guard{ev};
     HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    TRY(run_geometry(c));
     TRY(build_tables(c));
     HIPCHK(c, hipEventRecord(ev[1], c->stream));
     TRY(build_layout(c, (int)prec));
@@ -600,6 +614,8 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
                     c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), v64, v32, cnt + 1,
                     c->stream);
+    HIPCHK(c, hipGetLastError());
+    launch_symmetrize(c->band(), v64, v32, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

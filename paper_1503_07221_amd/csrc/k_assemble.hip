@@ -7,7 +7,9 @@
 //   k_singular   coincident / common-edge / common-vertex pairs: Sauter-Schwab rules
 // Every unordered pair {tau < sigma} is integrated once with tau as the x-triangle and its local
 // 3 x 3 block is added to A(v_b(sigma), v_a(tau)) and, by the symmetry of the kernel in
-// x <-> y, to A(v_a(tau), v_b(sigma)); a coincident pair adds its symmetrised block once.
+// x <-> y, to A(v_a(tau), v_b(sigma)); a coincident pair adds its symmetrised block once.  The
+// kernels add only the first of the two (a coincident block halved) into P and k_symmetrize
+// forms A = P + P^T, which gives exactly these sums.
 #include "tdbem_internal.hpp"
 
 namespace tdbem {
@@ -111,19 +113,6 @@ k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, 
         if (sB[k] > 0) atomicMax(&Bk[k], sB[k]);
 }
 
-// Add one local 3 x 3 block of the time pair (k, i) to the band storage.
-__device__ inline void scatter_add(const BandView& band, double* val, float* valf, int k, int i, int l, int j,
-                                   double v)
-{
-    const int64_t M = band.M;
-    const int s = i - (int)band.ilo[((int64_t)k * M + l) * M + j];
-    const int B = band.B[k];
-    if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
-    const int64_t idx = band.voff[k] + ((int64_t)l * B + s) * M + j;
-    if (valf) atomicAdd(valf + idx, (float)v);
-    else atomicAdd(val + idx, v);
-}
-
 __device__ inline double wave_min(double v)
 {
     for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
@@ -141,63 +130,94 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Regular pairs.  Block (tau, 256 consecutive sigma); one lane per unordered pair tau < sigma
-// without a common vertex.  The 49 distances are computed once; the (k, i) loop runs over the
-// union of the lanes' bands (wave-uniform, so kernel descriptors are scalar loads) and each lane
-// evaluates only the point pairs inside the open support.
+// Regular pairs.  Block = (tau, 32 consecutive sigma); a group of 8 lanes per unordered pair
+// tau < sigma without a common vertex, lane q < 7 owning the test point x_q and its 7 distances
+// to the points y_q' of sigma (lane 7 idles).  The (k, i) loop runs over the union of the bands
+// of the wave's 8 pairs (wave-uniform: kernel descriptors and interval starts are scalar loads).
+// Per (k, i) a lane forms R_b = sum_q' w_q' lam_b(q') psi(r)/r and sum_q' w_q' tpsi(r)/r; the
+// 8-lane group reduces w_q lam_a(q) R_b and the tpsi sum, and lane m writes entry (a, b) =
+// (m / 3, m % 3) (lane 0 also entry 8).  Only the half P(v_b(sigma), v_a(tau)) is added here;
+// the blocks are completed by A = P + P^T (k_symmetrize).
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
+__device__ inline double group8_sum(double v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    return v;
+}
+
+__device__ inline void scatter_half(const BandView& band, double* val, float* valf, int k, int i, int l, int j,
+                                    double v)
+{
+    const int64_t M = band.M;
+    const int s = i - (int)band.ilo[((int64_t)k * M + l) * M + j];
+    const int B = band.B[k];
+    if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
+    const int64_t idx = band.voff[k] + ((int64_t)l * B + s) * M + j;
+    if (valf) atomicAdd(valf + idx, (float)v);
+    else atomicAdd(val + idx, v);
+}
+
+__global__ void __launch_bounds__(256, 3)
 k_regular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
           unsigned long long* counter)
 {
     const int E = g.E;
     const int tau = blockIdx.y;
-    if ((int)(blockIdx.x * 256 + 255) <= tau) return;
-    const int sig = blockIdx.x * 256 + threadIdx.x;
+    if ((int)(blockIdx.x * 32 + 31) <= tau) return;   // whole block on or below the diagonal
+    __shared__ PieceTable spt;
+    load_piece_table(spt, tv.pt);
+    __syncthreads();
     const int N = tv.N;
+    const int q = threadIdx.x & 7;
+    const int sig = blockIdx.x * 32 + (threadIdx.x >> 3);
     const int tv0 = g.v[tau], tv1 = g.v[E + tau], tv2 = g.v[2 * E + tau];
-    bool active = sig > tau && sig < E;
+    bool pair_ok = sig > tau && sig < E;
     int sv0 = 0, sv1 = 0, sv2 = 0;
-    if (active) {
+    if (pair_ok) {
         sv0 = g.v[sig]; sv1 = g.v[E + sig]; sv2 = g.v[2 * E + sig];
         if (sv0 == tv0 || sv0 == tv1 || sv0 == tv2 || sv1 == tv0 || sv1 == tv1 || sv1 == tv2 ||
             sv2 == tv0 || sv2 == tv1 || sv2 == tv2)
-            active = false;
+            pair_ok = false;
     }
-    const int sg = active ? sig : tau;   // inactive lanes read valid memory and do no work
-    double r[49], ir[49];
+    const int sg = pair_ok ? sig : tau;       // every lane reads valid memory
+    const int qx = q < 7 ? q : 0;
+    double lqa0, lqa1, lqa2, wq;
+    rule7_point(qx, lqa0, lqa1, lqa2, wq);
+    if (q == 7) wq = 0.0;                     // the idle lane contributes nothing
+    const double x0 = g.qp[(3 * qx) * E + tau], x1 = g.qp[(3 * qx + 1) * E + tau], x2 = g.qp[(3 * qx + 2) * E + tau];
+    double r[7], ir[7];
     double rmin = 1e300, rmax = -1e300;
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        const double x0 = g.qp[(3 * q) * E + tau], x1 = g.qp[(3 * q + 1) * E + tau], x2 = g.qp[(3 * q + 2) * E + tau];
-#pragma unroll
-        for (int p = 0; p < 7; ++p) {
-            const double d0 = x0 - g.qp[(3 * p) * E + sg], d1 = x1 - g.qp[(3 * p + 1) * E + sg],
-                         d2 = x2 - g.qp[(3 * p + 2) * E + sg];
-            const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            r[7 * q + p] = rr;
-            ir[7 * q + p] = 1.0 / rr;
-            rmin = fmin(rmin, rr);
-            rmax = fmax(rmax, rr);
-        }
+    for (int p = 0; p < 7; ++p) {
+        const double d0 = x0 - g.qp[(3 * p) * E + sg], d1 = x1 - g.qp[(3 * p + 1) * E + sg],
+                     d2 = x2 - g.qp[(3 * p + 2) * E + sg];
+        r[p] = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        ir[p] = 1.0 / r[p];
+        rmin = fmin(rmin, r[p]);
+        rmax = fmax(rmax, r[p]);
     }
-    if (!active) { rmin = 1e300; rmax = -1e300; }
-    const double wmin = wave_min(rmin), wmax = wave_max(rmax);
-    if (wmax < wmin) return;   // no active lane in this wave
+    const bool lane_ok = pair_ok && q < 7;
+    if (!lane_ok) { rmin = 1e300; rmax = -1e300; }
+    // pair range (group of 8) and wave union
+    double pmin = rmin, pmax = rmax;
+    for (int o = 1; o <= 4; o <<= 1) { pmin = fmin(pmin, __shfl_xor(pmin, o, 64)); pmax = fmax(pmax, __shfl_xor(pmax, o, 64)); }
+    double wmin = pmin, wmax = pmax;
+    for (int o = 8; o <= 32; o <<= 1) { wmin = fmin(wmin, __shfl_xor(wmin, o, 64)); wmax = fmax(wmax, __shfl_xor(wmax, o, 64)); }
+    if (wmax < wmin) return;                  // no pair in this wave (wave-uniform)
 
-    // pair constants: n_tau . n_sigma, curl products, |tau||sigma|/(4 pi)
+    // the entry this lane writes: m = q (and 8 for lane 0)
+    const int ma = q / 3, mb = q % 3;
+    const int la = ma == 0 ? tv0 : (ma == 1 ? tv1 : tv2), jb = mb == 0 ? sv0 : (mb == 1 ? sv1 : sv2);
     const double nn = g.n[tau] * g.n[sg] + g.n[E + tau] * g.n[E + sg] + g.n[2 * E + tau] * g.n[2 * E + sg];
-    double C[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            C[a][b] = g.curl[(3 * a) * E + tau] * g.curl[(3 * b) * E + sg] +
-                      g.curl[(3 * a + 1) * E + tau] * g.curl[(3 * b + 1) * E + sg] +
-                      g.curl[(3 * a + 2) * E + tau] * g.curl[(3 * b + 2) * E + sg];
-    const double scale = g.area[tau] * g.area[sg] * 0.07957747154594767;   // 1/(4 pi)
-    const int vt[3] = {tv0, tv1, tv2};
-    const int vs[3] = {sv0, sv1, sv2};
+    const int ca = q < 7 ? ma : 2, cb = q < 7 ? mb : 1;   // lane 7 writes entry 7 = (2, 1)
+    const double Cm = g.curl[(3 * ca) * E + tau] * g.curl[(3 * cb) * E + sg] +
+                      g.curl[(3 * ca + 1) * E + tau] * g.curl[(3 * cb + 1) * E + sg] +
+                      g.curl[(3 * ca + 2) * E + tau] * g.curl[(3 * cb + 2) * E + sg];
+    const double C8 = g.curl[6 * E + tau] * g.curl[6 * E + sg] + g.curl[7 * E + tau] * g.curl[7 * E + sg] +
+                      g.curl[8 * E + tau] * g.curl[8 * E + sg];
+    const double scale = g.area[tau] * g.area[sg] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
     unsigned long long nq = 0;
 
     int ia = 0, ib = -1;
@@ -218,48 +238,75 @@ k_regular(GeomView g, TableView tv, const double* __restrict__ t, BandView band,
             const int f = tv.fid[k * N + i];
             if (f < 0) continue;
             const KernelDesc kd = tv.desc[f];
-            if (!active || !(rmax > kd.lo && rmin < kd.hi)) continue;
-            double S1[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-            double S2 = 0.0;
+            const bool pair_hit = pmax > kd.lo && pmin < kd.hi && pair_ok;
+            if (!__any(pair_hit)) continue;   // wave-uniform skip
+            double R0 = 0.0, R1 = 0.0, R2 = 0.0, S2 = 0.0;
             int hits = 0;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                double la0, la1, la2, wq;
-                rule7_point(q, la0, la1, la2, wq);
-                double R0 = 0.0, R1 = 0.0, R2 = 0.0;
+            if (pair_hit && q < 7) {
 #pragma unroll
                 for (int p = 0; p < 7; ++p) {
                     double lb0, lb1, lb2, wp;
                     rule7_point(p, lb0, lb1, lb2, wp);
                     double ps, pt;
-                    if (table_eval(kd, tv.ivl, tv.coef, tv.pt, r[7 * q + p], ps, pt)) {
+                    if (table_eval(kd, tv.ivl, tv.coef, spt, r[p], ps, pt)) {
                         ++hits;
-                        const double c = wp * ir[7 * q + p];
+                        const double c = wp * ir[p];
                         const double f1 = ps * c;
                         R0 = fma(f1, lb0, R0);
                         R1 = fma(f1, lb1, R1);
                         R2 = fma(f1, lb2, R2);
-                        S2 = fma(wq * c, pt, S2);
+                        S2 = fma(c, pt, S2);
                     }
                 }
-                S1[0][0] = fma(wq * la0, R0, S1[0][0]); S1[0][1] = fma(wq * la0, R1, S1[0][1]); S1[0][2] = fma(wq * la0, R2, S1[0][2]);
-                S1[1][0] = fma(wq * la1, R0, S1[1][0]); S1[1][1] = fma(wq * la1, R1, S1[1][1]); S1[1][2] = fma(wq * la1, R2, S1[1][2]);
-                S1[2][0] = fma(wq * la2, R0, S1[2][0]); S1[2][1] = fma(wq * la2, R1, S1[2][1]); S1[2][2] = fma(wq * la2, R2, S1[2][2]);
             }
-            if (hits == 0) continue;
             nq += hits;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const double v = (nn * S1[a][b] + C[a][b] * S2) * scale;
-                    scatter_add(band, val, valf, k, i, vt[a], vs[b], v);   // A(v_b(sigma), v_a(tau)) at row l = v_a(tau)
-                    scatter_add(band, val, valf, k, i, vs[b], vt[a], v);   // mirror: row l = v_b(sigma)
-                }
+            // group reduction of w_q lam_a(q) R_b (a, b) and w_q S2
+            const double s00 = group8_sum(wq * lqa0 * R0), s01 = group8_sum(wq * lqa0 * R1), s02 = group8_sum(wq * lqa0 * R2);
+            const double s10 = group8_sum(wq * lqa1 * R0), s11 = group8_sum(wq * lqa1 * R1), s12 = group8_sum(wq * lqa1 * R2);
+            const double s20 = group8_sum(wq * lqa2 * R0), s21 = group8_sum(wq * lqa2 * R1), s22 = group8_sum(wq * lqa2 * R2);
+            const double sS2 = group8_sum(wq * S2);
+            if (!pair_hit) continue;
+            double Sm;
+            switch (q) {
+            case 0: Sm = s00; break;
+            case 1: Sm = s01; break;
+            case 2: Sm = s02; break;
+            case 3: Sm = s10; break;
+            case 4: Sm = s11; break;
+            case 5: Sm = s12; break;
+            case 6: Sm = s20; break;
+            default: Sm = s21; break;
+            }
+            const int mla = q < 7 ? la : tv2, mjb = q < 7 ? jb : sv1;
+            scatter_half(band, val, valf, k, i, mla, mjb, (nn * Sm + Cm * sS2) * scale);
+            if (q == 0) scatter_half(band, val, valf, k, i, tv2, sv2, (nn * s22 + C8 * sS2) * scale);
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
     if ((threadIdx.x & 63) == 0 && tot) atomicAdd(counter, tot);
+}
+
+// A = P + P^T on the band storage: entry (k, l, s, j) and its transpose (k, j, s, l) share the
+// band slot because ilo is symmetric in (l, j).  One lane per (k, l, j) with j <= l.
+template <typename VT>
+__global__ void __launch_bounds__(256)
+k_symmetrize(BandView band, VT* __restrict__ val)
+{
+    const int64_t M = band.M;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (gid >= M * M) return;
+    const int l = (int)(gid / M), j = (int)(gid - (int64_t)l * M);
+    if (j > l) return;
+    const int B = band.B[k];
+    VT* base = val + band.voff[k];
+    for (int s = 0; s < B; ++s) {
+        VT* a = base + ((int64_t)l * B + s) * M + j;
+        VT* b = base + ((int64_t)j * B + s) * M + l;
+        const VT v = *a + *b;
+        *a = v;
+        *b = v;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -275,6 +322,9 @@ k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band
            int64_t npairs, const double* __restrict__ rules, const int32_t* __restrict__ roff,
            const int32_t* __restrict__ rcnt, double* val, float* valf, unsigned long long* counter)
 {
+    __shared__ PieceTable spt;
+    load_piece_table(spt, tv.pt);
+    __syncthreads();
     const int N = tv.N;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long nq = 0;
@@ -365,7 +415,7 @@ k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band
 #pragma unroll
                 for (int u = 0; u < kSingBand; ++u) {
                     double ps, pt;
-                    if (have[u] && table_eval(kd[u], tv.ivl, tv.coef, tv.pt, rr, ps, pt)) {
+                    if (have[u] && table_eval(kd[u], tv.ivl, tv.coef, spt, rr, ps, pt)) {
                         ++nq;
                         const double f1 = ps * wr;
                         const double R0 = f1 * ly0, R1 = f1 * ly1, R2 = f1 * ly2;
@@ -398,15 +448,12 @@ k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) scatter_add(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
+                        for (int b = 0; b < 3; ++b) scatter_half(band, val, valf, k, i, vtr[a], vsr[b], 0.5 * loc[a][b]);
                 } else {
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            scatter_add(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
-                            scatter_add(band, val, valf, k, i, vsr[b], vtr[a], loc[a][b]);
-                        }
+                        for (int b = 0; b < 3; ++b) scatter_half(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
                 }
             }
         }
@@ -456,8 +503,15 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
                     unsigned long long* counter, hipStream_t s)
 {
-    dim3 grid(grid_for(g.E, 256), g.E);
+    dim3 grid(grid_for(g.E, 32), g.E);
     hipLaunchKernelGGL(k_regular, grid, dim3(256), 0, s, g, tv, t, band, val, valf, counter);
+}
+
+void launch_symmetrize(BandView band, double* val, float* valf, hipStream_t s)
+{
+    dim3 grid(grid_for((int64_t)band.M * band.M, 256), band.N);
+    if (valf) hipLaunchKernelGGL(k_symmetrize<float>, grid, dim3(256), 0, s, band, valf);
+    else hipLaunchKernelGGL(k_symmetrize<double>, grid, dim3(256), 0, s, band, val);
 }
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,

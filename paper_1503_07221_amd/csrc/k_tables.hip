@@ -102,13 +102,16 @@ __global__ void __launch_bounds__(256)
 k_table_eval(TableView tv, int64_t n, const int32_t* __restrict__ k, const int32_t* __restrict__ i,
              const double* __restrict__ r, double* __restrict__ ps, double* __restrict__ tps)
 {
+    __shared__ PieceTable spt;
+    load_piece_table(spt, tv.pt);
+    __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int kk = k[s], ii = i[s];
     double a = 0.0, b = 0.0;
     if (kk >= 0 && kk < tv.N && ii >= 0 && ii < tv.N) {
         const int f = tv.fid[kk * tv.N + ii];
-        if (f >= 0) table_eval(tv.desc[f], tv.ivl, tv.coef, tv.pt, r[s], a, b);
+        if (f >= 0) table_eval(tv.desc[f], tv.ivl, tv.coef, spt, r[s], a, b);
     }
     ps[s] = a;
     tps[s] = b;

@@ -31,11 +31,22 @@ struct KernelDesc {
     int64_t coef_off;     // first double2 of this kernel: coef[coef_off + (j*kPieces + p)*kNc + m]
 };
 
-// Graded partition of [0, 1] into kPieces pieces: edges and inverse widths (constant memory).
+// Graded partition of [0, 1] into kPieces pieces: edges, inverse widths and a lookup table
+// lut[c] = the piece containing c / kLutCells.  Every piece is wider than one cell, so the piece
+// of any point is lut[cell] or the next one.  Kernels copy it to LDS.
+constexpr int kLutCells = 1024;
 struct PieceTable {
     double edge[kPieces + 1];
     double inv_width[kPieces];
+    uint8_t lut[kLutCells];
 };
+
+__device__ inline void load_piece_table(PieceTable& dst, const PieceTable& src)
+{
+    for (int s = threadIdx.x; s <= kPieces; s += blockDim.x) dst.edge[s] = src.edge[s];
+    for (int s = threadIdx.x; s < kPieces; s += blockDim.x) dst.inv_width[s] = src.inv_width[s];
+    for (int s = threadIdx.x; s < kLutCells; s += blockDim.x) dst.lut[s] = src.lut[s];
+}
 
 // ---------------------------------------------------------------------------------------------
 // Smooth cutoff F on [0, 1] with F', F'' (Section 3).
@@ -158,21 +169,23 @@ __host__ __device__ inline double time_grading_edge(int g)
 constexpr int kTimePieces = 12;
 
 // psi_{k,i}(r), tilde psi_{k,i}(r) from the tables; false (and zeros) outside the open support.
+// pt lives in LDS.  The interval is found by counting the interval starts below r (the starts
+// are the same for all lanes of a wave when (k, i) is wave-uniform).
 __device__ inline bool table_eval(const KernelDesc& kd, const double* __restrict__ ivl,
                                   const double2* __restrict__ coef, const PieceTable& pt,
                                   double r, double& ps, double& tps)
 {
     ps = 0.0; tps = 0.0;
     if (!(r > kd.lo && r < kd.hi)) return false;
-    int j = 0;
     const double* iv = ivl + kd.bp_off;
-    while (j + 1 < kd.nint && r >= iv[2 * (j + 1)]) ++j;
+    int j = 0;
+    for (int m = 1; m < kd.nint; ++m) j += r >= iv[2 * m] ? 1 : 0;
     double fr = (r - iv[2 * j]) * iv[2 * j + 1];
     fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-    int p = 0;
-#pragma unroll
-    for (int step = 16; step >= 1; step >>= 1)
-        if (p + step < kPieces && fr >= pt.edge[p + step]) p += step;
+    int cell = (int)(fr * kLutCells);
+    cell = cell < kLutCells ? cell : kLutCells - 1;
+    int p = pt.lut[cell];
+    if (p + 1 < kPieces && fr >= pt.edge[p + 1]) ++p;
     const double x = 2.0 * (fr - pt.edge[p]) * pt.inv_width[p] - 1.0;
     clenshaw2(coef + kd.coef_off + (int64_t)(j * kPieces + p) * kNc, x, ps, tps);
     return true;
@@ -223,6 +236,7 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
                     unsigned long long* counter, hipStream_t s);
+void launch_symmetrize(BandView band, double* val, float* valf, hipStream_t s);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      double* val, float* valf, unsigned long long* counter, hipStream_t s);
