@@ -164,10 +164,11 @@ struct tdbem_ctx {
     TimeRule rule{};
     PieceTable pieces{};
     // tables
-    DBuf d_desc, d_fid, d_ivl, d_coef, d_fk, d_fi;
+    DBuf d_desc, d_fid, d_ivl, d_coef, d_coef32, d_fk, d_fi;
+    double hmax = 0.0;   // longest triangle edge
     int64_t nfunc = 0;
     // band storage
-    DBuf d_ilo, d_B, d_voff, d_val, d_counter;
+    DBuf d_ilo, d_B, d_voff, d_val, d_counter, d_xt;
     std::vector<int32_t> Bk;
     std::vector<int64_t> voff;
     int64_t nvals = 0;
@@ -201,6 +202,7 @@ struct tdbem_ctx {
         tv.fid = d_fid.as<int32_t>();
         tv.ivl = d_ivl.as<double>();
         tv.coef = d_coef.as<double2>();
+        tv.coef32 = d_coef32.as<float2>();
         tv.N = N;
         tv.pt = pieces;
         return tv;
@@ -213,6 +215,7 @@ struct tdbem_ctx {
         b.voff = d_voff.as<int64_t>();
         b.M = M;
         b.N = N;
+        b.ntri = (int64_t)M * (M + 1) / 2;
         return b;
     }
     const double* valf64() const { return prec == TDBEM_FP64 ? d_val.as<double>() : nullptr; }
@@ -342,6 +345,7 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     c->M = (int)M;
     c->E = (int)E;
     c->xyz.assign(xyz, xyz + 3 * M);
+    c->hmax = 0.0;
     c->tri.assign(tri, tri + 3 * E);
     // diameter bound: bounding box diagonal
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -364,6 +368,7 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
                 const double dx = xyz[3 * v] - xyz[3 * u], dy = xyz[3 * v + 1] - xyz[3 * u + 1],
                              dz = xyz[3 * v + 2] - xyz[3 * u + 2];
                 rho[v] = std::max(rho[v], std::sqrt(dx * dx + dy * dy + dz * dz));
+                c->hmax = std::max(c->hmax, rho[v]);
             }
         }
     // singular pairs {tau <= sigma} sharing at least one vertex, grouped by kind
@@ -539,11 +544,12 @@ static tdbem_status build_tables(tdbem_ctx* c)
     TRY(upload(c, d_pcp, pc_p.data(), pc_p.size()));
     ALLOC(c, d_values, sizeof(double2) * (size_t)npieces * kNc);
     ALLOC(c, c->d_coef, sizeof(double2) * (size_t)npieces * kNc);
+    ALLOC(c, c->d_coef32, sizeof(float2) * (size_t)npieces * kNc);
     launch_table_values(c->d_t.as<double>(), N, c->cut, c->rule, c->pieces, d_pcf.as<int32_t>(), d_pcj.as<int32_t>(),
                         d_pcp.as<int32_t>(), npieces, c->d_fk.as<int32_t>(), c->d_fi.as<int32_t>(),
                         c->d_desc.as<KernelDesc>(), c->d_ivl.as<double>(), d_values.as<double2>(), c->stream);
     HIPCHK(c, hipGetLastError());
-    launch_table_coefs(d_values.as<double2>(), npieces, c->d_coef.as<double2>(), c->stream);
+    launch_table_coefs(d_values.as<double2>(), npieces, c->d_coef.as<double2>(), c->d_coef32.as<float2>(), c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));   // the temporaries are released on return
     return TDBEM_OK;
@@ -552,7 +558,8 @@ static tdbem_status build_tables(tdbem_ctx* c)
 static tdbem_status build_layout(tdbem_ctx* c, int prec)
 {
     const int64_t M = c->M, N = c->N;
-    ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * M * M));
+    const int64_t ntri = M * (M + 1) / 2;
+    ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * ntri));
     ALLOC(c, c->d_B, sizeof(int32_t) * N);
     HIPCHK(c, hipMemsetAsync(c->d_B.p, 0, sizeof(int32_t) * N, c->stream));
     launch_layout(c->d_xyz.as<double>(), c->d_rho.as<double>(), c->M, c->d_t.as<double>(), c->N,
@@ -565,7 +572,7 @@ static tdbem_status build_layout(tdbem_ctx* c, int prec)
     int64_t tot = 0;
     for (int k = 0; k < N; ++k) {
         c->voff[k] = tot;
-        tot += (int64_t)c->Bk[k] * M * M;
+        tot += (int64_t)c->Bk[k] * ntri;
     }
     c->nvals = tot;
     TRY(upload(c, c->d_voff, c->voff.data(), c->voff.size()));
@@ -579,6 +586,7 @@ static tdbem_status build_layout(tdbem_ctx* c, int prec)
     }
     ALLOC(c, c->d_val, need);
     HIPCHK(c, hipMemsetAsync(c->d_val.p, 0, need, c->stream));
+    ALLOC(c, c->d_xt, sizeof(double) * (size_t)(M * N));
     return TDBEM_OK;
 }
 
@@ -608,14 +616,15 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
     float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
     unsigned long long* cnt = c->d_counter.as<unsigned long long>();
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, cnt, c->stream);
+    // mixed precision: point pairs farther apart than three of the longest triangle edges are the
+    // far field; FP64 everywhere in FP64 mode
+    const double r_far = prec == TDBEM_MIXED ? 3.0 * c->hmax : INFINITY;
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, r_far, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
                     c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), v64, v32, cnt + 1,
                     c->stream);
-    HIPCHK(c, hipGetLastError());
-    launch_symmetrize(c->band(), v64, v32, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -705,7 +714,7 @@ tdbem_status tdbem_rhs_plane_pulse(tdbem_ctx* c, const double d[3], double t0, d
 
 static tdbem_status matvec_range(tdbem_ctx* c, int k0, int k1, int i0, int i1, const double* x, double* y)
 {
-    launch_matvec(c->band(), c->valf64(), c->valf32(), k0, k1, i0, i1, x, y, c->stream);
+    launch_matvec(c->band(), c->valf64(), c->valf32(), k0, k1, i0, i1, x, y, c->d_xt.as<double>(), c->stream);
     HIPCHK(c, hipGetLastError());
     ++c->matvecs;
     return TDBEM_OK;

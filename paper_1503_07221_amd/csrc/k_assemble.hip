@@ -8,8 +8,8 @@
 // Every unordered pair {tau < sigma} is integrated once with tau as the x-triangle and its local
 // 3 x 3 block is added to A(v_b(sigma), v_a(tau)) and, by the symmetry of the kernel in
 // x <-> y, to A(v_a(tau), v_b(sigma)); a coincident pair adds its symmetrised block once.  The
-// kernels add only the first of the two (a coincident block halved) into P and k_symmetrize
-// forms A = P + P^T, which gives exactly these sums.
+// kernels add only the first of the two (a coincident block halved) into P, A = P + P^T, which
+// the lower-triangle storage forms on the fly (scatter_half).
 #include "tdbem_internal.hpp"
 
 namespace tdbem {
@@ -69,7 +69,8 @@ k_geometry(const double* __restrict__ xyz, const int32_t* __restrict__ tri, int 
 }
 
 // Band of trial indices i for the time row k and a distance range (dmin, dmax): those with
-// lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).
+// lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).  Block
+// (j chunk, l); lanes with j > l idle (lower triangle only).
 __global__ void __launch_bounds__(256)
 k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, const double* __restrict__ t,
          int N, int16_t* __restrict__ ilo, int32_t* __restrict__ Bk)
@@ -77,9 +78,10 @@ k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, 
     extern __shared__ int32_t sB[];
     for (int k = threadIdx.x; k < N; k += blockDim.x) sB[k] = 0;
     __syncthreads();
-    const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pid < (int64_t)M * M) {
-        const int l = (int)(pid / M), j = (int)(pid - (int64_t)l * M);
+    const int l = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntri = (int64_t)M * (M + 1) / 2;
+    if (j <= l) {
         const double dx = xyz[3 * l] - xyz[3 * j], dy = xyz[3 * l + 1] - xyz[3 * j + 1], dz = xyz[3 * l + 2] - xyz[3 * j + 2];
         const double d = sqrt(dx * dx + dy * dy + dz * dz);
         const double slack = 1e-12 * (1.0 + t[N - 1]);
@@ -88,14 +90,12 @@ k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, 
         dmin = dmin > 0.0 ? dmin : 0.0;
         int ia = 0, ib = -1;
         for (int k = 0; k < N; ++k) {
-            // first i with lo_{k,i} < dmax
             while (ia < N) {
                 double lo, hi;
                 kernel_support(t, N, k, ia, lo, hi);
                 if (lo < dmax) break;
                 ++ia;
             }
-            // last i with hi_{k,i} > dmin
             while (ib + 1 < N) {
                 double lo, hi;
                 kernel_support(t, N, k, ib + 1, lo, hi);
@@ -103,7 +103,7 @@ k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, 
                 ++ib;
             }
             const int first = ia < N ? ia : N - 1;
-            ilo[((int64_t)k * M + l) * M + j] = (int16_t)first;
+            ilo[(int64_t)k * ntri + tri_index(l, j)] = (int16_t)first;
             const int cnt = ib - ia + 1;
             if (cnt > 0) atomicMax(&sB[k], cnt);
         }
@@ -129,16 +129,7 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// ---------------------------------------------------------------------------------------------
-// Regular pairs.  Block = (tau, 32 consecutive sigma); a group of 8 lanes per unordered pair
-// tau < sigma without a common vertex, lane q < 7 owning the test point x_q and its 7 distances
-// to the points y_q' of sigma (lane 7 idles).  The (k, i) loop runs over the union of the bands
-// of the wave's 8 pairs (wave-uniform: kernel descriptors and interval starts are scalar loads).
-// Per (k, i) a lane forms R_b = sum_q' w_q' lam_b(q') psi(r)/r and sum_q' w_q' tpsi(r)/r; the
-// 8-lane group reduces w_q lam_a(q) R_b and the tpsi sum, and lane m writes entry (a, b) =
-// (m / 3, m % 3) (lane 0 also entry 8).  Only the half P(v_b(sigma), v_a(tau)) is added here;
-// the blocks are completed by A = P + P^T (k_symmetrize).
-// ---------------------------------------------------------------------------------------------
+// Sum over the 8 lanes of a group (one triangle pair).
 __device__ inline double group8_sum(double v)
 {
     v += __shfl_xor(v, 1, 64);
@@ -147,78 +138,139 @@ __device__ inline double group8_sum(double v)
     return v;
 }
 
+// P(l, j) += v for the half P of the assembly (A = P + P^T): in the lower-triangle storage an
+// off-diagonal contribution lands at (max, min) and a diagonal one counts twice.
 __device__ inline void scatter_half(const BandView& band, double* val, float* valf, int k, int i, int l, int j,
                                     double v)
 {
-    const int64_t M = band.M;
-    const int s = i - (int)band.ilo[((int64_t)k * M + l) * M + j];
+    if (j > l) { const int tmp = j; j = l; l = tmp; }
+    if (j == l) v *= 2.0;
+    const int s = i - (int)band.ilo[(int64_t)k * band.ntri + tri_index(l, j)];
     const int B = band.B[k];
     if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
-    const int64_t idx = band.voff[k] + ((int64_t)l * B + s) * M + j;
+    const int64_t idx = band_value_index(band, k, l, j, s, B);
     if (valf) atomicAdd(valf + idx, (float)v);
     else atomicAdd(val + idx, v);
 }
 
-__global__ void __launch_bounds__(256, 3)
-k_regular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
-          unsigned long long* counter)
+// Regular pairs, sorted-distance form.  Block = (tau, C consecutive sigma), 256 threads.  The
+// 49 C point-pair distances are computed once and sorted (bitonic, in LDS).  For every (k, i) of
+// the block's band the elements with r inside supp psi_{k,i} form one contiguous range of the
+// sorted list; lanes take consecutive elements, so the lanes of a wave read few distinct
+// Chebyshev pieces and their coefficient loads coalesce.  Results psi(r) w_q w_q'/r go to LDS in
+// element order; then a group of 8 lanes per pair (lane q < 7 owns test point x_q) contracts
+// them with the barycentric weights, R_b = sum_q' lam_b(q') P, reduces lam_a(q) R_b over the
+// group, and lane m adds entry (a, b) = (m / 3, m % 3) of the pair's 3 x 3 block (lane 0 also
+// entry 8).  Only the half P(v_b(sigma), v_a(tau)) is added; the lower-triangle storage
+// receives A = P + P^T directly (scatter_half).
+template <int C>
+__global__ void __launch_bounds__(256, 2)
+k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val,
+                 float* valf, double r_far, unsigned long long* counter)
 {
+    constexpr int NEL = C * 49;
+    constexpr int NSORT = NEL <= 512 ? 512 : (NEL <= 1024 ? 1024 : 2048);
+    static_assert(NEL <= 2048, "tile too large");
     const int E = g.E;
     const int tau = blockIdx.y;
-    if ((int)(blockIdx.x * 32 + 31) <= tau) return;   // whole block on or below the diagonal
+    const int sig0 = blockIdx.x * C;
+    if (sig0 + C - 1 <= tau) return;          // whole block on or below the diagonal (uniform)
     __shared__ PieceTable spt;
+    __shared__ double s_key[NSORT];
+    __shared__ uint16_t s_idx[NSORT];
+    __shared__ double s_winv[NEL], s_P[NEL], s_Pt[NEL];
+    __shared__ uint32_t s_stamp[NEL];
+    __shared__ double s_pmin[C], s_pmax[C];
+    const int tid = threadIdx.x;
     load_piece_table(spt, tv.pt);
-    __syncthreads();
-    const int N = tv.N;
-    const int q = threadIdx.x & 7;
-    const int sig = blockIdx.x * 32 + (threadIdx.x >> 3);
     const int tv0 = g.v[tau], tv1 = g.v[E + tau], tv2 = g.v[2 * E + tau];
-    bool pair_ok = sig > tau && sig < E;
-    int sv0 = 0, sv1 = 0, sv2 = 0;
-    if (pair_ok) {
-        sv0 = g.v[sig]; sv1 = g.v[E + sig]; sv2 = g.v[2 * E + sig];
-        if (sv0 == tv0 || sv0 == tv1 || sv0 == tv2 || sv1 == tv0 || sv1 == tv1 || sv1 == tv2 ||
-            sv2 == tv0 || sv2 == tv1 || sv2 == tv2)
-            pair_ok = false;
+    for (int e = tid; e < NSORT; e += 256) {
+        if (e < NEL) {
+            const int p = e / 49, qq = e - 49 * p, q = qq / 7, qp = qq - 7 * q;
+            const int sig = sig0 + p;
+            bool ok = sig > tau && sig < E;
+            const int sg = ok ? sig : tau;
+            if (ok) {
+                const int a0 = g.v[sg], a1 = g.v[E + sg], a2 = g.v[2 * E + sg];
+                ok = !(a0 == tv0 || a0 == tv1 || a0 == tv2 || a1 == tv0 || a1 == tv1 || a1 == tv2 || a2 == tv0 ||
+                       a2 == tv1 || a2 == tv2);
+            }
+            const double d0 = g.qp[(3 * q) * E + tau] - g.qp[(3 * qp) * E + sg];
+            const double d1 = g.qp[(3 * q + 1) * E + tau] - g.qp[(3 * qp + 1) * E + sg];
+            const double d2 = g.qp[(3 * q + 2) * E + tau] - g.qp[(3 * qp + 2) * E + sg];
+            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            double la, lb, lc, wq, wp;
+            rule7_point(q, la, lb, lc, wq);
+            rule7_point(qp, la, lb, lc, wp);
+            s_key[e] = ok ? r : INFINITY;
+            s_winv[e] = ok ? wq * wp / r : 0.0;
+            s_stamp[e] = 0xffffffffu;
+        } else {
+            s_key[e] = INFINITY;
+        }
+        s_idx[e] = (uint16_t)e;
     }
-    const int sg = pair_ok ? sig : tau;       // every lane reads valid memory
-    const int qx = q < 7 ? q : 0;
-    double lqa0, lqa1, lqa2, wq;
-    rule7_point(qx, lqa0, lqa1, lqa2, wq);
-    if (q == 7) wq = 0.0;                     // the idle lane contributes nothing
-    const double x0 = g.qp[(3 * qx) * E + tau], x1 = g.qp[(3 * qx + 1) * E + tau], x2 = g.qp[(3 * qx + 2) * E + tau];
-    double r[7], ir[7];
-    double rmin = 1e300, rmax = -1e300;
-#pragma unroll
-    for (int p = 0; p < 7; ++p) {
-        const double d0 = x0 - g.qp[(3 * p) * E + sg], d1 = x1 - g.qp[(3 * p + 1) * E + sg],
-                     d2 = x2 - g.qp[(3 * p + 2) * E + sg];
-        r[p] = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        ir[p] = 1.0 / r[p];
-        rmin = fmin(rmin, r[p]);
-        rmax = fmax(rmax, r[p]);
+    __syncthreads();
+    if (tid < C) {
+        double mn = INFINITY, mx = -INFINITY;
+        for (int u = 0; u < 49; ++u) {
+            const double r = s_key[tid * 49 + u];
+            if (r < INFINITY) { mn = fmin(mn, r); mx = fmax(mx, r); }
+        }
+        s_pmin[tid] = mn;
+        s_pmax[tid] = mx;
     }
-    const bool lane_ok = pair_ok && q < 7;
-    if (!lane_ok) { rmin = 1e300; rmax = -1e300; }
-    // pair range (group of 8) and wave union
-    double pmin = rmin, pmax = rmax;
-    for (int o = 1; o <= 4; o <<= 1) { pmin = fmin(pmin, __shfl_xor(pmin, o, 64)); pmax = fmax(pmax, __shfl_xor(pmax, o, 64)); }
-    double wmin = pmin, wmax = pmax;
-    for (int o = 8; o <= 32; o <<= 1) { wmin = fmin(wmin, __shfl_xor(wmin, o, 64)); wmax = fmax(wmax, __shfl_xor(wmax, o, 64)); }
-    if (wmax < wmin) return;                  // no pair in this wave (wave-uniform)
-
-    // the entry this lane writes: m = q (and 8 for lane 0)
-    const int ma = q / 3, mb = q % 3;
+    // bitonic sort of (s_key, s_idx) by key
+    for (int size = 2; size <= NSORT; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int u = tid; u < NSORT / 2; u += 256) {
+                const int lo = 2 * stride * (u / stride) + (u % stride);
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double ka = s_key[lo], kb = s_key[hi];
+                if ((ka > kb) == up) {
+                    s_key[lo] = kb; s_key[hi] = ka;
+                    const uint16_t ia = s_idx[lo];
+                    s_idx[lo] = s_idx[hi]; s_idx[hi] = ia;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // number of valid elements (keys below infinity)
+    int nvalid = 0;
+    {
+        int lo = 0, hi = NSORT;
+        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] < INFINITY) lo = mid + 1; else hi = mid; }
+        nvalid = lo;
+    }
+    if (nvalid == 0) return;                   // uniform: every thread computed the same value
+    const double wmin = s_key[0], wmax = s_key[nvalid - 1];
+    const int N = tv.N;
+    const int lane = tid & 63, wave = tid >> 6;
+    // contraction lanes: pair gp, test point gq (gq == 7 idles)
+    const int gp = tid >> 3, gq = tid & 7;
+    const int gsig = sig0 + gp;
+    const int gsg = (gsig < E) ? gsig : tau;
+    double lqa0, lqa1, lqa2, wdummy;
+    rule7_point(gq < 7 ? gq : 0, lqa0, lqa1, lqa2, wdummy);
+    if (gq == 7) { lqa0 = lqa1 = lqa2 = 0.0; }
+    const int ma = gq / 3, mb = gq % 3;
+    const int sv0 = g.v[gsg], sv1 = g.v[E + gsg], sv2 = g.v[2 * E + gsg];
     const int la = ma == 0 ? tv0 : (ma == 1 ? tv1 : tv2), jb = mb == 0 ? sv0 : (mb == 1 ? sv1 : sv2);
-    const double nn = g.n[tau] * g.n[sg] + g.n[E + tau] * g.n[E + sg] + g.n[2 * E + tau] * g.n[2 * E + sg];
-    const int ca = q < 7 ? ma : 2, cb = q < 7 ? mb : 1;   // lane 7 writes entry 7 = (2, 1)
-    const double Cm = g.curl[(3 * ca) * E + tau] * g.curl[(3 * cb) * E + sg] +
-                      g.curl[(3 * ca + 1) * E + tau] * g.curl[(3 * cb + 1) * E + sg] +
-                      g.curl[(3 * ca + 2) * E + tau] * g.curl[(3 * cb + 2) * E + sg];
-    const double C8 = g.curl[6 * E + tau] * g.curl[6 * E + sg] + g.curl[7 * E + tau] * g.curl[7 * E + sg] +
-                      g.curl[8 * E + tau] * g.curl[8 * E + sg];
-    const double scale = g.area[tau] * g.area[sg] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
+    const int mla = gq < 7 ? la : tv2, mjb = gq < 7 ? jb : sv1;
+    const double nn = g.n[tau] * g.n[gsg] + g.n[E + tau] * g.n[E + gsg] + g.n[2 * E + tau] * g.n[2 * E + gsg];
+    const int ca = gq < 7 ? ma : 2, cb = gq < 7 ? mb : 1;
+    const double Cm = g.curl[(3 * ca) * E + tau] * g.curl[(3 * cb) * E + gsg] +
+                      g.curl[(3 * ca + 1) * E + tau] * g.curl[(3 * cb + 1) * E + gsg] +
+                      g.curl[(3 * ca + 2) * E + tau] * g.curl[(3 * cb + 2) * E + gsg];
+    const double C8 = g.curl[6 * E + tau] * g.curl[6 * E + gsg] + g.curl[7 * E + tau] * g.curl[7 * E + gsg] +
+                      g.curl[8 * E + tau] * g.curl[8 * E + gsg];
+    const double scale = g.area[tau] * g.area[gsg] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
+    const double pmn = s_pmin[gp], pmx = s_pmax[gp];
     unsigned long long nq = 0;
+    uint32_t it = 0;
 
     int ia = 0, ib = -1;
     for (int k = 0; k < N; ++k) {
@@ -238,75 +290,104 @@ k_regular(GeomView g, TableView tv, const double* __restrict__ t, BandView band,
             const int f = tv.fid[k * N + i];
             if (f < 0) continue;
             const KernelDesc kd = tv.desc[f];
-            const bool pair_hit = pmax > kd.lo && pmin < kd.hi && pair_ok;
-            if (!__any(pair_hit)) continue;   // wave-uniform skip
-            double R0 = 0.0, R1 = 0.0, R2 = 0.0, S2 = 0.0;
-            int hits = 0;
-            if (pair_hit && q < 7) {
+            // sorted range lo < r < hi
+            int s0, s1;
+            {
+                int lo = 0, hi = nvalid;
+                while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] <= kd.lo) lo = mid + 1; else hi = mid; }
+                s0 = lo;
+                hi = nvalid;
+                while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] < kd.hi) lo = mid + 1; else hi = mid; }
+                s1 = lo;
+            }
+            if (s1 <= s0) continue;            // uniform
+            ++it;
+            const double* iv = tv.ivl + kd.bp_off;
+            for (int base = s0 + 64 * wave; base < s1; base += 256) {
+                const int s = base + lane;
+                bool active = s < s1;
+                const double r = active ? s_key[s] : kd.lo;
+                int code = -1;
+                double x = 0.0;
+                if (active) {
+                    int j = 0;
+                    for (int m = 1; m < kd.nint; ++m) j += r >= iv[2 * m] ? 1 : 0;
+                    double fr = (r - iv[2 * j]) * iv[2 * j + 1];
+                    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+                    int cell = (int)(fr * kLutCells);
+                    cell = cell < kLutCells ? cell : kLutCells - 1;
+                    int p = spt.lut[cell];
+                    if (p + 1 < kPieces && fr >= spt.edge[p + 1]) ++p;
+                    x = 2.0 * (fr - spt.edge[p]) * spt.inv_width[p] - 1.0;
+                    code = j * kPieces + p;
+                }
+                if (active) {
+                    // lanes hold consecutive distances, so neighbouring lanes mostly read the
+                    // same piece: the per-lane loads coalesce into few cache lines.  Mixed
+                    // precision: far-field distances (r >= r_far) on the middle (uniform) pieces
+                    // evaluate the FP32 copy of the series; pieces graded towards a breakpoint
+                    // (the flat support edges) stay in FP64.
+                    double ps, pt;
+                    const int pc = code % kPieces;
+                    if (r >= r_far && pc >= kPieces / 2 - 3 && pc < kPieces / 2 + 3) {
+                        float fps, fpt;
+                        clenshaw2_f32(tv.coef32 + kd.coef_off + (int64_t)code * kNc, (float)x, fps, fpt);
+                        ps = fps;
+                        pt = fpt;
+                    } else {
+                        clenshaw2(tv.coef + kd.coef_off + (int64_t)code * kNc, x, ps, pt);
+                    }
+                    const int e = s_idx[s];
+                    const double w = s_winv[e];
+                    s_P[e] = ps * w;
+                    s_Pt[e] = pt * w;
+                    s_stamp[e] = it;
+                    ++nq;
+                }
+            }
+            __syncthreads();
+            const bool pair_hit = pmx > kd.lo && pmn < kd.hi;
+            double R0 = 0.0, R1 = 0.0, R2 = 0.0, T = 0.0;
+            if (pair_hit && gq < 7) {
+                const int e0 = gp * 49 + gq * 7;
 #pragma unroll
                 for (int p = 0; p < 7; ++p) {
                     double lb0, lb1, lb2, wp;
                     rule7_point(p, lb0, lb1, lb2, wp);
-                    double ps, pt;
-                    if (table_eval(kd, tv.ivl, tv.coef, spt, r[p], ps, pt)) {
-                        ++hits;
-                        const double c = wp * ir[p];
-                        const double f1 = ps * c;
-                        R0 = fma(f1, lb0, R0);
-                        R1 = fma(f1, lb1, R1);
-                        R2 = fma(f1, lb2, R2);
-                        S2 = fma(c, pt, S2);
+                    if (s_stamp[e0 + p] == it) {
+                        const double P = s_P[e0 + p];
+                        R0 = fma(P, lb0, R0);
+                        R1 = fma(P, lb1, R1);
+                        R2 = fma(P, lb2, R2);
+                        T += s_Pt[e0 + p];
                     }
                 }
             }
-            nq += hits;
-            // group reduction of w_q lam_a(q) R_b (a, b) and w_q S2
-            const double s00 = group8_sum(wq * lqa0 * R0), s01 = group8_sum(wq * lqa0 * R1), s02 = group8_sum(wq * lqa0 * R2);
-            const double s10 = group8_sum(wq * lqa1 * R0), s11 = group8_sum(wq * lqa1 * R1), s12 = group8_sum(wq * lqa1 * R2);
-            const double s20 = group8_sum(wq * lqa2 * R0), s21 = group8_sum(wq * lqa2 * R1), s22 = group8_sum(wq * lqa2 * R2);
-            const double sS2 = group8_sum(wq * S2);
-            if (!pair_hit) continue;
-            double Sm;
-            switch (q) {
-            case 0: Sm = s00; break;
-            case 1: Sm = s01; break;
-            case 2: Sm = s02; break;
-            case 3: Sm = s10; break;
-            case 4: Sm = s11; break;
-            case 5: Sm = s12; break;
-            case 6: Sm = s20; break;
-            default: Sm = s21; break;
+            // reduce lam_a(q) R_b and T over the 8 lanes of the pair (lam includes w_q via s_winv)
+            const double s00 = group8_sum(lqa0 * R0), s01 = group8_sum(lqa0 * R1), s02 = group8_sum(lqa0 * R2);
+            const double s10 = group8_sum(lqa1 * R0), s11 = group8_sum(lqa1 * R1), s12 = group8_sum(lqa1 * R2);
+            const double s20 = group8_sum(lqa2 * R0), s21 = group8_sum(lqa2 * R1), s22 = group8_sum(lqa2 * R2);
+            const double sT = group8_sum(gq < 7 ? T : 0.0);
+            if (pair_hit && gsig < E) {
+                double Sm;
+                switch (gq) {
+                case 0: Sm = s00; break;
+                case 1: Sm = s01; break;
+                case 2: Sm = s02; break;
+                case 3: Sm = s10; break;
+                case 4: Sm = s11; break;
+                case 5: Sm = s12; break;
+                case 6: Sm = s20; break;
+                default: Sm = s21; break;
+                }
+                scatter_half(band, val, valf, k, i, mla, mjb, (nn * Sm + Cm * sT) * scale);
+                if (gq == 0) scatter_half(band, val, valf, k, i, tv2, sv2, (nn * s22 + C8 * sT) * scale);
             }
-            const int mla = q < 7 ? la : tv2, mjb = q < 7 ? jb : sv1;
-            scatter_half(band, val, valf, k, i, mla, mjb, (nn * Sm + Cm * sS2) * scale);
-            if (q == 0) scatter_half(band, val, valf, k, i, tv2, sv2, (nn * s22 + C8 * sS2) * scale);
+            __syncthreads();
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
-    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(counter, tot);
-}
-
-// A = P + P^T on the band storage: entry (k, l, s, j) and its transpose (k, j, s, l) share the
-// band slot because ilo is symmetric in (l, j).  One lane per (k, l, j) with j <= l.
-template <typename VT>
-__global__ void __launch_bounds__(256)
-k_symmetrize(BandView band, VT* __restrict__ val)
-{
-    const int64_t M = band.M;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (gid >= M * M) return;
-    const int l = (int)(gid / M), j = (int)(gid - (int64_t)l * M);
-    if (j > l) return;
-    const int B = band.B[k];
-    VT* base = val + band.voff[k];
-    for (int s = 0; s < B; ++s) {
-        VT* a = base + ((int64_t)l * B + s) * M + j;
-        VT* b = base + ((int64_t)j * B + s) * M + l;
-        const VT v = *a + *b;
-        *a = v;
-        *b = v;
-    }
+    if (lane == 0 && tot) atomicAdd(counter, tot);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -469,14 +550,15 @@ k_get_entries(BandView band, const double* __restrict__ val, const float* __rest
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int kk = k[s], ii = i[s], jj = j[s], ll = l[s];
+    const int kk = k[s], ii = i[s];
+    int jj = j[s], ll = l[s];
+    if (jj > ll) { const int tmp = jj; jj = ll; ll = tmp; }   // symmetric blocks: lower triangle
     double v = 0.0;
-    if (kk >= 0 && kk < band.N && ii >= 0 && ii < band.N && jj >= 0 && jj < band.M && ll >= 0 && ll < band.M) {
-        const int64_t M = band.M;
+    if (kk >= 0 && kk < band.N && ii >= 0 && ii < band.N && jj >= 0 && ll < band.M) {
         const int B = band.B[kk];
-        const int sl = ii - (int)band.ilo[((int64_t)kk * M + ll) * M + jj];
+        const int sl = ii - (int)band.ilo[(int64_t)kk * band.ntri + tri_index(ll, jj)];
         if (sl >= 0 && sl < B) {
-            const int64_t idx = band.voff[kk] + ((int64_t)ll * B + sl) * M + jj;
+            const int64_t idx = band_value_index(band, kk, ll, jj, sl, B);
             v = valf ? (double)valf[idx] : val[idx];
         }
     }
@@ -495,23 +577,16 @@ void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P
 void launch_layout(const double* xyz, const double* rho, int M, const double* t, int N, int16_t* ilo, int32_t* Bk,
                    hipStream_t s)
 {
-    const int64_t n = (int64_t)M * M;
-    hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 256)), dim3(256), sizeof(int32_t) * N, s, xyz, rho, M, t, N, ilo,
+    hipLaunchKernelGGL(k_layout, dim3(grid_for(M, 256), M), dim3(256), sizeof(int32_t) * N, s, xyz, rho, M, t, N, ilo,
                        Bk);
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    unsigned long long* counter, hipStream_t s)
+                    double r_far, unsigned long long* counter, hipStream_t s)
 {
-    dim3 grid(grid_for(g.E, 32), g.E);
-    hipLaunchKernelGGL(k_regular, grid, dim3(256), 0, s, g, tv, t, band, val, valf, counter);
-}
-
-void launch_symmetrize(BandView band, double* val, float* valf, hipStream_t s)
-{
-    dim3 grid(grid_for((int64_t)band.M * band.M, 256), band.N);
-    if (valf) hipLaunchKernelGGL(k_symmetrize<float>, grid, dim3(256), 0, s, band, valf);
-    else hipLaunchKernelGGL(k_symmetrize<double>, grid, dim3(256), 0, s, band, val);
+    constexpr int C = 32;
+    dim3 grid(grid_for(g.E, C), g.E);
+    hipLaunchKernelGGL(k_regular_sorted<C>, grid, dim3(256), 0, s, g, tv, t, band, val, valf, r_far, counter);
 }
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,

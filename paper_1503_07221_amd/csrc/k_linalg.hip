@@ -75,32 +75,69 @@ k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, d
     atomicAdd(gvec + (int64_t)k * M + g.v[2 * E + e], acc2);
 }
 
-// y[(k-k0)*M + l] = sum_j sum_s A_{k, ilo+s}(j, l) x[(ilo+s-i0)*M + j] over i0 <= ilo+s < i1:
-// one wave per row (k, l), lanes stride over j (coalesced values and band starts).
+// xt[j*ni + ii] = x[ii*M + j]: trial vector with the time index fastest, so that the band of one
+// vertex is contiguous.
+__global__ void __launch_bounds__(256)
+k_transpose_in(const double* __restrict__ x, int M, int ni, double* __restrict__ xt)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= (int64_t)M * ni) return;
+    const int ii = (int)(s / M), j = (int)(s - (int64_t)ii * M);
+    xt[(int64_t)j * ni + ii] = x[s];
+}
+
+// y = A[k0:k1, i0:i1] x on the lower-triangle band storage.  Block = one 64 x 64 tile (rows l,
+// columns j <= l) of one time row k; wave w takes rows l = 64 tl + w + 4m, lanes the columns.
+// A stored entry (l, j) serves y_k(l) += A x_i(j) and, off the diagonal, y_k(j) += A x_i(l)
+// (block symmetry); rows are reduced per wave, columns over the block, both added atomically
+// into y (zeroed before).
 template <typename VT>
 __global__ void __launch_bounds__(256)
-k_matvec(BandView band, const VT* __restrict__ val, int k0, int k1, int i0, int i1, const double* __restrict__ x,
-         double* __restrict__ y)
+k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, const double* __restrict__ xt,
+             double* __restrict__ y)
 {
     const int M = band.M;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= (int64_t)(k1 - k0) * M) return;
-    const int k = k0 + (int)(row / M);
-    const int l = (int)(row - (int64_t)(k - k0) * M);
+    const int k = k0 + blockIdx.y;
+    const int t = blockIdx.x;
+    int tl = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((tl + 1) * (tl + 2) / 2 <= t) ++tl;
+    while (tl * (tl + 1) / 2 > t) --tl;
+    const int tj = t - tl * (tl + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = tj * 64 + lane;
+    const int ni = i1 - i0;
     const int B = band.B[k];
-    const VT* __restrict__ v = val + band.voff[k] + (int64_t)l * B * M;
-    const int16_t* __restrict__ il = band.ilo + ((int64_t)k * M + l) * M;
-    double acc = 0.0;
-    for (int j = lane; j < M; j += 64) {
-        const int ib = il[j];
-        for (int s = 0; s < B; ++s) {
-            const int i = ib + s;
-            if (i >= i0 && i < i1) acc = fma((double)v[(int64_t)s * M + j], x[(int64_t)(i - i0) * M + j], acc);
+    const int64_t voff = band.voff[k];
+    const int16_t* __restrict__ il = band.ilo + (int64_t)k * band.ntri;
+    double* __restrict__ yk = y + (int64_t)(k - k0) * M;
+    double col = 0.0;
+    for (int m = 0; m < 16; ++m) {
+        const int l = tl * 64 + wave + 4 * m;
+        double row = 0.0;
+        if (l < M && j <= l) {
+            const int ib = il[tri_index(l, j)];
+            const VT* __restrict__ v = val + voff + (int64_t)B * tri_index(l, 0) + j;
+            const double* __restrict__ xj = xt + (int64_t)j * ni - i0;
+            const double* __restrict__ xl = xt + (int64_t)l * ni - i0;
+            for (int s = 0; s < B; ++s) {
+                const int i = ib + s;
+                if (i >= i0 && i < i1) {
+                    const double a = (double)v[(int64_t)s * (l + 1)];
+                    row = fma(a, xj[i], row);
+                    if (j < l) col = fma(a, xl[i], col);
+                }
+            }
         }
+        for (int o = 32; o >= 1; o >>= 1) row += __shfl_xor(row, o, 64);
+        if (lane == 0 && l < M && row != 0.0) atomicAdd(yk + l, row);
     }
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) y[row] = acc;
+    __shared__ double s_col[4][64];
+    s_col[wave][lane] = col;
+    __syncthreads();
+    if (wave == 0 && j < M) {
+        const double c = s_col[0][lane] + s_col[1][lane] + s_col[2][lane] + s_col[3][lane];
+        if (c != 0.0) atomicAdd(yk + j, c);
+    }
 }
 
 // Partial dot products of w with nvec vectors V[q*ld + .]: block (b, q) sums its chunk.
@@ -194,14 +231,20 @@ void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, doub
 }
 
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
-                   const double* x, double* y, hipStream_t s)
+                   const double* x, double* y, double* xt, hipStream_t s)
 {
-    const int64_t rows = (int64_t)(k1 - k0) * band.M;
+    const int64_t M = band.M;
+    const int64_t rows = (int64_t)(k1 - k0) * M;
     if (rows <= 0) return;
+    const int ni = i1 - i0;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(rows, 256)), dim3(256), 0, s, y, 0.0, rows);
+    hipLaunchKernelGGL(k_transpose_in, dim3(grid_for(M * ni, 256)), dim3(256), 0, s, x, (int)M, ni, xt);
+    const int T = (int)((M + 63) / 64);
+    dim3 grid(T * (T + 1) / 2, k1 - k0);
     if (valf)
-        hipLaunchKernelGGL(k_matvec<float>, dim3(grid_for(rows, 4)), dim3(256), 0, s, band, valf, k0, k1, i0, i1, x, y);
+        hipLaunchKernelGGL(k_matvec_tri<float>, grid, dim3(256), 0, s, band, valf, k0, i0, i1, xt, y);
     else
-        hipLaunchKernelGGL(k_matvec<double>, dim3(grid_for(rows, 4)), dim3(256), 0, s, band, val, k0, k1, i0, i1, x, y);
+        hipLaunchKernelGGL(k_matvec_tri<double>, grid, dim3(256), 0, s, band, val, k0, i0, i1, xt, y);
 }
 
 int dots_partial_blocks(int64_t n) { return (int)((n + kDotChunk - 1) / kDotChunk); }

@@ -147,9 +147,27 @@ struct TableView {
     const int32_t* fid;       // fid[k*N + i]: index into desc or -1 (identically zero kernel)
     const double* ivl;        // interval starts and inverse lengths
     const double2* coef;      // Chebyshev coefficients (psi, tpsi)
+    const float2* coef32;     // the same rounded to FP32 (mixed precision far field)
     int32_t N;
     PieceTable pt;
 };
+
+// Clenshaw in FP32 for the mixed-precision far field.
+__device__ inline void clenshaw2_f32(const float2* __restrict__ c, float x, float& ps, float& pt)
+{
+    const float x2 = 2.0f * x;
+    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+    for (int m = kDeg; m >= 1; --m) {
+        const float2 cm = c[m];
+        const float a0 = fmaf(x2, a1, cm.x - a2);
+        const float b0 = fmaf(x2, b1, cm.y - b2);
+        a2 = a1; a1 = a0; b2 = b1; b1 = b0;
+    }
+    const float2 c0 = c[0];
+    ps = fmaf(x, a1, c0.x - a2);
+    pt = fmaf(x, b1, c0.y - b2);
+}
 
 // Gauss-Legendre rule on [-1, 1] used for every time integral of the library.
 constexpr int kTimeGauss = 20;
@@ -204,16 +222,25 @@ struct GeomView {
     int32_t E;
 };
 
-// Band storage of the blocks: for every ordered vertex pair (l, j) and time row k, the
-// trial indices i = ilo[k][l][j] + s, s < B_k, that can be non-zero
-// (eq. (SparsitySmallBlock) with conservative patch distances), values at
-// val[voff[k] + (l*B_k + s)*M + j].
+// Band storage of the blocks.  Every block is symmetric in (j, l), so only the lower triangle
+// j <= l is kept.  For every vertex pair (l, j <= l) and time row k the trial indices
+// i = ilo[k][(l, j)] + s, s < B_k, are those whose kernel support meets the conservative distance
+// range of the two hats (eq. (SparsitySmallBlock)); the values of row l are stored slot-major,
+// val[voff[k] + B_k * l(l+1)/2 + s*(l+1) + j], so a wave reads one slot of a row coalesced.
+__host__ __device__ inline int64_t tri_index(int64_t l, int64_t j) { return l * (l + 1) / 2 + j; }
+
 struct BandView {
-    const int16_t* ilo;    // ilo[(k*M + l)*M + j]
+    const int16_t* ilo;    // ilo[k*ntri + tri_index(l, j)], j <= l
     const int32_t* B;      // B[k]
     const int64_t* voff;   // voff[k]
     int32_t M, N;
+    int64_t ntri;          // M (M + 1) / 2
 };
+
+__device__ inline int64_t band_value_index(const BandView& b, int k, int64_t l, int64_t j, int s, int B)
+{
+    return b.voff[k] + (int64_t)B * tri_index(l, 0) + (int64_t)s * (l + 1) + j;
+}
 
 }  // namespace tdbem
 
@@ -225,7 +252,7 @@ void launch_table_values(const double* t, int N, int cut, TimeRule rule, PieceTa
                          const int32_t* pc_j, const int32_t* pc_p, int64_t npieces, const int32_t* f_k,
                          const int32_t* f_i, const KernelDesc* desc, const double* ivl, double2* values,
                          hipStream_t s);
-void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, hipStream_t s);
+void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, float2* coef32, hipStream_t s);
 void launch_table_eval(TableView tv, int64_t n, const int32_t* k, const int32_t* i, const double* r,
                        double* ps, double* tps, hipStream_t s);
 
@@ -235,8 +262,7 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
                    int32_t* Bk, hipStream_t s);
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    unsigned long long* counter, hipStream_t s);
-void launch_symmetrize(BandView band, double* val, float* valf, hipStream_t s);
+                    double r_far, unsigned long long* counter, hipStream_t s);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      double* val, float* valf, unsigned long long* counter, hipStream_t s);
@@ -246,7 +272,7 @@ void launch_get_entries(BandView band, const double* val, const float* valf, int
 void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
                 double t0, double width, int M, double* gvec, hipStream_t s);
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
-                   const double* x, double* y, hipStream_t s);
+                   const double* x, double* y, double* xt, hipStream_t s);
 
 void launch_dots(const double* V, int nvec, int64_t n, int64_t ld, const double* w, double* partial,
                  double* out, hipStream_t s);
