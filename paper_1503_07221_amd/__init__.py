@@ -69,6 +69,10 @@ def load_library(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime; loading it first makes libtdbem resolve to the same
+    # runtime (one HIP runtime per process), so that torch's device memory and streams are valid
+    # handles for the library.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"libtdbem.so not found at {path}; run __graft_entry__.build() first")
     L = ctypes.CDLL(path)

@@ -168,7 +168,7 @@ struct tdbem_ctx {
     double hmax = 0.0;   // longest triangle edge
     int64_t nfunc = 0;
     // band storage
-    DBuf d_ilo, d_B, d_voff, d_val, d_counter, d_xt;
+    DBuf d_ilo, d_B, d_voff, d_val, d_counter;
     std::vector<int32_t> Bk;
     std::vector<int64_t> voff;
     int64_t nvals = 0;
@@ -586,7 +586,6 @@ static tdbem_status build_layout(tdbem_ctx* c, int prec)
     }
     ALLOC(c, c->d_val, need);
     HIPCHK(c, hipMemsetAsync(c->d_val.p, 0, need, c->stream));
-    ALLOC(c, c->d_xt, sizeof(double) * (size_t)(M * N));
     return TDBEM_OK;
 }
 
@@ -714,7 +713,7 @@ tdbem_status tdbem_rhs_plane_pulse(tdbem_ctx* c, const double d[3], double t0, d
 
 static tdbem_status matvec_range(tdbem_ctx* c, int k0, int k1, int i0, int i1, const double* x, double* y)
 {
-    launch_matvec(c->band(), c->valf64(), c->valf32(), k0, k1, i0, i1, x, y, c->d_xt.as<double>(), c->stream);
+    launch_matvec(c->band(), c->valf64(), c->valf32(), k0, k1, i0, i1, x, y, c->stream);
     HIPCHK(c, hipGetLastError());
     ++c->matvecs;
     return TDBEM_OK;

@@ -153,39 +153,105 @@ __device__ inline void scatter_half(const BandView& band, double* val, float* va
     else atomicAdd(val + idx, v);
 }
 
-// Regular pairs, sorted-distance form.  Block = (tau, C consecutive sigma), 256 threads.  The
-// 49 C point-pair distances are computed once and sorted (bitonic, in LDS).  For every (k, i) of
-// the block's band the elements with r inside supp psi_{k,i} form one contiguous range of the
-// sorted list; lanes take consecutive elements, so the lanes of a wave read few distinct
-// Chebyshev pieces and their coefficient loads coalesce.  Results psi(r) w_q w_q'/r go to LDS in
-// element order; then a group of 8 lanes per pair (lane q < 7 owns test point x_q) contracts
-// them with the barycentric weights, R_b = sum_q' lam_b(q') P, reduces lam_a(q) R_b over the
-// group, and lane m adds entry (a, b) = (m / 3, m % 3) of the pair's 3 x 3 block (lane 0 also
-// entry 8).  Only the half P(v_b(sigma), v_a(tau)) is added; the lower-triangle storage
-// receives A = P + P^T directly (scatter_half).
-template <int C>
-__global__ void __launch_bounds__(256, 2)
-k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val,
-                 float* valf, double r_far, unsigned long long* counter)
+// Number of keys of the ascending array key[0..n) below v (key < v, or key <= v when le): the
+// 64 lanes sample evenly spaced keys and the ballot narrows the range (2 rounds for n <= 4096).
+// Every lane returns the same value.
+__device__ inline int wave_count_below(const double* key, int n, double v, bool le)
 {
-    constexpr int NEL = C * 49;
-    constexpr int NSORT = NEL <= 512 ? 512 : (NEL <= 1024 ? 1024 : 2048);
-    static_assert(NEL <= 2048, "tile too large");
+    const int lane = threadIdx.x & 63;
+    int base = 0, len = n;
+    while (len > 64) {
+        const int step = (len + 63) / 64;
+        const int p = base + lane * step;
+        const bool below = p < base + len && (le ? key[p] <= v : key[p] < v);
+        const int cnt = __popcll(__ballot(below));
+        if (cnt == 0) return base;
+        const int lo = base + (cnt - 1) * step + 1;
+        const int hi = base + cnt * step < base + len ? base + cnt * step : base + len;
+        base = lo;
+        len = hi - lo;
+    }
+    const bool below = lane < len && (le ? key[base + lane] <= v : key[base + lane] < v);
+    return base + __popcll(__ballot(below));
+}
+
+// One sorted element of the support range: locate its piece, evaluate both series and store
+// psi(r) w_q w_q'/r and tpsi(r) w_q w_q'/r at the element's own index.
+__device__ inline void eval_sorted_element(const KernelDesc& kd, const double* __restrict__ iv, const TableView& tv,
+                                           const PieceTable& spt, double r, int e, double w, double r_far,
+                                           double* s_P, double* s_Pt)
+{
+    int j = 0;
+    for (int m = 1; m < kd.nint; ++m) j += r >= iv[2 * m] ? 1 : 0;
+    double fr = (r - iv[2 * j]) * iv[2 * j + 1];
+    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    int cell = (int)(fr * kLutCells);
+    cell = cell < kLutCells ? cell : kLutCells - 1;
+    int p = spt.lut[cell];
+    if (p + 1 < kPieces && fr >= spt.edge[p + 1]) ++p;
+    const double x = 2.0 * (fr - spt.edge[p]) * spt.inv_width[p] - 1.0;
+    const int64_t off = kd.coef_off + (int64_t)(j * kPieces + p) * kNc;
+    double ps, pt;
+    // mixed precision: far-field distances on the middle pieces (away from the flat support
+    // edges) evaluate the FP32 copy of the series
+    if (r >= r_far && p >= kPieces / 2 - 3 && p < kPieces / 2 + 3) {
+        float fps, fpt;
+        clenshaw2_f32(tv.coef32 + off, (float)x, fps, fpt);
+        ps = fps;
+        pt = fpt;
+    } else {
+        clenshaw2(tv.coef + off, x, ps, pt);
+    }
+    s_P[e] = ps * w;
+    s_Pt[e] = pt * w;
+}
+
+// Wave-scope ordering of LDS accesses between lanes of one wave (no block barrier).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Regular pairs, wave-independent sorted form.  Every wave owns 8 consecutive sigma of one tau
+// (392 point pairs), sorts their distances once in its own LDS region, and then runs the
+// (k, i) loop on its own: the point pairs inside supp psi_{k,i} are one contiguous range of the
+// sorted list, consecutive lanes take consecutive distances (their Chebyshev pieces mostly
+// coincide, so the coefficient loads coalesce), the values psi(r) w_q w_q'/r go to LDS in
+// element order, and the 8 lanes of each pair (lane q < 7 owns test point x_q) contract them with
+// the barycentric weights, reduce lam_a(q) R_b over the group and add entry (a, b) = (m/3, m%3)
+// of the pair's 3 x 3 block (lane 0 also entry 8).  Only the half P(v_b(sigma), v_a(tau)) is
+// added; the lower-triangle storage receives A = P + P^T directly (scatter_half).  No block
+// barrier is taken inside the loop, so the waves of a CU hide each other's latencies.
+constexpr int kWavePairs = 8;
+constexpr int kWaveEl = kWavePairs * 49;     // 392
+constexpr int kWaveSort = 512;
+struct WaveLds {
+    double key[kWaveSort];
+    uint16_t idx[kWaveSort];
+    double winv[kWaveEl];
+    double P[kWaveEl];
+    double Pt[kWaveEl];
+    double pmin[kWavePairs], pmax[kWavePairs];
+};
+
+__global__ void __launch_bounds__(64)
+k_regular_wave(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
+               double r_far, unsigned long long* counter)
+{
     const int E = g.E;
     const int tau = blockIdx.y;
-    const int sig0 = blockIdx.x * C;
-    if (sig0 + C - 1 <= tau) return;          // whole block on or below the diagonal (uniform)
+    const int lane = threadIdx.x;
+    const int sig0 = blockIdx.x * kWavePairs;
+    if (sig0 + kWavePairs - 1 <= tau) return;            // all sigma <= tau (block = one wave)
     __shared__ PieceTable spt;
-    __shared__ double s_key[NSORT];
-    __shared__ uint16_t s_idx[NSORT];
-    __shared__ double s_winv[NEL], s_P[NEL], s_Pt[NEL];
-    __shared__ uint32_t s_stamp[NEL];
-    __shared__ double s_pmin[C], s_pmax[C];
-    const int tid = threadIdx.x;
+    __shared__ WaveLds L;
     load_piece_table(spt, tv.pt);
+    __syncthreads();
     const int tv0 = g.v[tau], tv1 = g.v[E + tau], tv2 = g.v[2 * E + tau];
-    for (int e = tid; e < NSORT; e += 256) {
-        if (e < NEL) {
+    for (int e = lane; e < kWaveSort; e += 64) {
+        if (e < kWaveEl) {
             const int p = e / 49, qq = e - 49 * p, q = qq / 7, qp = qq - 7 * q;
             const int sig = sig0 + p;
             bool ok = sig > tau && sig < E;
@@ -202,55 +268,49 @@ k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandVie
             double la, lb, lc, wq, wp;
             rule7_point(q, la, lb, lc, wq);
             rule7_point(qp, la, lb, lc, wp);
-            s_key[e] = ok ? r : INFINITY;
-            s_winv[e] = ok ? wq * wp / r : 0.0;
-            s_stamp[e] = 0xffffffffu;
+            L.key[e] = ok ? r : INFINITY;
+            L.winv[e] = ok ? wq * wp / r : 0.0;
+            L.P[e] = 0.0;
+            L.Pt[e] = 0.0;
         } else {
-            s_key[e] = INFINITY;
+            L.key[e] = INFINITY;
         }
-        s_idx[e] = (uint16_t)e;
+        L.idx[e] = (uint16_t)e;
     }
-    __syncthreads();
-    if (tid < C) {
+    wave_sync();
+    if (lane < kWavePairs) {
         double mn = INFINITY, mx = -INFINITY;
         for (int u = 0; u < 49; ++u) {
-            const double r = s_key[tid * 49 + u];
+            const double r = L.key[lane * 49 + u];
             if (r < INFINITY) { mn = fmin(mn, r); mx = fmax(mx, r); }
         }
-        s_pmin[tid] = mn;
-        s_pmax[tid] = mx;
+        L.pmin[lane] = mn;
+        L.pmax[lane] = mx;
     }
-    // bitonic sort of (s_key, s_idx) by key
-    for (int size = 2; size <= NSORT; size <<= 1) {
+    // bitonic sort of (key, idx) inside the wave
+    for (int size = 2; size <= kWaveSort; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int u = tid; u < NSORT / 2; u += 256) {
+            wave_sync();
+            for (int u = lane; u < kWaveSort / 2; u += 64) {
                 const int lo = 2 * stride * (u / stride) + (u % stride);
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
-                const double ka = s_key[lo], kb = s_key[hi];
+                const double ka = L.key[lo], kb = L.key[hi];
                 if ((ka > kb) == up) {
-                    s_key[lo] = kb; s_key[hi] = ka;
-                    const uint16_t ia = s_idx[lo];
-                    s_idx[lo] = s_idx[hi]; s_idx[hi] = ia;
+                    L.key[lo] = kb; L.key[hi] = ka;
+                    const uint16_t ia = L.idx[lo];
+                    L.idx[lo] = L.idx[hi]; L.idx[hi] = ia;
                 }
             }
         }
     }
-    __syncthreads();
-    // number of valid elements (keys below infinity)
-    int nvalid = 0;
-    {
-        int lo = 0, hi = NSORT;
-        while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] < INFINITY) lo = mid + 1; else hi = mid; }
-        nvalid = lo;
-    }
-    if (nvalid == 0) return;                   // uniform: every thread computed the same value
-    const double wmin = s_key[0], wmax = s_key[nvalid - 1];
+    wave_sync();
+    const int nvalid = wave_count_below(L.key, kWaveSort, INFINITY, false);
+    if (nvalid == 0) return;
+    const double wmin = L.key[0], wmax = L.key[nvalid - 1];
     const int N = tv.N;
-    const int lane = tid & 63, wave = tid >> 6;
     // contraction lanes: pair gp, test point gq (gq == 7 idles)
-    const int gp = tid >> 3, gq = tid & 7;
+    const int gp = lane >> 3, gq = lane & 7;
     const int gsig = sig0 + gp;
     const int gsg = (gsig < E) ? gsig : tau;
     double lqa0, lqa1, lqa2, wdummy;
@@ -268,9 +328,10 @@ k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandVie
     const double C8 = g.curl[6 * E + tau] * g.curl[6 * E + gsg] + g.curl[7 * E + tau] * g.curl[7 * E + gsg] +
                       g.curl[8 * E + tau] * g.curl[8 * E + gsg];
     const double scale = g.area[tau] * g.area[gsg] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
-    const double pmn = s_pmin[gp], pmx = s_pmax[gp];
+    const double pmn = L.pmin[gp], pmx = L.pmax[gp];
+    const bool pair_valid = pmx >= pmn;
     unsigned long long nq = 0;
-    uint32_t it = 0;
+    int prev0 = 0, prev1 = 0;                 // sorted range written for the previous (k, i)
 
     int ia = 0, ib = -1;
     for (int k = 0; k < N; ++k) {
@@ -290,63 +351,31 @@ k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandVie
             const int f = tv.fid[k * N + i];
             if (f < 0) continue;
             const KernelDesc kd = tv.desc[f];
-            // sorted range lo < r < hi
-            int s0, s1;
-            {
-                int lo = 0, hi = nvalid;
-                while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] <= kd.lo) lo = mid + 1; else hi = mid; }
-                s0 = lo;
-                hi = nvalid;
-                while (lo < hi) { const int mid = (lo + hi) >> 1; if (s_key[mid] < kd.hi) lo = mid + 1; else hi = mid; }
-                s1 = lo;
-            }
-            if (s1 <= s0) continue;            // uniform
-            ++it;
+            const int s0 = wave_count_below(L.key, nvalid, kd.lo, true);    // first r > lo
+            const int s1 = wave_count_below(L.key, nvalid, kd.hi, false);   // first r >= hi
+            if (s1 <= s0) continue;
+            // the previous range's values outside the new range become zeros
+            const int z0 = prev0 < s0 ? prev0 : s0, z1 = prev1 > s1 ? prev1 : s1;
+            for (int s = z0 + lane; s < z1; s += 64)
+                if (s < s0 || s >= s1) { const int e = L.idx[s]; L.P[e] = 0.0; L.Pt[e] = 0.0; }
+            prev0 = s0;
+            prev1 = s1;
             const double* iv = tv.ivl + kd.bp_off;
-            for (int base = s0 + 64 * wave; base < s1; base += 256) {
-                const int s = base + lane;
-                bool active = s < s1;
-                const double r = active ? s_key[s] : kd.lo;
-                int code = -1;
-                double x = 0.0;
-                if (active) {
-                    int j = 0;
-                    for (int m = 1; m < kd.nint; ++m) j += r >= iv[2 * m] ? 1 : 0;
-                    double fr = (r - iv[2 * j]) * iv[2 * j + 1];
-                    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-                    int cell = (int)(fr * kLutCells);
-                    cell = cell < kLutCells ? cell : kLutCells - 1;
-                    int p = spt.lut[cell];
-                    if (p + 1 < kPieces && fr >= spt.edge[p + 1]) ++p;
-                    x = 2.0 * (fr - spt.edge[p]) * spt.inv_width[p] - 1.0;
-                    code = j * kPieces + p;
+            for (int base = s0; base < s1; base += 128) {
+                const int sa = base + lane, sb = base + 64 + lane;
+                if (sa < s1) {
+                    const int e = L.idx[sa];
+                    eval_sorted_element(kd, iv, tv, spt, L.key[sa], e, L.winv[e], r_far, L.P, L.Pt);
+                    ++nq;
                 }
-                if (active) {
-                    // lanes hold consecutive distances, so neighbouring lanes mostly read the
-                    // same piece: the per-lane loads coalesce into few cache lines.  Mixed
-                    // precision: far-field distances (r >= r_far) on the middle (uniform) pieces
-                    // evaluate the FP32 copy of the series; pieces graded towards a breakpoint
-                    // (the flat support edges) stay in FP64.
-                    double ps, pt;
-                    const int pc = code % kPieces;
-                    if (r >= r_far && pc >= kPieces / 2 - 3 && pc < kPieces / 2 + 3) {
-                        float fps, fpt;
-                        clenshaw2_f32(tv.coef32 + kd.coef_off + (int64_t)code * kNc, (float)x, fps, fpt);
-                        ps = fps;
-                        pt = fpt;
-                    } else {
-                        clenshaw2(tv.coef + kd.coef_off + (int64_t)code * kNc, x, ps, pt);
-                    }
-                    const int e = s_idx[s];
-                    const double w = s_winv[e];
-                    s_P[e] = ps * w;
-                    s_Pt[e] = pt * w;
-                    s_stamp[e] = it;
+                if (sb < s1) {
+                    const int e = L.idx[sb];
+                    eval_sorted_element(kd, iv, tv, spt, L.key[sb], e, L.winv[e], r_far, L.P, L.Pt);
                     ++nq;
                 }
             }
-            __syncthreads();
-            const bool pair_hit = pmx > kd.lo && pmn < kd.hi;
+            wave_sync();
+            const bool pair_hit = pair_valid && pmx > kd.lo && pmn < kd.hi;
             double R0 = 0.0, R1 = 0.0, R2 = 0.0, T = 0.0;
             if (pair_hit && gq < 7) {
                 const int e0 = gp * 49 + gq * 7;
@@ -354,21 +383,18 @@ k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandVie
                 for (int p = 0; p < 7; ++p) {
                     double lb0, lb1, lb2, wp;
                     rule7_point(p, lb0, lb1, lb2, wp);
-                    if (s_stamp[e0 + p] == it) {
-                        const double P = s_P[e0 + p];
-                        R0 = fma(P, lb0, R0);
-                        R1 = fma(P, lb1, R1);
-                        R2 = fma(P, lb2, R2);
-                        T += s_Pt[e0 + p];
-                    }
+                    const double P = L.P[e0 + p];
+                    R0 = fma(P, lb0, R0);
+                    R1 = fma(P, lb1, R1);
+                    R2 = fma(P, lb2, R2);
+                    T += L.Pt[e0 + p];
                 }
             }
-            // reduce lam_a(q) R_b and T over the 8 lanes of the pair (lam includes w_q via s_winv)
             const double s00 = group8_sum(lqa0 * R0), s01 = group8_sum(lqa0 * R1), s02 = group8_sum(lqa0 * R2);
             const double s10 = group8_sum(lqa1 * R0), s11 = group8_sum(lqa1 * R1), s12 = group8_sum(lqa1 * R2);
             const double s20 = group8_sum(lqa2 * R0), s21 = group8_sum(lqa2 * R1), s22 = group8_sum(lqa2 * R2);
             const double sT = group8_sum(gq < 7 ? T : 0.0);
-            if (pair_hit && gsig < E) {
+            if (pair_hit) {
                 double Sm;
                 switch (gq) {
                 case 0: Sm = s00; break;
@@ -383,7 +409,7 @@ k_regular_sorted(GeomView g, TableView tv, const double* __restrict__ t, BandVie
                 scatter_half(band, val, valf, k, i, mla, mjb, (nn * Sm + Cm * sT) * scale);
                 if (gq == 0) scatter_half(band, val, valf, k, i, tv2, sv2, (nn * s22 + C8 * sT) * scale);
             }
-            __syncthreads();
+            wave_sync();
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
@@ -584,9 +610,8 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
                     double r_far, unsigned long long* counter, hipStream_t s)
 {
-    constexpr int C = 32;
-    dim3 grid(grid_for(g.E, C), g.E);
-    hipLaunchKernelGGL(k_regular_sorted<C>, grid, dim3(256), 0, s, g, tv, t, band, val, valf, r_far, counter);
+    dim3 grid(grid_for(g.E, kWavePairs), g.E);
+    hipLaunchKernelGGL(k_regular_wave, grid, dim3(64), 0, s, g, tv, t, band, val, valf, r_far, counter);
 }
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,

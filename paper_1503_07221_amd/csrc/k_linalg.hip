@@ -75,17 +75,6 @@ k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, d
     atomicAdd(gvec + (int64_t)k * M + g.v[2 * E + e], acc2);
 }
 
-// xt[j*ni + ii] = x[ii*M + j]: trial vector with the time index fastest, so that the band of one
-// vertex is contiguous.
-__global__ void __launch_bounds__(256)
-k_transpose_in(const double* __restrict__ x, int M, int ni, double* __restrict__ xt)
-{
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= (int64_t)M * ni) return;
-    const int ii = (int)(s / M), j = (int)(s - (int64_t)ii * M);
-    xt[(int64_t)j * ni + ii] = x[s];
-}
-
 // y = A[k0:k1, i0:i1] x on the lower-triangle band storage.  Block = one 64 x 64 tile (rows l,
 // columns j <= l) of one time row k; wave w takes rows l = 64 tl + w + 4m, lanes the columns.
 // A stored entry (l, j) serves y_k(l) += A x_i(j) and, off the diagonal, y_k(j) += A x_i(l)
@@ -93,7 +82,7 @@ k_transpose_in(const double* __restrict__ x, int M, int ni, double* __restrict__
 // into y (zeroed before).
 template <typename VT>
 __global__ void __launch_bounds__(256)
-k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, const double* __restrict__ xt,
+k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, const double* __restrict__ x,
              double* __restrict__ y)
 {
     const int M = band.M;
@@ -105,26 +94,40 @@ k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, 
     const int tj = t - tl * (tl + 1) / 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = tj * 64 + lane;
-    const int ni = i1 - i0;
     const int B = band.B[k];
     const int64_t voff = band.voff[k];
     const int16_t* __restrict__ il = band.ilo + (int64_t)k * band.ntri;
     double* __restrict__ yk = y + (int64_t)(k - k0) * M;
     double col = 0.0;
+    constexpr int kSlots = 8;    // slots issued together (loads first, then the FMAs)
     for (int m = 0; m < 16; ++m) {
         const int l = tl * 64 + wave + 4 * m;
         double row = 0.0;
         if (l < M && j <= l) {
             const int ib = il[tri_index(l, j)];
+            const int slo = i0 - ib > 0 ? i0 - ib : 0;
+            const int shi = i1 - ib < B ? i1 - ib : B;
             const VT* __restrict__ v = val + voff + (int64_t)B * tri_index(l, 0) + j;
-            const double* __restrict__ xj = xt + (int64_t)j * ni - i0;
-            const double* __restrict__ xl = xt + (int64_t)l * ni - i0;
-            for (int s = 0; s < B; ++s) {
-                const int i = ib + s;
-                if (i >= i0 && i < i1) {
-                    const double a = (double)v[(int64_t)s * (l + 1)];
-                    row = fma(a, xj[i], row);
-                    if (j < l) col = fma(a, xl[i], col);
+            // x in its own time-major layout: for one slot the lanes read consecutive j
+            const double* __restrict__ xj = x + (int64_t)(ib - i0) * M + j;
+            const double* __restrict__ xl = x + (int64_t)(ib - i0) * M + l;
+            const bool off_diag = j < l;
+            for (int s0 = slo; s0 < shi; s0 += kSlots) {
+                double a[kSlots], bj[kSlots], bl[kSlots];
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    const int s = s0 + u;
+                    a[u] = 0.0; bj[u] = 0.0; bl[u] = 0.0;
+                    if (s < shi) {
+                        a[u] = (double)v[(int64_t)s * (l + 1)];
+                        bj[u] = xj[(int64_t)s * M];
+                        bl[u] = xl[(int64_t)s * M];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    row = fma(a[u], bj[u], row);
+                    col = off_diag ? fma(a[u], bl[u], col) : col;
                 }
             }
         }
@@ -231,20 +234,18 @@ void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, doub
 }
 
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
-                   const double* x, double* y, double* xt, hipStream_t s)
+                   const double* x, double* y, hipStream_t s)
 {
     const int64_t M = band.M;
     const int64_t rows = (int64_t)(k1 - k0) * M;
     if (rows <= 0) return;
-    const int ni = i1 - i0;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(rows, 256)), dim3(256), 0, s, y, 0.0, rows);
-    hipLaunchKernelGGL(k_transpose_in, dim3(grid_for(M * ni, 256)), dim3(256), 0, s, x, (int)M, ni, xt);
     const int T = (int)((M + 63) / 64);
     dim3 grid(T * (T + 1) / 2, k1 - k0);
     if (valf)
-        hipLaunchKernelGGL(k_matvec_tri<float>, grid, dim3(256), 0, s, band, valf, k0, i0, i1, xt, y);
+        hipLaunchKernelGGL(k_matvec_tri<float>, grid, dim3(256), 0, s, band, valf, k0, i0, i1, x, y);
     else
-        hipLaunchKernelGGL(k_matvec_tri<double>, grid, dim3(256), 0, s, band, val, k0, i0, i1, xt, y);
+        hipLaunchKernelGGL(k_matvec_tri<double>, grid, dim3(256), 0, s, band, val, k0, i0, i1, x, y);
 }
 
 int dots_partial_blocks(int64_t n) { return (int)((n + kDotChunk - 1) / kDotChunk); }

@@ -272,7 +272,7 @@ void launch_get_entries(BandView band, const double* val, const float* valf, int
 void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
                 double t0, double width, int M, double* gvec, hipStream_t s);
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
-                   const double* x, double* y, double* xt, hipStream_t s);
+                   const double* x, double* y, hipStream_t s);
 
 void launch_dots(const double* V, int nvec, int64_t n, int64_t ld, const double* w, double* partial,
                  double* out, hipStream_t s);
