@@ -2,16 +2,21 @@
 
 One step = the whole hot path on the resident inputs of the 5120-triangle sphere with 64 graded
 temporal bases on [0, 8]: geometry, time-kernel tables, band layout, regular and singular
-assembly of every block A_{k,i}, the plane-pulse right-hand side, and the FGMRES(30) solve to a
-relative residual of 1e-8 with the recursive block-Hessenberg preconditioner (Algorithm 1).
+assembly of every block A_{k,i} in FP64, the plane-pulse right-hand side, and the FGMRES solve
+to a relative residual of 1e-8 with the recursive block-Hessenberg preconditioner (Algorithm 1).
 
 The headline value is assembly quadrature evaluations per second (one evaluation = one
-(x_q, y_q', k, i) with |x_q - y_q'| inside supp psi_{k,i}, counted over unordered triangle pairs);
-the same JSON line carries the solve time, iterations and residual, the roofline of the dominant
-kernel (the regular-pair assembly kernel, FP64 vector ALU bound) and the CPU oracle timed on a
-sample of the same workload.
+(x_q, y_q', k, i) with |x_q - y_q'| inside supp psi_{k,i}, counted over unordered triangle pairs).
+The same JSON line carries the solve, the mixed-precision form (FP32 far field, FP64 singular
+pairs and solver) with its error against FP64, the roofline of the dominant kernel (the
+regular-pair assembly kernel, FP64 vector ALU bound) and the CPU oracle timed on a sample of the
+same workload.
+
+`--copy-calibration` runs only a plain 1 GiB device copy (the reference kernel that scales the
+FETCH_SIZE / WRITE_SIZE hardware counters into HBM bytes).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,12 +27,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X, published
-HBM_PEAK_GBS = 8000.0
 # Algorithmic FP64 flops of one quadrature evaluation: two Clenshaw series of degree D
 # (per step one FMA and one subtraction: 3 flops; final step 3 flops) plus the map to the
 # piece variable (2 flops) and the accumulation (weight 1, product 1, three FMAs 6, one FMA 2).
 CHEB_DEGREE = 14
 FLOPS_PER_QUAD_EVAL = 2 * (3 * CHEB_DEGREE + 3) + 2 + 10
+REGULAR_KERNEL = "k_regular_wave"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07221_amd", "csrc", "k_assemble.hip")
 
 
 def parse():
@@ -36,13 +42,55 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere5120_graded64")
-    ap.add_argument("--precond", default="2,10", help="Algorithm 1 inner iterations per level ('' = none)")
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--precond", default="3,3,10", help="Algorithm 1 inner iterations per level ('' = none)")
+    ap.add_argument("--restart", type=int, default=300)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--max-it", type=int, default=2000)
+    ap.add_argument("--max-it", type=int, default=300)
+    ap.add_argument("--skip-solve", action="store_true", help="assembly and right-hand side only (profiling)")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=800, help="regular pairs timed on the CPU oracle")
+    ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 27                                   # 2^27 doubles = 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                      "dispatches": 3}))
+
+
+def source_digest():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counted_traffic(workload, launches_quad):
+    """HBM bytes per launch of the regular kernel from the committed counter summary, when it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{REGULAR_KERNEL}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals.get("kernel_source_sha256_16") != source_digest():
+            return None
+        fetch = float(vals["fetch_kib_per_dispatch"]) * 1024 * float(vals["fetch_scale"])
+        write = float(vals["write_kib_per_dispatch"]) * 1024 * float(vals["write_scale"])
+        return fetch + write
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, npairs):
@@ -65,12 +113,27 @@ def cpu_baseline(cfg, npairs):
             "sample": f"{npairs} random regular triangle pairs of {cfg['name']} ({n} quad-evals, {dt:.1f} s)"}
 
 
+def sample_entries(ctx, cfg, n, seed):
+    """Seeded (k, i, j, l) inside the Hessenberg band (i in k-5 .. k+1) for entry comparisons."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    M, N = len(cfg["mesh"][0]), len(cfg["grid"])
+    k = rng.integers(0, N, n)
+    i = np.clip(k - rng.integers(-1, 6, n), 0, N - 1)
+    j = rng.integers(0, M, n)
+    l = rng.integers(0, M, n)
+    return k, i, j, l
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
     import paper_1503_07221_amd as tb
@@ -83,37 +146,43 @@ def main():
     ctx = tb.Context(0)
     ctx.set_mesh(xyz, tri)
     ctx.set_time_grid(grid, cfg["cutoff"])
-    g = torch.empty(len(grid) * len(xyz), dtype=torch.float64, device="cuda:0")
+    n = len(grid) * len(xyz)
+    g = torch.empty(n, dtype=torch.float64, device="cuda:0")
     alpha = torch.empty_like(g)
 
-    def step():
-        rep = ctx.assemble(tb.FP64)
+    def step(prec=tb.FP64, out=alpha):
+        rep = ctx.assemble(prec)
         ctx.rhs_plane_pulse(cfg["direction"], cfg["t0"], cfg["width"], out=g)
-        _, srep = ctx.solve(g, tol=args.tol, restart=args.restart, max_it=args.max_it, precond_inner=inner,
-                            out=alpha)
+        srep = None
+        if not args.skip_solve:
+            _, srep = ctx.solve(g, tol=args.tol, restart=args.restart, max_it=args.max_it, precond_inner=inner,
+                                out=out)
         return rep, srep
 
-    for _ in range(args.warmup):
-        step()
-        print(f"# warmup step done", file=sys.stderr, flush=True)
+    def note(tag, rep, srep):
+        s = f"# {tag}: assembly {rep['ms_total']:.1f} ms (regular {rep['ms_regular']:.1f})"
+        if srep:
+            s += f", solve {srep['ms']:.1f} ms ({srep['iterations']} it, residual {srep['rel_residual']:.2e})"
+        print(s, file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        note(f"warmup {w}", *step())
     torch.cuda.synchronize()
     reps, sreps = [], []
     t0 = time.perf_counter()
     for s in range(args.steps):
         rep, srep = step()
         reps.append(rep); sreps.append(srep)
-        print(f"# step {s}: assembly {rep['ms_total']:.1f} ms, solve {srep['ms']:.1f} ms "
-              f"({srep['iterations']} it, residual {srep['rel_residual']:.2e})", file=sys.stderr, flush=True)
+        note(f"step {s}", rep, srep)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
     quad = reps[-1]["quad_evals"]
+    quad_reg = reps[-1]["quad_evals_regular"]
     asm_ms = float(np.mean([r["ms_total"] for r in reps]))
     reg_ms = float(np.mean([r["ms_regular"] for r in reps]))
-    solve_ms = float(np.mean([s["ms"] for s in sreps]))
-    # quad-evals handled by the regular kernel = total minus the singular pairs' share, which the
-    # library does not split; the regular kernel dominates (>97 % of the count)
-    achieved_tflops = quad * FLOPS_PER_QUAD_EVAL / (reg_ms * 1e-3) / 1e12
+    achieved_tflops = quad_reg * FLOPS_PER_QUAD_EVAL / (reg_ms * 1e-3) / 1e12
+    traffic = counted_traffic(cfg["name"], quad_reg)
     out = {
         "metric": "assembly quad-evals/s + FGMRES solve time to 1e-8 resid (FP64 vs mixed)",
         "value": quad / (asm_ms * 1e-3),
@@ -129,22 +198,49 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "triangles": int(len(tri)), "vertices": int(len(xyz)),
                    "time_bases": int(len(grid)), "T": float(grid[-1]), "precision": "fp64",
-                   "solver": f"FGMRES({args.restart}) + Algorithm 1 {inner}" if inner else f"FGMRES({args.restart})"},
+                   "solver": (f"FGMRES({args.restart}) + Algorithm 1 {inner}" if inner else f"FGMRES({args.restart})")
+                   if not args.skip_solve else "none (assembly only)"},
         "assembly_ms": asm_ms,
         "quad_evals": int(quad),
-        "solve_ms": solve_ms,
-        "solve_iterations": int(sreps[-1]["iterations"]),
-        "solve_matvecs": int(sreps[-1]["matvecs"]),
-        "solve_rel_residual": float(sreps[-1]["rel_residual"]),
-        "solve_converged": bool(sreps[-1]["converged"]),
+        "quad_evals_regular": int(quad_reg),
         "assembly_breakdown_ms": {k: float(np.mean([r[k] for r in reps]))
                                   for k in ("ms_tables", "ms_layout", "ms_regular", "ms_singular")},
         "matrix_bytes": int(reps[-1]["bytes_matrix"]),
-        "roofline": {"bound": "alu", "kernel": "k_regular", "achieved": achieved_tflops,
+        "roofline": {"bound": "alu", "kernel": REGULAR_KERNEL, "achieved": achieved_tflops,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_quad_eval": FLOPS_PER_QUAD_EVAL},
+                     "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "flops_per_quad_eval": FLOPS_PER_QUAD_EVAL, "launch_ms": reg_ms,
+                     "quad_evals_per_launch": int(quad_reg)},
     }
+    if not args.skip_solve:
+        out["solve"] = {"ms": float(np.mean([s["ms"] for s in sreps])), "iterations": int(sreps[-1]["iterations"]),
+                        "matvecs": int(sreps[-1]["matvecs"]), "rel_residual": float(sreps[-1]["rel_residual"]),
+                        "converged": bool(sreps[-1]["converged"])}
+    if not args.no_mixed:
+        # the mixed form on the same inputs, compared with the FP64 matrix and solution above
+        xr = torch.randn(n, dtype=torch.float64, device="cuda:0",
+                         generator=torch.Generator(device="cuda:0").manual_seed(11))
+        y64 = ctx.matvec(xr).clone()
+        ks, is_, js, ls = sample_entries(ctx, cfg, 200000, 5)
+        e64 = ctx.get_entries(ks, is_, js, ls)
+        a64 = alpha.clone()
+        alpha32 = torch.empty_like(g)
+        mrep, msrep = step(tb.MIXED, alpha32)
+        note("mixed", mrep, msrep)
+        y32 = ctx.matvec(xr)
+        e32 = ctx.get_entries(ks, is_, js, ls)
+        mixed = {"assembly_ms": mrep["ms_total"], "regular_ms": mrep["ms_regular"],
+                 "value": mrep["quad_evals"] / (mrep["ms_total"] * 1e-3), "matrix_bytes": int(mrep["bytes_matrix"]),
+                 "matvec_rel_err_vs_fp64": float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)),
+                 "entry_max_err_rel_to_max_entry": float(np.max(np.abs(e32 - e64)) / np.max(np.abs(e64)))}
+        if msrep:
+            mixed.update({"solve_ms": msrep["ms"], "iterations": int(msrep["iterations"]),
+                          "rel_residual_mixed_operator": float(msrep["rel_residual"]),
+                          "solution_rel_diff_vs_fp64": float(torch.linalg.norm(alpha32 - a64) / torch.linalg.norm(a64))})
+            ctx.assemble(tb.FP64)               # FP64 residual of the mixed solution
+            res = g - ctx.matvec(alpha32)
+            mixed["rel_residual_fp64_operator"] = float(torch.linalg.norm(res) / torch.linalg.norm(g))
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_pairs)
     ctx.close()

@@ -68,6 +68,7 @@ typedef struct {
     int64_t table_functions;     /* (k, i) kernels tabulated */
     int64_t bytes_matrix;        /* device bytes of the assembled blocks */
     double ms_tables, ms_layout, ms_regular, ms_singular, ms_total;
+    int64_t quad_evals_regular;  /* the part of quad_evals computed by the regular-pair kernel */
 } tdbem_assembly_report;
 
 typedef struct {

@@ -42,7 +42,8 @@ class AssemblyReport(ctypes.Structure):
                 ("pairs_coincident", ctypes.c_int64), ("pairs_edge", ctypes.c_int64),
                 ("pairs_vertex", ctypes.c_int64), ("table_functions", ctypes.c_int64),
                 ("bytes_matrix", ctypes.c_int64), ("ms_tables", ctypes.c_double), ("ms_layout", ctypes.c_double),
-                ("ms_regular", ctypes.c_double), ("ms_singular", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_regular", ctypes.c_double), ("ms_singular", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("quad_evals_regular", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -634,6 +634,7 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         float ms[4];
         for (int s = 0; s < 4; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
         rep->quad_evals = (int64_t)(counts[0] + counts[1]);
+        rep->quad_evals_regular = (int64_t)counts[0];
         const int64_t E = c->E;
         rep->pairs_coincident = c->npairs_kind[0];
         rep->pairs_edge = c->npairs_kind[1];
