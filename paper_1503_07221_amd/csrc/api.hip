@@ -157,14 +157,15 @@ struct tdbem_ctx {
     bool have_mesh = false, have_grid = false;
 
     // mesh on the device
-    DBuf d_xyz, d_tri, d_rho, g_P, g_n, g_area, g_curl, g_qp, g_v, d_pairs, d_rules, d_roff, d_rcnt;
+    DBuf d_xyz, d_tri, d_rho, g_P, g_n, g_area, g_curl, g_qp, g_v, d_pairs, d_rules, d_roff, d_rcnt, d_tiles;
+    int64_t ntiles = 0;
     int64_t npairs = 0, npairs_kind[3] = {0, 0, 0};
     // time grid
     DBuf d_t;
     TimeRule rule{};
     PieceTable pieces{};
     // tables
-    DBuf d_desc, d_fid, d_ivl, d_coef, d_coef32, d_fk, d_fi;
+    DBuf d_desc, d_fid, d_ivl, d_coef, d_coef32, d_fk, d_fi, d_meta, d_cell;
     double hmax = 0.0;   // longest triangle edge
     int64_t nfunc = 0;
     // band storage
@@ -203,6 +204,8 @@ struct tdbem_ctx {
         tv.ivl = d_ivl.as<double>();
         tv.coef = d_coef.as<double2>();
         tv.coef32 = d_coef32.as<float2>();
+        tv.meta = d_meta.as<double4>();
+        tv.cell = d_cell.as<uint16_t>();
         tv.N = N;
         tv.pt = pieces;
         return tv;
@@ -435,6 +438,9 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     TRY(upload(c, c->d_tri, c->tri.data(), c->tri.size()));
     TRY(upload(c, c->d_rho, rho.data(), rho.size()));
     TRY(upload(c, c->d_pairs, pairs.data(), pairs.size()));
+    const std::vector<int32_t> tiles = regular_tiles((int)E);
+    c->ntiles = (int64_t)tiles.size() / 2;
+    TRY(upload(c, c->d_tiles, tiles.data(), tiles.size()));
     TRY(upload(c, c->d_rules, rules.data(), rules.size()));
     TRY(upload(c, c->d_roff, roff, 3));
     TRY(upload(c, c->d_rcnt, rcnt, 3));
@@ -485,6 +491,8 @@ static tdbem_status build_tables(tdbem_ctx* c)
     std::vector<KernelDesc> desc;
     std::vector<int32_t> fid((size_t)N * N, -1), fk, fi;
     std::vector<double> ivl;
+    std::vector<double4> meta;
+    std::vector<uint16_t> cell;
     std::vector<int32_t> pc_f, pc_j, pc_p;
     int64_t coef_off = 0;
     for (int k = 0; k < N; ++k)
@@ -513,10 +521,30 @@ static tdbem_status build_tables(tdbem_ctx* c)
             kd.nint = (int32_t)uniq.size();
             kd.bp_off = (int32_t)ivl.size();
             kd.coef_off = coef_off;
+            kd.cell_scale = kCells / (end - lo);
+            kd.cell_off = (int32_t)cell.size();
+            kd.pad = 0;
+            const size_t m0 = meta.size();
             for (size_t s = 0; s < uniq.size(); ++s) {
-                const double a = uniq[s], b = s + 1 < uniq.size() ? uniq[s + 1] : end;
+                const double a = uniq[s], b = s + 1 < uniq.size() ? uniq[s + 1] : end, len = b - a;
                 ivl.push_back(a);
-                ivl.push_back(1.0 / (b - a));
+                ivl.push_back(1.0 / len);
+                for (int p = 0; p < kPieces; ++p) {
+                    const double e0 = c->pieces.edge[p], e1 = c->pieces.edge[p + 1];
+                    const bool last_interval = s + 1 == uniq.size();
+                    double4 r;
+                    r.x = p + 1 < kPieces ? a + e1 * len : (last_interval ? INFINITY : uniq[s + 1]);
+                    r.y = a + 0.5 * (e0 + e1) * len;
+                    r.z = 2.0 / ((e1 - e0) * len);
+                    r.w = ((s == 0 && p < kPieces / 2) || (last_interval && p >= kPieces / 2)) ? 1.0 : 0.0;
+                    meta.push_back(r);
+                }
+            }
+            for (int cc = 0; cc < kCells; ++cc) {
+                const double rc = lo + cc / kd.cell_scale;
+                size_t g = m0;
+                while (g + 1 < meta.size() && meta[g].x <= rc) ++g;
+                cell.push_back((uint16_t)(g - m0));
             }
             const int f = (int)desc.size();
             fid[(size_t)k * N + i] = f;
@@ -535,7 +563,11 @@ static tdbem_status build_tables(tdbem_ctx* c)
     const int64_t npieces = (int64_t)pc_f.size();
     TRY(upload(c, c->d_desc, desc.data(), desc.size()));
     TRY(upload(c, c->d_fid, fid.data(), fid.size()));
+    // padding: the regular kernel reads all kMaxIntervals starts of a kernel at once
+    ivl.insert(ivl.end(), 2 * kMaxIntervals, 0.0);
     TRY(upload(c, c->d_ivl, ivl.data(), ivl.size()));
+    TRY(upload(c, c->d_meta, meta.data(), meta.size()));
+    TRY(upload(c, c->d_cell, cell.data(), cell.size()));
     TRY(upload(c, c->d_fk, fk.data(), fk.size()));
     TRY(upload(c, c->d_fi, fi.data(), fi.size()));
     DBuf d_pcf, d_pcj, d_pcp, d_values;
@@ -618,7 +650,8 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     // mixed precision: point pairs farther apart than three of the longest triangle edges are the
     // far field; FP64 everywhere in FP64 mode
     const double r_far = prec == TDBEM_MIXED ? 3.0 * c->hmax : INFINITY;
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, r_far, cnt, c->stream);
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, r_far, c->d_tiles.as<int2>(),
+                   c->ntiles, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,

@@ -12,6 +12,8 @@
 // the lower-triangle storage forms on the fly (scatter_half).
 #include "tdbem_internal.hpp"
 
+#include <vector>
+
 namespace tdbem {
 
 // 7-point degree-5 rule (Radon; Stroud T2:5-1): centroid weight 9/40, orbits (a,a,1-2a) with
@@ -175,164 +177,245 @@ __device__ inline int wave_count_below(const double* key, int n, double v, bool 
     return base + __popcll(__ballot(below));
 }
 
-// One sorted element of the support range: locate its piece, evaluate both series and store
-// psi(r) w_q w_q'/r and tpsi(r) w_q w_q'/r at the element's own index.
-__device__ inline void eval_sorted_element(const KernelDesc& kd, const double* __restrict__ iv, const TableView& tv,
-                                           const PieceTable& spt, double r, int e, double w, double r_far,
-                                           double* s_P, double* s_Pt)
+// Both Chebyshev series at x from coefficients held in registers: T_m(x) by the three-term
+// recurrence, the two sums accumulated alongside (41 FP64 operations for degree 14).
+__device__ inline void cheb_sums(const double2 (&c)[kNc], double x, double& ps, double& pt)
 {
-    int j = 0;
-    for (int m = 1; m < kd.nint; ++m) j += r >= iv[2 * m] ? 1 : 0;
-    double fr = (r - iv[2 * j]) * iv[2 * j + 1];
-    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-    int cell = (int)(fr * kLutCells);
-    cell = cell < kLutCells ? cell : kLutCells - 1;
-    int p = spt.lut[cell];
-    if (p + 1 < kPieces && fr >= spt.edge[p + 1]) ++p;
-    const double x = 2.0 * (fr - spt.edge[p]) * spt.inv_width[p] - 1.0;
-    const int64_t off = kd.coef_off + (int64_t)(j * kPieces + p) * kNc;
-    double ps, pt;
-    // mixed precision: far-field distances on the middle pieces (away from the flat support
-    // edges) evaluate the FP32 copy of the series
-    if (r >= r_far && p >= kPieces / 2 - 3 && p < kPieces / 2 + 3) {
-        float fps, fpt;
-        clenshaw2_f32(tv.coef32 + off, (float)x, fps, fpt);
-        ps = fps;
-        pt = fpt;
-    } else {
-        clenshaw2(tv.coef + off, x, ps, pt);
+    const double x2 = 2.0 * x;
+    double tm1 = 1.0, tm = x;
+    ps = fma(c[1].x, x, c[0].x);
+    pt = fma(c[1].y, x, c[0].y);
+#pragma unroll
+    for (int m = 2; m < kNc; ++m) {
+        const double tn = fma(x2, tm, -tm1);
+        ps = fma(c[m].x, tn, ps);
+        pt = fma(c[m].y, tn, pt);
+        tm1 = tm;
+        tm = tn;
     }
-    s_P[e] = ps * w;
-    s_Pt[e] = pt * w;
 }
 
-// Wave-scope ordering of LDS accesses between lanes of one wave (no block barrier).
-__device__ inline void wave_sync()
+// The same in FP32, the coefficient pair m stored as two floats in the bits of c[m].x.
+__device__ inline void cheb_sums_f32(const double2 (&c)[kNc], float x, float& ps, float& pt)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float x2 = 2.0f * x;
+    float tm1 = 1.0f, tm = x;
+    auto lo = [&](int m) { return __uint_as_float((uint32_t)__double_as_longlong(c[m].x)); };
+    auto hi = [&](int m) { return __uint_as_float((uint32_t)((uint64_t)__double_as_longlong(c[m].x) >> 32)); };
+    ps = fmaf(lo(1), x, lo(0));
+    pt = fmaf(hi(1), x, hi(0));
+#pragma unroll
+    for (int m = 2; m < kNc; ++m) {
+        const float tn = fmaf(x2, tm, -tm1);
+        ps = fmaf(lo(m), tn, ps);
+        pt = fmaf(hi(m), tn, pt);
+        tm1 = tm;
+        tm = tn;
+    }
 }
 
-// Regular pairs, wave-independent sorted form.  Every wave owns 8 consecutive sigma of one tau
-// (392 point pairs), sorts their distances once in its own LDS region, and then runs the
-// (k, i) loop on its own: the point pairs inside supp psi_{k,i} are one contiguous range of the
-// sorted list, consecutive lanes take consecutive distances (their Chebyshev pieces mostly
-// coincide, so the coefficient loads coalesce), the values psi(r) w_q w_q'/r go to LDS in
-// element order, and the 8 lanes of each pair (lane q < 7 owns test point x_q) contract them with
-// the barycentric weights, reduce lam_a(q) R_b over the group and add entry (a, b) = (m/3, m%3)
-// of the pair's 3 x 3 block (lane 0 also entry 8).  Only the half P(v_b(sigma), v_a(tau)) is
-// added; the lower-triangle storage receives A = P + P^T directly (scatter_half).  No block
-// barrier is taken inside the loop, so the waves of a CU hide each other's latencies.
-constexpr int kWavePairs = 8;
-constexpr int kWaveEl = kWavePairs * 49;     // 392
-constexpr int kWaveSort = 512;
-struct WaveLds {
-    double key[kWaveSort];
-    uint16_t idx[kWaveSort];
-    double winv[kWaveEl];
-    double P[kWaveEl];
-    double Pt[kWaveEl];
-    double pmin[kWavePairs], pmax[kWavePairs];
+// 1/r to about one ulp: hardware reciprocal refined by two Newton steps.
+__device__ inline double recip(double r)
+{
+    double y = __builtin_amdgcn_rcp(r);
+    double e = fma(-r, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-r, y, 1.0);
+    return fma(y, e, y);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Regular pairs, tiled.  One workgroup (256 lanes) owns a tile of kTileT consecutive test
+// triangles tau and kTileS consecutive trial triangles sigma (the unordered pairs sigma > tau
+// without a common vertex: 32 x 49 point pairs).  It sorts the point-pair distances once; for
+// every (k, i) the distances inside supp psi_{k,i} form one range of the sorted list, which the
+// lanes split into contiguous chunks.  A lane keeps the Chebyshev coefficients of its current
+// piece in registers and reloads them only when the piece changes (sorted neighbours share
+// pieces), adds psi w/r lam_b(q') and tpsi w/r into per-(pair, test point) sums in LDS, and the
+// 8 lanes of each pair then contract those sums into the pair's 3 x 3 block.  Blocks of pairs
+// that share vertices are merged in an LDS tile over the two vertex sets before one atomic add
+// per (vertex, vertex) entry goes to the band storage.  Two barriers per (k, i).
+// ---------------------------------------------------------------------------------------------
+constexpr int kTileT = 4, kTileS = 8;
+constexpr int kTilePairs = kTileT * kTileS;          // 32
+constexpr int kTileEl = kTilePairs * 49;             // 1568
+constexpr int kTileSort = 2048;
+constexpr int kTileThreads = 256;
+constexpr int kTileVt = 3 * kTileT, kTileVs = 3 * kTileS;
+constexpr int kTileR = kTilePairs * 7 * 4;
+
+struct TileLds {
+    double key[kTileSort];
+    double R[2][kTileR];             // (q, {R_0, R_1, R_2, T}, pair): sum_q' lam_b(q') psi w/r, sum_q' tpsi w/r
+    double acc[kTileVt * kTileVs];
+    double wqq[49];                  // w_q w_q'
+    double lam[7 * 3];               // lam_b(q')
+    double pmin[kTilePairs], pmax[kTilePairs];
+    uint16_t idx[kTileSort];
+    int32_t vt[kTileVt], vs[kTileVs];
+    int32_t pok[kTilePairs];
+    int32_t nvt, nvs;
 };
 
-__global__ void __launch_bounds__(64)
-k_regular_wave(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
-               double r_far, unsigned long long* counter)
+template <bool MIXED>
+__global__ void __launch_bounds__(kTileThreads, 4)
+k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
+               double r_far, const int2* __restrict__ tiles, int64_t ntiles, unsigned long long* counter)
 {
+    // consecutive workgroups go to the 8 XCDs in turn: give each XCD one contiguous range of the
+    // tile list (same test rows, shared L2 lines for the output)
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t tix = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tix >= ntiles) return;
+    const int2 tl = tiles[tix];
     const int E = g.E;
-    const int tau = blockIdx.y;
-    const int lane = threadIdx.x;
-    const int sig0 = blockIdx.x * kWavePairs;
-    if (sig0 + kWavePairs - 1 <= tau) return;            // all sigma <= tau (block = one wave)
+    const int tau0 = tl.x * kTileT, sig0 = tl.y * kTileS;
+    const int tid = threadIdx.x;
+
     __shared__ PieceTable spt;
-    __shared__ WaveLds L;
+    __shared__ TileLds L;
     load_piece_table(spt, tv.pt);
-    __syncthreads();
-    const int tv0 = g.v[tau], tv1 = g.v[E + tau], tv2 = g.v[2 * E + tau];
-    for (int e = lane; e < kWaveSort; e += 64) {
-        if (e < kWaveEl) {
-            const int p = e / 49, qq = e - 49 * p, q = qq / 7, qp = qq - 7 * q;
-            const int sig = sig0 + p;
-            bool ok = sig > tau && sig < E;
-            const int sg = ok ? sig : tau;
-            if (ok) {
-                const int a0 = g.v[sg], a1 = g.v[E + sg], a2 = g.v[2 * E + sg];
-                ok = !(a0 == tv0 || a0 == tv1 || a0 == tv2 || a1 == tv0 || a1 == tv1 || a1 == tv2 || a2 == tv0 ||
-                       a2 == tv1 || a2 == tv2);
+    if (tid == 0) {
+        int n = 0;
+        for (int a = 0; a < kTileT && tau0 + a < E; ++a)
+            for (int c = 0; c < 3; ++c) {
+                const int v = g.v[c * E + tau0 + a];
+                bool f = false;
+                for (int u = 0; u < n; ++u) f = f || L.vt[u] == v;
+                if (!f) L.vt[n++] = v;
             }
-            const double d0 = g.qp[(3 * q) * E + tau] - g.qp[(3 * qp) * E + sg];
-            const double d1 = g.qp[(3 * q + 1) * E + tau] - g.qp[(3 * qp + 1) * E + sg];
-            const double d2 = g.qp[(3 * q + 2) * E + tau] - g.qp[(3 * qp + 2) * E + sg];
-            const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            double la, lb, lc, wq, wp;
-            rule7_point(q, la, lb, lc, wq);
-            rule7_point(qp, la, lb, lc, wp);
-            L.key[e] = ok ? r : INFINITY;
-            L.winv[e] = ok ? wq * wp / r : 0.0;
-            L.P[e] = 0.0;
-            L.Pt[e] = 0.0;
-        } else {
-            L.key[e] = INFINITY;
+        L.nvt = n;
+    } else if (tid == 64) {
+        int n = 0;
+        for (int a = 0; a < kTileS && sig0 + a < E; ++a)
+            for (int c = 0; c < 3; ++c) {
+                const int v = g.v[c * E + sig0 + a];
+                bool f = false;
+                for (int u = 0; u < n; ++u) f = f || L.vs[u] == v;
+                if (!f) L.vs[n++] = v;
+            }
+        L.nvs = n;
+    } else if (tid >= 128 && tid < 128 + 49) {
+        const int qq = tid - 128;
+        double l0, l1, l2, wq, wp;
+        rule7_point(qq / 7, l0, l1, l2, wq);
+        rule7_point(qq % 7, l0, l1, l2, wp);
+        L.wqq[qq] = wq * wp;
+        if (qq < 7) {
+            rule7_point(qq, l0, l1, l2, wp);
+            L.lam[3 * qq] = l0;
+            L.lam[3 * qq + 1] = l1;
+            L.lam[3 * qq + 2] = l2;
         }
-        L.idx[e] = (uint16_t)e;
+    } else if (tid >= 192 && tid < 192 + kTilePairs) {
+        const int p = tid - 192;
+        const int tau = tau0 + p / kTileS, sig = sig0 + p % kTileS;
+        bool ok = tau < E && sig < E && sig > tau;
+        if (ok) {
+            const int t0 = g.v[tau], t1 = g.v[E + tau], t2 = g.v[2 * E + tau];
+            const int a0 = g.v[sig], a1 = g.v[E + sig], a2 = g.v[2 * E + sig];
+            ok = !(a0 == t0 || a0 == t1 || a0 == t2 || a1 == t0 || a1 == t1 || a1 == t2 || a2 == t0 || a2 == t1 ||
+                   a2 == t2);
+        }
+        L.pok[p] = ok ? 1 : 0;
     }
-    wave_sync();
-    if (lane < kWavePairs) {
+    for (int z = tid; z < 2 * kTileR; z += kTileThreads) (&L.R[0][0])[z] = 0.0;
+    for (int z = tid; z < kTileVt * kTileVs; z += kTileThreads) L.acc[z] = 0.0;
+    __syncthreads();
+    for (int e = tid; e < kTileSort; e += kTileThreads) {
+        double r = INFINITY;
+        if (e < kTileEl) {
+            const int p = e / 49, qq = e - 49 * p, q = qq / 7, qp = qq - 7 * q;
+            if (L.pok[p]) {
+                const int tau = tau0 + p / kTileS, sig = sig0 + p % kTileS;
+                const double d0 = g.qp[(3 * q) * E + tau] - g.qp[(3 * qp) * E + sig];
+                const double d1 = g.qp[(3 * q + 1) * E + tau] - g.qp[(3 * qp + 1) * E + sig];
+                const double d2 = g.qp[(3 * q + 2) * E + tau] - g.qp[(3 * qp + 2) * E + sig];
+                r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            }
+        }
+        L.key[e] = r;
+        {
+            const int p = e / 49, qq = e - 49 * p;
+            L.idx[e] = (uint16_t)((p << 6) | ((qq / 7) << 3) | (qq % 7));
+        }
+    }
+    __syncthreads();
+    // distance range of every pair (8 lanes per pair, lane m < 7 scans the row q = m)
+    const int gp = tid >> 3, gm = tid & 7;
+    {
         double mn = INFINITY, mx = -INFINITY;
-        for (int u = 0; u < 49; ++u) {
-            const double r = L.key[lane * 49 + u];
-            if (r < INFINITY) { mn = fmin(mn, r); mx = fmax(mx, r); }
+        if (gm < 7)
+            for (int u = 0; u < 7; ++u) {
+                const double r = L.key[gp * 49 + gm * 7 + u];
+                if (r < INFINITY) { mn = fmin(mn, r); mx = fmax(mx, r); }
+            }
+        for (int o = 1; o < 8; o <<= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, 64));
+            mx = fmax(mx, __shfl_xor(mx, o, 64));
         }
-        L.pmin[lane] = mn;
-        L.pmax[lane] = mx;
+        if (gm == 0) { L.pmin[gp] = mn; L.pmax[gp] = mx; }
     }
-    // bitonic sort of (key, idx) inside the wave
-    for (int size = 2; size <= kWaveSort; size <<= 1) {
+    // bitonic sort of (key, idx)
+    for (int size = 2; size <= kTileSort; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            wave_sync();
-            for (int u = lane; u < kWaveSort / 2; u += 64) {
+            __syncthreads();
+            for (int u = tid; u < kTileSort / 2; u += kTileThreads) {
                 const int lo = 2 * stride * (u / stride) + (u % stride);
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
                 const double ka = L.key[lo], kb = L.key[hi];
                 if ((ka > kb) == up) {
-                    L.key[lo] = kb; L.key[hi] = ka;
+                    L.key[lo] = kb;
+                    L.key[hi] = ka;
                     const uint16_t ia = L.idx[lo];
-                    L.idx[lo] = L.idx[hi]; L.idx[hi] = ia;
+                    L.idx[lo] = L.idx[hi];
+                    L.idx[hi] = ia;
                 }
             }
         }
-    }
-    wave_sync();
-    const int nvalid = wave_count_below(L.key, kWaveSort, INFINITY, false);
-    if (nvalid == 0) return;
+    __syncthreads();
+    const int nvalid = __builtin_amdgcn_readfirstlane(wave_count_below(L.key, kTileSort, INFINITY, false));
+    if (nvalid == 0) return;                      // uniform: the whole workgroup leaves
     const double wmin = L.key[0], wmax = L.key[nvalid - 1];
-    const int N = tv.N;
-    // contraction lanes: pair gp, test point gq (gq == 7 idles)
-    const int gp = lane >> 3, gq = lane & 7;
-    const int gsig = sig0 + gp;
-    const int gsg = (gsig < E) ? gsig : tau;
-    double lqa0, lqa1, lqa2, wdummy;
-    rule7_point(gq < 7 ? gq : 0, lqa0, lqa1, lqa2, wdummy);
-    if (gq == 7) { lqa0 = lqa1 = lqa2 = 0.0; }
-    const int ma = gq / 3, mb = gq % 3;
-    const int sv0 = g.v[gsg], sv1 = g.v[E + gsg], sv2 = g.v[2 * E + gsg];
-    const int la = ma == 0 ? tv0 : (ma == 1 ? tv1 : tv2), jb = mb == 0 ? sv0 : (mb == 1 ? sv1 : sv2);
-    const int mla = gq < 7 ? la : tv2, mjb = gq < 7 ? jb : sv1;
-    const double nn = g.n[tau] * g.n[gsg] + g.n[E + tau] * g.n[E + gsg] + g.n[2 * E + tau] * g.n[2 * E + gsg];
-    const int ca = gq < 7 ? ma : 2, cb = gq < 7 ? mb : 1;
-    const double Cm = g.curl[(3 * ca) * E + tau] * g.curl[(3 * cb) * E + gsg] +
-                      g.curl[(3 * ca + 1) * E + tau] * g.curl[(3 * cb + 1) * E + gsg] +
-                      g.curl[(3 * ca + 2) * E + tau] * g.curl[(3 * cb + 2) * E + gsg];
-    const double C8 = g.curl[6 * E + tau] * g.curl[6 * E + gsg] + g.curl[7 * E + tau] * g.curl[7 * E + gsg] +
-                      g.curl[8 * E + tau] * g.curl[8 * E + gsg];
-    const double scale = g.area[tau] * g.area[gsg] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
-    const double pmn = L.pmin[gp], pmx = L.pmax[gp];
-    const bool pair_valid = pmx >= pmn;
-    unsigned long long nq = 0;
-    int prev0 = 0, prev1 = 0;                 // sorted range written for the previous (k, i)
 
+    // contraction lanes: pair gp, local entry gm = 3a + b (gm == 0 also takes entry 8)
+    const int ctau = tau0 + gp / kTileS, csig = sig0 + gp % kTileS;
+    const bool pvalid = L.pok[gp] != 0;
+    const double pmn = L.pmin[gp], pmx = L.pmax[gp];
+    const int ea = gm / 3, eb = gm % 3;
+    double nn = 0.0, Cm = 0.0, C8 = 0.0, scale = 0.0;
+    int om = 0, o8 = 0;
+    if (pvalid) {
+        nn = g.n[ctau] * g.n[csig] + g.n[E + ctau] * g.n[E + csig] + g.n[2 * E + ctau] * g.n[2 * E + csig];
+        Cm = g.curl[(3 * ea) * E + ctau] * g.curl[(3 * eb) * E + csig] +
+             g.curl[(3 * ea + 1) * E + ctau] * g.curl[(3 * eb + 1) * E + csig] +
+             g.curl[(3 * ea + 2) * E + ctau] * g.curl[(3 * eb + 2) * E + csig];
+        C8 = g.curl[6 * E + ctau] * g.curl[6 * E + csig] + g.curl[7 * E + ctau] * g.curl[7 * E + csig] +
+             g.curl[8 * E + ctau] * g.curl[8 * E + csig];
+        scale = g.area[ctau] * g.area[csig] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
+        const int vl = g.v[ea * E + ctau], vj = g.v[eb * E + csig];
+        const int vl8 = g.v[2 * E + ctau], vj8 = g.v[2 * E + csig];
+        int xl = 0, xj = 0, xl8 = 0, xj8 = 0;
+        for (int u = 0; u < L.nvt; ++u) {
+            xl = L.vt[u] == vl ? u : xl;
+            xl8 = L.vt[u] == vl8 ? u : xl8;
+        }
+        for (int u = 0; u < L.nvs; ++u) {
+            xj = L.vs[u] == vj ? u : xj;
+            xj8 = L.vs[u] == vj8 ? u : xj8;
+        }
+        om = xl * kTileVs + xj;
+        o8 = xl8 * kTileVs + xj8;
+    }
+
+    const int N = tv.N;
+    double2 cc[kNc];            // coefficients of the lane's current piece
+    double rhi = -1.0, rc = 0.0, ra = 0.0;
+    int64_t pcur = -1;
+    bool c32 = false;
+    unsigned long long nq = 0;
+    int buf = 0;
     int ia = 0, ib = -1;
     for (int k = 0; k < N; ++k) {
         while (ia < N) {
@@ -348,72 +431,106 @@ k_regular_wave(GeomView g, TableView tv, const double* __restrict__ t, BandView 
             ++ib;
         }
         for (int i = ia; i <= ib; ++i) {
-            const int f = tv.fid[k * N + i];
+            const int f = __builtin_amdgcn_readfirstlane(tv.fid[k * N + i]);
             if (f < 0) continue;
             const KernelDesc kd = tv.desc[f];
-            const int s0 = wave_count_below(L.key, nvalid, kd.lo, true);    // first r > lo
-            const int s1 = wave_count_below(L.key, nvalid, kd.hi, false);   // first r >= hi
+            const int s0 = __builtin_amdgcn_readfirstlane(wave_count_below(L.key, nvalid, kd.lo, true));
+            const int s1 = __builtin_amdgcn_readfirstlane(wave_count_below(L.key, nvalid, kd.hi, false));
             if (s1 <= s0) continue;
-            // the previous range's values outside the new range become zeros
-            const int z0 = prev0 < s0 ? prev0 : s0, z1 = prev1 > s1 ? prev1 : s1;
-            for (int s = z0 + lane; s < z1; s += 64)
-                if (s < s0 || s >= s1) { const int e = L.idx[s]; L.P[e] = 0.0; L.Pt[e] = 0.0; }
-            prev0 = s0;
-            prev1 = s1;
-            const double* iv = tv.ivl + kd.bp_off;
-            for (int base = s0; base < s1; base += 128) {
-                const int sa = base + lane, sb = base + 64 + lane;
-                if (sa < s1) {
-                    const int e = L.idx[sa];
-                    eval_sorted_element(kd, iv, tv, spt, L.key[sa], e, L.winv[e], r_far, L.P, L.Pt);
-                    ++nq;
-                }
-                if (sb < s1) {
-                    const int e = L.idx[sb];
-                    eval_sorted_element(kd, iv, tv, spt, L.key[sb], e, L.winv[e], r_far, L.P, L.Pt);
-                    ++nq;
-                }
-            }
-            wave_sync();
-            const bool pair_hit = pair_valid && pmx > kd.lo && pmn < kd.hi;
-            double R0 = 0.0, R1 = 0.0, R2 = 0.0, T = 0.0;
-            if (pair_hit && gq < 7) {
-                const int e0 = gp * 49 + gq * 7;
+            const int n = s1 - s0;
+            const int C = (n + kTileThreads - 1) / kTileThreads;
+            const int u1 = min(n, (tid + 1) * C);
+            double* __restrict__ Rb = L.R[buf];
+            rhi = -1.0;                                  // new kernel: no cached piece
+            pcur = -1;
+            for (int u = tid * C; u < u1; ++u) {
+                const int s = s0 + u;
+                const double r = L.key[s];
+                const int code = L.idx[s];
+                if (r >= rhi) {
+                    // the lane's next piece: the first one from the cell table (new kernel), else
+                    // the one after the current piece; advance while r lies beyond its end
+                    int64_t g;
+                    if (pcur < 0) {
+                        int cl = (int)((r - kd.lo) * kd.cell_scale);
+                        cl = cl < 0 ? 0 : (cl < kCells ? cl : kCells - 1);
+                        g = kd.coef_off / kNc + tv.cell[kd.cell_off + cl];
+                    } else {
+                        g = pcur + 1;
+                    }
+                    double4 mt = tv.meta[g];
+                    while (r >= mt.x) mt = tv.meta[++g];
+                    pcur = g;
+                    rhi = mt.x;
+                    rc = mt.y;
+                    ra = mt.z;
+                    const int64_t off = g * kNc;
+                    // mixed precision: far-field pieces away from the two ends of the support
+                    // evaluate the FP32 copy of the series
+                    c32 = MIXED && r >= r_far && mt.w == 0.0;
+                    if (c32) {
 #pragma unroll
-                for (int p = 0; p < 7; ++p) {
-                    double lb0, lb1, lb2, wp;
-                    rule7_point(p, lb0, lb1, lb2, wp);
-                    const double P = L.P[e0 + p];
-                    R0 = fma(P, lb0, R0);
-                    R1 = fma(P, lb1, R1);
-                    R2 = fma(P, lb2, R2);
-                    T += L.Pt[e0 + p];
+                        for (int m = 0; m < kNc; ++m) {
+                            const float2 v = tv.coef32[off + m];
+                            cc[m].x = __longlong_as_double((long long)(((uint64_t)__float_as_uint(v.y) << 32) |
+                                                                       (uint64_t)__float_as_uint(v.x)));
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < kNc; ++m) cc[m] = tv.coef[off + m];
+                    }
+                }
+                const double x = (r - rc) * ra;
+                double ps, pt;
+                if (MIXED && c32) {
+                    float fps, fpt;
+                    cheb_sums_f32(cc, (float)x, fps, fpt);
+                    ps = fps;
+                    pt = fpt;
+                } else {
+                    cheb_sums(cc, x, ps, pt);
+                }
+                const int pr = code >> 6, q = (code >> 3) & 7, qp = code & 7;
+                const double w = L.wqq[7 * q + qp] * recip(r);
+                const double P = ps * w;
+                double* Rq = Rb + q * 4 * kTilePairs + pr;
+                atomicAdd(Rq, P * L.lam[3 * qp]);
+                atomicAdd(Rq + kTilePairs, P * L.lam[3 * qp + 1]);
+                atomicAdd(Rq + 2 * kTilePairs, P * L.lam[3 * qp + 2]);
+                atomicAdd(Rq + 3 * kTilePairs, pt * w);
+                ++nq;
+            }
+            __syncthreads();
+            // the other buffer was read by the previous (k, i): clear it for the next one
+            for (int z = tid; z < kTileR; z += kTileThreads) L.R[buf ^ 1][z] = 0.0;
+            if (pvalid && pmx > kd.lo && pmn < kd.hi) {
+                const double* Rp = Rb + gp;
+                double Sm = 0.0, S8 = 0.0, ST = 0.0;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    double l0, l1, l2, w;
+                    rule7_point(q, l0, l1, l2, w);
+                    Sm = fma(ea == 0 ? l0 : (ea == 1 ? l1 : l2), Rp[(4 * q + eb) * kTilePairs], Sm);
+                    S8 = fma(l2, Rp[(4 * q + 2) * kTilePairs], S8);
+                    ST += Rp[(4 * q + 3) * kTilePairs];
+                }
+                atomicAdd(&L.acc[om], (nn * Sm + Cm * ST) * scale);
+                if (gm == 0) atomicAdd(&L.acc[o8], (nn * S8 + C8 * ST) * scale);
+            }
+            __syncthreads();
+            for (int z = tid; z < kTileVt * kTileVs; z += kTileThreads) {
+                const double v = L.acc[z];
+                if (v != 0.0) {
+                    const int a = z / kTileVs, b = z - kTileVs * a;
+                    scatter_half(band, val, valf, k, i, L.vt[a], L.vs[b], v);
+                    L.acc[z] = 0.0;
                 }
             }
-            const double s00 = group8_sum(lqa0 * R0), s01 = group8_sum(lqa0 * R1), s02 = group8_sum(lqa0 * R2);
-            const double s10 = group8_sum(lqa1 * R0), s11 = group8_sum(lqa1 * R1), s12 = group8_sum(lqa1 * R2);
-            const double s20 = group8_sum(lqa2 * R0), s21 = group8_sum(lqa2 * R1), s22 = group8_sum(lqa2 * R2);
-            const double sT = group8_sum(gq < 7 ? T : 0.0);
-            if (pair_hit) {
-                double Sm;
-                switch (gq) {
-                case 0: Sm = s00; break;
-                case 1: Sm = s01; break;
-                case 2: Sm = s02; break;
-                case 3: Sm = s10; break;
-                case 4: Sm = s11; break;
-                case 5: Sm = s12; break;
-                case 6: Sm = s20; break;
-                default: Sm = s21; break;
-                }
-                scatter_half(band, val, valf, k, i, mla, mjb, (nn * Sm + Cm * sT) * scale);
-                if (gq == 0) scatter_half(band, val, valf, k, i, tv2, sv2, (nn * s22 + C8 * sT) * scale);
-            }
-            wave_sync();
+            buf ^= 1;
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
-    if (lane == 0 && tot) atomicAdd(counter, tot);
+    if ((tid & 63) == 0 && tot) atomicAdd(counter, tot);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -608,10 +725,30 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    double r_far, unsigned long long* counter, hipStream_t s)
+                    double r_far, const int2* tiles, int64_t ntiles, unsigned long long* counter, hipStream_t s)
 {
-    dim3 grid(grid_for(g.E, kWavePairs), g.E);
-    hipLaunchKernelGGL(k_regular_wave, grid, dim3(64), 0, s, g, tv, t, band, val, valf, r_far, counter);
+    if (ntiles <= 0) return;
+    const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
+    if (valf)
+        hipLaunchKernelGGL(k_regular_tile<true>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, r_far,
+                           tiles, ntiles, counter);
+    else
+        hipLaunchKernelGGL(k_regular_tile<false>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, r_far,
+                           tiles, ntiles, counter);
+}
+
+// Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau.
+std::vector<int32_t> regular_tiles(int E)
+{
+    std::vector<int32_t> out;
+    const int nA = (E + kTileT - 1) / kTileT, nB = (E + kTileS - 1) / kTileS;
+    for (int a = 0; a < nA; ++a)
+        for (int b = 0; b < nB; ++b)
+            if (b * kTileS + kTileS - 1 > a * kTileT) {
+                out.push_back(a);
+                out.push_back(b);
+            }
+    return out;
 }
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace tdbem {
 
 // ---------------------------------------------------------------------------------------------
@@ -29,7 +31,17 @@ struct KernelDesc {
     int32_t nint;         // number of intervals
     int32_t bp_off;       // interval starts and inverse lengths: ivl[bp_off + 2*j], ivl[bp_off + 2*j + 1]
     int64_t coef_off;     // first double2 of this kernel: coef[coef_off + (j*kPieces + p)*kNc + m]
+    double cell_scale;    // kCells / (length of the tabulated range starting at lo)
+    int32_t cell_off;     // first entry of this kernel in the cell table
+    int32_t pad;
 };
+
+// Per-piece record (piece g = coef offset / kNc): the piece covers r < rhi (and r at or above the
+// previous piece's rhi), x = (r - rc) * ra maps it onto [-1, 1]; near = 1 for the pieces of the
+// first half of the first interval and the second half of the last one (the flat ends of the
+// support).  The cell table splits [lo, end) of every kernel into kCells equal cells and holds
+// the first piece (kernel-local index) that meets each cell.
+constexpr int kCells = 256;
 
 // Graded partition of [0, 1] into kPieces pieces: edges, inverse widths and a lookup table
 // lut[c] = the piece containing c / kLutCells.  Every piece is wider than one cell, so the piece
@@ -148,6 +160,8 @@ struct TableView {
     const double* ivl;        // interval starts and inverse lengths
     const double2* coef;      // Chebyshev coefficients (psi, tpsi)
     const float2* coef32;     // the same rounded to FP32 (mixed precision far field)
+    const double4* meta;      // per-piece record (rhi, rc, ra, near)
+    const uint16_t* cell;     // cell table
     int32_t N;
     PieceTable pt;
 };
@@ -262,7 +276,8 @@ void launch_layout(const double* xyz, const double* rho, int M, const double* t,
                    int32_t* Bk, hipStream_t s);
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    double r_far, unsigned long long* counter, hipStream_t s);
+                    double r_far, const int2* tiles, int64_t ntiles, unsigned long long* counter, hipStream_t s);
+std::vector<int32_t> regular_tiles(int E);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      double* val, float* valf, unsigned long long* counter, hipStream_t s);
