@@ -218,7 +218,8 @@ struct tdbem_ctx {
         b.voff = d_voff.as<int64_t>();
         b.M = M;
         b.N = N;
-        b.ntri = (int64_t)M * (M + 1) / 2;
+        const int64_t T = ((int64_t)M + kBT - 1) / kBT;
+        b.nt = T * (T + 1) / 2;
         return b;
     }
     const double* valf64() const { return prec == TDBEM_FP64 ? d_val.as<double>() : nullptr; }
@@ -590,12 +591,14 @@ static tdbem_status build_tables(tdbem_ctx* c)
 static tdbem_status build_layout(tdbem_ctx* c, int prec)
 {
     const int64_t M = c->M, N = c->N;
-    const int64_t ntri = M * (M + 1) / 2;
-    ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * ntri));
+    const int64_t T = (M + kBT - 1) / kBT;
+    const int64_t per_k = T * (T + 1) / 2 * kBT * kBT;     // tile slots of one time row
+    ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * per_k));
+    HIPCHK(c, hipMemsetAsync(c->d_ilo.p, 0, sizeof(int16_t) * (size_t)(N * per_k), c->stream));
     ALLOC(c, c->d_B, sizeof(int32_t) * N);
     HIPCHK(c, hipMemsetAsync(c->d_B.p, 0, sizeof(int32_t) * N, c->stream));
-    launch_layout(c->d_xyz.as<double>(), c->d_rho.as<double>(), c->M, c->d_t.as<double>(), c->N,
-                  c->d_ilo.as<int16_t>(), c->d_B.as<int32_t>(), c->stream);
+    launch_layout(c->band(), c->d_xyz.as<double>(), c->d_rho.as<double>(), c->d_t.as<double>(), c->d_ilo.as<int16_t>(),
+                  c->d_B.as<int32_t>(), c->stream);
     HIPCHK(c, hipGetLastError());
     c->Bk.assign(N, 0);
     HIPCHK(c, hipMemcpyAsync(c->Bk.data(), c->d_B.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
@@ -604,7 +607,7 @@ static tdbem_status build_layout(tdbem_ctx* c, int prec)
     int64_t tot = 0;
     for (int k = 0; k < N; ++k) {
         c->voff[k] = tot;
-        tot += (int64_t)c->Bk[k] * ntri;
+        tot += (int64_t)c->Bk[k] * per_k;
     }
     c->nvals = tot;
     TRY(upload(c, c->d_voff, c->voff.data(), c->voff.size()));

@@ -74,15 +74,15 @@ k_geometry(const double* __restrict__ xyz, const int32_t* __restrict__ tri, int 
 // lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).  Block
 // (j chunk, l); lanes with j > l idle (lower triangle only).
 __global__ void __launch_bounds__(256)
-k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, const double* __restrict__ t,
-         int N, int16_t* __restrict__ ilo, int32_t* __restrict__ Bk)
+k_layout(BandView band, const double* __restrict__ xyz, const double* __restrict__ rho,
+         const double* __restrict__ t, int16_t* __restrict__ ilo, int32_t* __restrict__ Bk)
 {
+    const int M = band.M, N = band.N;
     extern __shared__ int32_t sB[];
     for (int k = threadIdx.x; k < N; k += blockDim.x) sB[k] = 0;
     __syncthreads();
     const int l = blockIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntri = (int64_t)M * (M + 1) / 2;
     if (j <= l) {
         const double dx = xyz[3 * l] - xyz[3 * j], dy = xyz[3 * l + 1] - xyz[3 * j + 1], dz = xyz[3 * l + 2] - xyz[3 * j + 2];
         const double d = sqrt(dx * dx + dy * dy + dz * dz);
@@ -105,7 +105,7 @@ k_layout(const double* __restrict__ xyz, const double* __restrict__ rho, int M, 
                 ++ib;
             }
             const int first = ia < N ? ia : N - 1;
-            ilo[(int64_t)k * ntri + tri_index(l, j)] = (int16_t)first;
+            ilo[band_ilo_index(band, k, l, j)] = (int16_t)first;
             const int cnt = ib - ia + 1;
             if (cnt > 0) atomicMax(&sB[k], cnt);
         }
@@ -147,7 +147,7 @@ __device__ inline void scatter_half(const BandView& band, double* val, float* va
 {
     if (j > l) { const int tmp = j; j = l; l = tmp; }
     if (j == l) v *= 2.0;
-    const int s = i - (int)band.ilo[(int64_t)k * band.ntri + tri_index(l, j)];
+    const int s = i - (int)band.ilo[band_ilo_index(band, k, l, j)];
     const int B = band.B[k];
     if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
     const int64_t idx = band_value_index(band, k, l, j, s, B);
@@ -699,7 +699,7 @@ k_get_entries(BandView band, const double* __restrict__ val, const float* __rest
     double v = 0.0;
     if (kk >= 0 && kk < band.N && ii >= 0 && ii < band.N && jj >= 0 && ll < band.M) {
         const int B = band.B[kk];
-        const int sl = ii - (int)band.ilo[(int64_t)kk * band.ntri + tri_index(ll, jj)];
+        const int sl = ii - (int)band.ilo[band_ilo_index(band, kk, ll, jj)];
         if (sl >= 0 && sl < B) {
             const int64_t idx = band_value_index(band, kk, ll, jj, sl, B);
             v = valf ? (double)valf[idx] : val[idx];
@@ -717,11 +717,11 @@ void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P
                        geo_curl, geo_qp, geo_v);
 }
 
-void launch_layout(const double* xyz, const double* rho, int M, const double* t, int N, int16_t* ilo, int32_t* Bk,
+void launch_layout(BandView band, const double* xyz, const double* rho, const double* t, int16_t* ilo, int32_t* Bk,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layout, dim3(grid_for(M, 256), M), dim3(256), sizeof(int32_t) * N, s, xyz, rho, M, t, N, ilo,
-                       Bk);
+    hipLaunchKernelGGL(k_layout, dim3(grid_for(band.M, 256), band.M), dim3(256), sizeof(int32_t) * band.N, s, band,
+                       xyz, rho, t, ilo, Bk);
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,

@@ -75,11 +75,14 @@ k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, d
     atomicAdd(gvec + (int64_t)k * M + g.v[2 * E + e], acc2);
 }
 
-// y = A[k0:k1, i0:i1] x on the lower-triangle band storage.  Block = one 64 x 64 tile (rows l,
-// columns j <= l) of one time row k; wave w takes rows l = 64 tl + w + 4m, lanes the columns.
-// A stored entry (l, j) serves y_k(l) += A x_i(j) and, off the diagonal, y_k(j) += A x_i(l)
-// (block symmetry); rows are reduced per wave, columns over the block, both added atomically
-// into y (zeroed before).
+// y = A[k0:k1, i0:i1] x on the lower-triangle band storage.  Block = one 64 x 64 vertex tile
+// (rows l, columns j <= l) of one time row k, whose values are one contiguous stretch; wave w
+// takes the 16 rows l = 64 tl + w + 4m, lanes the columns.  A stored entry (l, j) serves
+// y_k(l) += A x_i(j) and, off the diagonal, y_k(j) += A x_i(l) (block symmetry).  Rows go two
+// at a time: the band starts of the next two rows are loaded while the current two are in
+// flight, and all their slots are issued before the FMAs.  Row partials are reduced over the
+// lanes through LDS, column sums over the 4 waves; both are added atomically into y (zeroed
+// before).
 template <typename VT>
 __global__ void __launch_bounds__(256)
 k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, const double* __restrict__ x,
@@ -87,56 +90,99 @@ k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, 
 {
     const int M = band.M;
     const int k = k0 + blockIdx.y;
+    const int B = band.B[k];
+    if (B == 0) return;                        // no stored values in this time row
     const int t = blockIdx.x;
     int tl = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((tl + 1) * (tl + 2) / 2 <= t) ++tl;
     while (tl * (tl + 1) / 2 > t) --tl;
     const int tj = t - tl * (tl + 1) / 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = tj * 64 + lane;
-    const int B = band.B[k];
-    const int64_t voff = band.voff[k];
-    const int16_t* __restrict__ il = band.ilo + (int64_t)k * band.ntri;
+    const int j = tj * kBT + lane;
+    const int16_t* __restrict__ il = band.ilo + ((int64_t)k * band.nt + t) * (kBT * kBT) + lane;
+    const VT* __restrict__ vt = val + band.voff[k] + (int64_t)t * kBT * kBT * B + lane;
     double* __restrict__ yk = y + (int64_t)(k - k0) * M;
+    __shared__ double s_row[4][16][65];
+    __shared__ double s_col[4][64];
+    constexpr int kSlots = 8;    // slots of one row issued together
+    // every load below is unconditional at an in-range address (tile entries outside the
+    // triangle are stored zeros; lanes without a range read x at block i0, column <= M-1 and are
+    // masked out), so the compiler issues the loads of two rows together and waits once
+    const int je = j < M ? j : M - 1;
     double col = 0.0;
-    constexpr int kSlots = 8;    // slots issued together (loads first, then the FMAs)
-    for (int m = 0; m < 16; ++m) {
-        const int l = tl * 64 + wave + 4 * m;
-        double row = 0.0;
-        if (l < M && j <= l) {
-            const int ib = il[tri_index(l, j)];
-            const int slo = i0 - ib > 0 ? i0 - ib : 0;
-            const int shi = i1 - ib < B ? i1 - ib : B;
-            const VT* __restrict__ v = val + voff + (int64_t)B * tri_index(l, 0) + j;
-            // x in its own time-major layout: for one slot the lanes read consecutive j
-            const double* __restrict__ xj = x + (int64_t)(ib - i0) * M + j;
-            const double* __restrict__ xl = x + (int64_t)(ib - i0) * M + l;
-            const bool off_diag = j < l;
-            for (int s0 = slo; s0 < shi; s0 += kSlots) {
-                double a[kSlots], bj[kSlots], bl[kSlots];
+    int ibA = il[(wave + 0) * kBT], ibB = il[(wave + 4) * kBT];
+    for (int m = 0; m < 16; m += 2) {
+        const int nA = il[(wave + 4 * (m + 2 < 16 ? m + 2 : 14)) * kBT];
+        const int nB = il[(wave + 4 * (m + 3 < 16 ? m + 3 : 15)) * kBT];
+        double a[2][kSlots], bj[2][kSlots], bl[2][kSlots];
+        int cnt[2];
 #pragma unroll
-                for (int u = 0; u < kSlots; ++u) {
-                    const int s = s0 + u;
-                    a[u] = 0.0; bj[u] = 0.0; bl[u] = 0.0;
-                    if (s < shi) {
-                        a[u] = (double)v[(int64_t)s * (l + 1)];
-                        bj[u] = xj[(int64_t)s * M];
-                        bl[u] = xl[(int64_t)s * M];
-                    }
-                }
+        for (int h = 0; h < 2; ++h) {
+            const int lr = wave + 4 * (m + h);
+            const int l = tl * kBT + lr;
+            const bool act = l < M && j <= l;
+            const int ib = h ? ibB : ibA;
+            const int lo = i0 - ib > 0 ? i0 - ib : 0;
+            const int hi = i1 - ib < B ? i1 - ib : B;
+            cnt[h] = act && hi > lo ? hi - lo : 0;
+            const int s0 = cnt[h] ? lo : 0, ibe = cnt[h] ? ib : i0;
+            const int top = cnt[h] ? cnt[h] - 1 : 0;
+            const int le = l < M ? l : M - 1;
+            const VT* __restrict__ v = vt + ((int64_t)lr * B + s0) * kBT;
+            const double* __restrict__ xj = x + (int64_t)(ibe + s0 - i0) * M + je;
+            const double* __restrict__ xl = x + (int64_t)(ibe + s0 - i0) * M + le;
 #pragma unroll
-                for (int u = 0; u < kSlots; ++u) {
-                    row = fma(a[u], bj[u], row);
-                    col = off_diag ? fma(a[u], bl[u], col) : col;
-                }
+            for (int u = 0; u < kSlots; ++u) {
+                const int su = u < top ? u : top;
+                a[h][u] = (double)v[su * kBT];
+                bj[h][u] = xj[(int64_t)su * M];
+                bl[h][u] = xl[(int64_t)su * M];
             }
         }
-        for (int o = 32; o >= 1; o >>= 1) row += __shfl_xor(row, o, 64);
-        if (lane == 0 && l < M && row != 0.0) atomicAdd(yk + l, row);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int lr = wave + 4 * (m + h);
+            const int l = tl * kBT + lr;
+            const bool off_diag = j < l;
+            double row = 0.0, cl = 0.0;
+#pragma unroll
+            for (int u = 0; u < kSlots; ++u) {
+                const double av = u < cnt[h] ? a[h][u] : 0.0;
+                row = fma(av, bj[h][u], row);
+                cl = fma(av, bl[h][u], cl);
+            }
+            // bands wider than kSlots (rare): the remaining slots one at a time
+            if (cnt[h] > kSlots) {
+                const int ib = h ? ibB : ibA;
+                const int lo = i0 - ib > 0 ? i0 - ib : 0;
+                const VT* __restrict__ v = vt + (int64_t)lr * B * kBT;
+                const double* __restrict__ xj = x + (int64_t)(ib - i0) * M + j;
+                const double* __restrict__ xl = x + (int64_t)(ib - i0) * M + l;
+                for (int s = lo + kSlots; s < lo + cnt[h]; ++s) {
+                    const double av = (double)v[s * kBT];
+                    row = fma(av, xj[(int64_t)s * M], row);
+                    cl = fma(av, xl[(int64_t)s * M], cl);
+                }
+            }
+            col += off_diag ? cl : 0.0;
+            s_row[wave][m + h][lane] = row;
+        }
+        ibA = nA;
+        ibB = nB;
     }
-    __shared__ double s_col[4][64];
     s_col[wave][lane] = col;
     __syncthreads();
+    {
+        // row sums: lane = (row m, quarter q) sums 16 lanes of its row, then the 4 quarters
+        const int m = lane >> 2, q = lane & 3;
+        double rs = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) rs += s_row[wave][m][16 * q + u];
+        rs += __shfl_xor(rs, 1, 64);
+        rs += __shfl_xor(rs, 2, 64);
+        const int l = tl * kBT + wave + 4 * m;
+        if (q == 0 && l < M && rs != 0.0) atomicAdd(yk + l, rs);
+    }
     if (wave == 0 && j < M) {
         const double c = s_col[0][lane] + s_col[1][lane] + s_col[2][lane] + s_col[3][lane];
         if (c != 0.0) atomicAdd(yk + j, c);

@@ -238,22 +238,34 @@ struct GeomView {
 
 // Band storage of the blocks.  Every block is symmetric in (j, l), so only the lower triangle
 // j <= l is kept.  For every vertex pair (l, j <= l) and time row k the trial indices
-// i = ilo[k][(l, j)] + s, s < B_k, are those whose kernel support meets the conservative distance
-// range of the two hats (eq. (SparsitySmallBlock)); the values of row l are stored slot-major,
-// val[voff[k] + B_k * l(l+1)/2 + s*(l+1) + j], so a wave reads one slot of a row coalesced.
+// i = ilo + s, s < B_k, are those whose kernel support meets the conservative distance range of
+// the two hats (eq. (SparsitySmallBlock)).  The triangle is cut into 64 x 64 vertex tiles
+// (tl, tj <= tl), numbered t = tl(tl+1)/2 + tj (nt of them); per time row k the tiles follow
+// each other and a tile holds [row l % 64][slot s][column j % 64], so the values a workgroup of
+// the matvec reads form one contiguous stretch:
+//   ilo[(k nt + t) 4096 + (l % 64) 64 + j % 64]
+//   val[voff[k] + ((t 64 + l % 64) B_k + s) 64 + j % 64]
+// Tile entries outside the triangle or past M stay zero.
+constexpr int kBT = 64;
 __host__ __device__ inline int64_t tri_index(int64_t l, int64_t j) { return l * (l + 1) / 2 + j; }
+__host__ __device__ inline int64_t band_tile(int64_t l, int64_t j) { return tri_index(l / kBT, j / kBT); }
 
 struct BandView {
-    const int16_t* ilo;    // ilo[k*ntri + tri_index(l, j)], j <= l
+    const int16_t* ilo;    // first trial index of every (k, l, j <= l), tiled as above
     const int32_t* B;      // B[k]
     const int64_t* voff;   // voff[k]
     int32_t M, N;
-    int64_t ntri;          // M (M + 1) / 2
+    int64_t nt;            // tiles per time row
 };
+
+__host__ __device__ inline int64_t band_ilo_index(const BandView& b, int k, int64_t l, int64_t j)
+{
+    return ((int64_t)k * b.nt + band_tile(l, j)) * (kBT * kBT) + (l % kBT) * kBT + j % kBT;
+}
 
 __device__ inline int64_t band_value_index(const BandView& b, int k, int64_t l, int64_t j, int s, int B)
 {
-    return b.voff[k] + (int64_t)B * tri_index(l, 0) + (int64_t)s * (l + 1) + j;
+    return b.voff[k] + ((band_tile(l, j) * kBT + l % kBT) * (int64_t)B + s) * kBT + j % kBT;
 }
 
 }  // namespace tdbem
@@ -272,7 +284,7 @@ void launch_table_eval(TableView tv, int64_t n, const int32_t* k, const int32_t*
 
 void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P, double* geo_n,
                      double* geo_area, double* geo_curl, double* geo_qp, int32_t* geo_v, hipStream_t s);
-void launch_layout(const double* xyz, const double* rho, int M, const double* t, int N, int16_t* ilo,
+void launch_layout(BandView band, const double* xyz, const double* rho, const double* t, int16_t* ilo,
                    int32_t* Bk, hipStream_t s);
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,

@@ -3,6 +3,8 @@
 Tolerances: blocks of eq. (MatrixEntries) to 1e-11 relative per block (max norm); the time
 kernel tables to 1e-11 (psi) and 1e-12 (tilde psi) of each kernel's maximum; RHS and matvec to
 1e-13; solves to their residual tolerance.  Integer work (quadrature-point counts) is exact.
+The mixed-precision form (FP32 series on far-field pieces, FP32 storage, FP64 singular pairs,
+sums and solver) is held to MIXED_TOL relative per block.
 """
 import numpy as np
 import pytest
@@ -13,6 +15,9 @@ from workloads import equidistant_grid, graded_grid, get_config, icosphere, toru
 pytestmark = pytest.mark.gpu
 
 BLOCK_TOL = 1e-11
+# FP32 storage rounds every entry (2^-24 relative) and the far-field series run in FP32: the
+# sum of a few hundred FP32-rounded terms of one sign, ~1e-6 of the block maximum at worst
+MIXED_TOL = 2e-6
 
 
 @pytest.fixture(scope="module")
@@ -169,6 +174,51 @@ def test_sampled_entries_full_size(ctx, oracle_mod, name):
         got_t = ctx.get_entries(K.ravel(), I.ravel(), sl[s], sj[s]).reshape(N, N)
         assert np.array_equal(got, got_t)
         assert np.all(got[np.triu_indices(N, 2)] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["sphere320_eq10", "sphere5120_graded64"])
+def test_mixed_sampled_entries(ctx, tb, oracle_mod, name):
+    """Mixed precision against the FP64 oracle at sampled vertex pairs of every (k, i) block,
+    with the exact block symmetry and Hessenberg zeros kept."""
+    c = get_config(name)
+    xyz, tri = c["mesh"]; grid = c["grid"]
+    ctx.set_mesh(xyz, tri)
+    ctx.set_time_grid(grid, c["cutoff"])
+    ctx.assemble(tb.MIXED)
+    N = len(grid)
+    sj, sl = _sample_pairs(xyz, tri, np.random.default_rng(6), 4 if name == "sphere320_eq10" else 2)
+    if name == "sphere5120_graded64":
+        sj, sl = sj[:3], sl[:3]
+    ref = oracle_mod.assemble_entries(xyz, tri, grid, sj, sl, kind=c["cutoff"])
+    K, I = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    worst = 0.0
+    for s in range(len(sj)):
+        got = ctx.get_entries(K.ravel(), I.ravel(), sj[s], sl[s]).reshape(N, N)
+        sc = np.abs(ref[s]).max()
+        worst = max(worst, np.abs(got - ref[s]).max() / sc)
+        got_t = ctx.get_entries(K.ravel(), I.ravel(), sl[s], sj[s]).reshape(N, N)
+        assert np.array_equal(got, got_t)
+        assert np.all(got[np.triu_indices(N, 2)] == 0.0)
+    assert worst <= MIXED_TOL, worst
+
+
+def test_mixed_solve_config1(ctx, tb):
+    """The mixed operator's solution of the 320-triangle workload to 1e-8 (its own residual),
+    then its residual against the FP64 operator and its distance to the FP64 solution."""
+    import torch
+    c = get_config("sphere320_eq10")
+    xyz, tri = c["mesh"]
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "bump")
+    ctx.assemble(tb.MIXED)
+    g = ctx.rhs_plane_pulse(c["direction"], c["t0"], c["width"])
+    a32, rep = ctx.solve(g, tol=1e-8, precond_inner=(2, 10), max_it=4000)
+    assert rep["converged"]
+    ctx.assemble(tb.FP64)
+    a64, rep = ctx.solve(g, tol=1e-8, precond_inner=(2, 10), max_it=4000)
+    assert rep["converged"]
+    r = g - ctx.matvec(a32)
+    assert torch.linalg.norm(r).item() <= 1e-5 * torch.linalg.norm(g).item()
+    assert torch.linalg.norm(a32 - a64).item() <= 1e-4 * torch.linalg.norm(a64).item()
 
 
 # --- RHS, matvec, solve ----------------------------------------------------------------------
