@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere5120_graded64")
-X
+    ap.add_argument("--precond", default="2,10", help="Algorithm 1 inner iterations per level ('' = none)")
     ap.add_argument("--restart", type=int, default=300)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=300)
