@@ -27,12 +27,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X, published
-# Algorithmic FP64 flops of one quadrature evaluation: two Clenshaw series of degree D
-# (per step one FMA and one subtraction: 3 flops; final step 3 flops) plus the map to the
-# piece variable (2 flops) and the accumulation (weight 1, product 1, three FMAs 6, one FMA 2).
+# Algorithmic FP64 flops of one quadrature evaluation: the Chebyshev polynomials T_2..T_D of
+# the piece variable by their three-term recurrence (one FMA each), the two series psi and
+# tilde psi (one FMA per term), the map of r to the piece variable (2), the weight w_q w_q'/r
+# (2) and the accumulation (psi w, three products and sums with lam_b, tilde psi w and its sum: 9).
 CHEB_DEGREE = 14
-FLOPS_PER_QUAD_EVAL = 2 * (3 * CHEB_DEGREE + 3) + 2 + 10
-REGULAR_KERNEL = "k_regular_wave"
+FLOPS_PER_QUAD_EVAL = 2 * (CHEB_DEGREE - 1) + 2 * 2 * CHEB_DEGREE + 2 + 2 + 9
+REGULAR_KERNEL = "k_regular_tile"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07221_amd", "csrc", "k_assemble.hip")
 
 

@@ -242,12 +242,15 @@ constexpr int kTileEl = kTilePairs * 49;             // 1568
 constexpr int kTileSort = 2048;
 constexpr int kTileThreads = 256;
 constexpr int kTileVt = 3 * kTileT, kTileVs = 3 * kTileS;
-constexpr int kTileR = kTilePairs * 7 * 4;
+constexpr int kTileR = kTilePairs * (7 * 3 + 1);     // R_b per (q, b, pair), then T per pair
 
 struct TileLds {
     double key[kTileSort];
-    double R[2][kTileR];             // (q, {R_0, R_1, R_2, T}, pair): sum_q' lam_b(q') psi w/r, sum_q' tpsi w/r
+    double R[2][kTileR];             // R_b(q, pair) = sum_q' lam_b(q') psi w/r; T(pair) = sum tpsi w/r
     double acc[kTileVt * kTileVs];
+    double alpha[kTilePairs];        // (n_tau . n_sigma) |tau||sigma| / (4 pi)
+    double beta[kTilePairs * 9];     // C_ab |tau||sigma| / (4 pi), entry e = 3a + b
+    uint16_t aoff[kTilePairs * 9];   // entry (v_a(tau), v_b(sigma)) of the merged vertex tile
     double wqq[49];                  // w_q w_q'
     double lam[7 * 3];               // lam_b(q')
     double pmin[kTilePairs], pmax[kTilePairs];
@@ -379,35 +382,34 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
     if (nvalid == 0) return;                      // uniform: the whole workgroup leaves
     const double wmin = L.key[0], wmax = L.key[nvalid - 1];
 
-    // contraction lanes: pair gp, local entry gm = 3a + b (gm == 0 also takes entry 8)
-    const int ctau = tau0 + gp / kTileS, csig = sig0 + gp % kTileS;
-    const bool pvalid = L.pok[gp] != 0;
-    const double pmn = L.pmin[gp], pmx = L.pmax[gp];
-    const int ea = gm / 3, eb = gm % 3;
-    double nn = 0.0, Cm = 0.0, C8 = 0.0, scale = 0.0;
-    int om = 0, o8 = 0;
-    if (pvalid) {
-        nn = g.n[ctau] * g.n[csig] + g.n[E + ctau] * g.n[E + csig] + g.n[2 * E + ctau] * g.n[2 * E + csig];
-        Cm = g.curl[(3 * ea) * E + ctau] * g.curl[(3 * eb) * E + csig] +
-             g.curl[(3 * ea + 1) * E + ctau] * g.curl[(3 * eb + 1) * E + csig] +
-             g.curl[(3 * ea + 2) * E + ctau] * g.curl[(3 * eb + 2) * E + csig];
-        C8 = g.curl[6 * E + ctau] * g.curl[6 * E + csig] + g.curl[7 * E + ctau] * g.curl[7 * E + csig] +
-             g.curl[8 * E + ctau] * g.curl[8 * E + csig];
-        scale = g.area[ctau] * g.area[csig] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
-        const int vl = g.v[ea * E + ctau], vj = g.v[eb * E + csig];
-        const int vl8 = g.v[2 * E + ctau], vj8 = g.v[2 * E + csig];
-        int xl = 0, xj = 0, xl8 = 0, xj8 = 0;
-        for (int u = 0; u < L.nvt; ++u) {
-            xl = L.vt[u] == vl ? u : xl;
-            xl8 = L.vt[u] == vl8 ? u : xl8;
+    // contraction tables of every pair: lane (pair gp, entry gm = 3a + b; gm == 0 also entry 8)
+    {
+        const int ctau = tau0 + gp / kTileS, csig = sig0 + gp % kTileS;
+        for (int e = gm; e < 9; e += 8) {
+            double beta = 0.0;
+            int off = 0;
+            if (L.pok[gp]) {
+                const int ea = e / 3, eb = e % 3;
+                const double scale = g.area[ctau] * g.area[csig] * 0.07957747154594767;   // |tau||sigma|/(4 pi)
+                beta = (g.curl[(3 * ea) * E + ctau] * g.curl[(3 * eb) * E + csig] +
+                        g.curl[(3 * ea + 1) * E + ctau] * g.curl[(3 * eb + 1) * E + csig] +
+                        g.curl[(3 * ea + 2) * E + ctau] * g.curl[(3 * eb + 2) * E + csig]) * scale;
+                if (e == 0)
+                    L.alpha[gp] = (g.n[ctau] * g.n[csig] + g.n[E + ctau] * g.n[E + csig] +
+                                   g.n[2 * E + ctau] * g.n[2 * E + csig]) * scale;
+                const int vl = g.v[ea * E + ctau], vj = g.v[eb * E + csig];
+                int xl = 0, xj = 0;
+                for (int u = 0; u < L.nvt; ++u) xl = L.vt[u] == vl ? u : xl;
+                for (int u = 0; u < L.nvs; ++u) xj = L.vs[u] == vj ? u : xj;
+                off = xl * kTileVs + xj;
+            } else if (e == 0) {
+                L.alpha[gp] = 0.0;
+            }
+            L.beta[9 * gp + e] = beta;
+            L.aoff[9 * gp + e] = (uint16_t)off;
         }
-        for (int u = 0; u < L.nvs; ++u) {
-            xj = L.vs[u] == vj ? u : xj;
-            xj8 = L.vs[u] == vj8 ? u : xj8;
-        }
-        om = xl * kTileVs + xj;
-        o8 = xl8 * kTileVs + xj8;
     }
+    __syncthreads();
 
     const int N = tv.N;
     double2 cc[kNc];            // coefficients of the lane's current piece
@@ -443,6 +445,17 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
             double* __restrict__ Rb = L.R[buf];
             rhi = -1.0;                                  // new kernel: no cached piece
             pcur = -1;
+            if (MIXED) {
+                // mixed precision, decided for the whole wave: FP32 series when every distance
+                // of the wave's stretch is in the far field and away from the two flat ends of
+                // the support (the first half of the first interval, the second half of the
+                // last), FP64 otherwise
+                const int wa = (tid & ~63) * C, wb = min(n, ((tid & ~63) + 64) * C);
+                const double* iv = tv.ivl + kd.bp_off;
+                const double lo_end = iv[0] + 0.5 / iv[1];
+                const double hi_start = iv[2 * (kd.nint - 1)] + 0.5 / iv[2 * kd.nint - 1];
+                c32 = wa < wb && L.key[s0 + wa] >= r_far && L.key[s0 + wa] >= lo_end && L.key[s0 + wb - 1] < hi_start;
+            }
             for (int u = tid * C; u < u1; ++u) {
                 const int s = s0 + u;
                 const double r = L.key[s];
@@ -467,8 +480,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                     const int64_t off = g * kNc;
                     // mixed precision: far-field pieces away from the two ends of the support
                     // evaluate the FP32 copy of the series
-                    c32 = MIXED && r >= r_far && mt.w == 0.0;
-                    if (c32) {
+                    if (MIXED && c32) {
 #pragma unroll
                         for (int m = 0; m < kNc; ++m) {
                             const float2 v = tv.coef32[off + m];
@@ -493,29 +505,30 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                 const int pr = code >> 6, q = (code >> 3) & 7, qp = code & 7;
                 const double w = L.wqq[7 * q + qp] * recip(r);
                 const double P = ps * w;
-                double* Rq = Rb + q * 4 * kTilePairs + pr;
+                double* Rq = Rb + q * 3 * kTilePairs + pr;
                 atomicAdd(Rq, P * L.lam[3 * qp]);
                 atomicAdd(Rq + kTilePairs, P * L.lam[3 * qp + 1]);
                 atomicAdd(Rq + 2 * kTilePairs, P * L.lam[3 * qp + 2]);
-                atomicAdd(Rq + 3 * kTilePairs, pt * w);
+                atomicAdd(Rb + 21 * kTilePairs + pr, pt * w);
                 ++nq;
             }
             __syncthreads();
             // the other buffer was read by the previous (k, i): clear it for the next one
             for (int z = tid; z < kTileR; z += kTileThreads) L.R[buf ^ 1][z] = 0.0;
-            if (pvalid && pmx > kd.lo && pmn < kd.hi) {
+            if (L.pok[gp] && L.pmax[gp] > kd.lo && L.pmin[gp] < kd.hi) {
                 const double* Rp = Rb + gp;
-                double Sm = 0.0, S8 = 0.0, ST = 0.0;
+                const int ea = gm / 3, eb = gm % 3;
+                double Sm = 0.0, S8 = 0.0;
 #pragma unroll
                 for (int q = 0; q < 7; ++q) {
                     double l0, l1, l2, w;
                     rule7_point(q, l0, l1, l2, w);
-                    Sm = fma(ea == 0 ? l0 : (ea == 1 ? l1 : l2), Rp[(4 * q + eb) * kTilePairs], Sm);
-                    S8 = fma(l2, Rp[(4 * q + 2) * kTilePairs], S8);
-                    ST += Rp[(4 * q + 3) * kTilePairs];
+                    Sm = fma(ea == 0 ? l0 : (ea == 1 ? l1 : l2), Rp[(3 * q + eb) * kTilePairs], Sm);
+                    S8 = fma(l2, Rp[(3 * q + 2) * kTilePairs], S8);
                 }
-                atomicAdd(&L.acc[om], (nn * Sm + Cm * ST) * scale);
-                if (gm == 0) atomicAdd(&L.acc[o8], (nn * S8 + C8 * ST) * scale);
+                const double ST = Rp[21 * kTilePairs], al = L.alpha[gp];
+                atomicAdd(&L.acc[L.aoff[9 * gp + gm]], fma(al, Sm, L.beta[9 * gp + gm] * ST));
+                if (gm == 0) atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * ST));
             }
             __syncthreads();
             for (int z = tid; z < kTileVt * kTileVs; z += kTileThreads) {
