@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X, published
+HBM_PEAK_GBS = 8000.0
 # Algorithmic FP64 flops of one quadrature evaluation: the Chebyshev polynomials T_2..T_D of
 # the piece variable by their three-term recurrence (one FMA each), the two series psi and
 # tilde psi (one FMA per term), the map of r to the piece variable (2), the weight w_q w_q'/r
@@ -160,6 +161,21 @@ def main():
                                 out=out)
         return rep, srep
 
+    def time_matvec(launches=20):
+        """Average time of a full block matvec y = A x (HIP events on the library's stream)."""
+        x = torch.randn(n, dtype=torch.float64, device="cuda:0",
+                        generator=torch.Generator(device="cuda:0").manual_seed(12))
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ctx.matvec(x, out=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            ctx.matvec(x, out=y)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / launches
+
     def note(tag, rep, srep):
         s = f"# {tag}: assembly {rep['ms_total']:.1f} ms (regular {rep['ms_regular']:.1f})"
         if srep:
@@ -213,6 +229,9 @@ def main():
                      "flops_per_quad_eval": FLOPS_PER_QUAD_EVAL, "launch_ms": reg_ms,
                      "quad_evals_per_launch": int(quad_reg)},
     }
+    mv_ms = time_matvec()
+    out["matvec"] = {"fp64_ms": mv_ms, "fp64_GBps": reps[-1]["bytes_matrix"] / (mv_ms * 1e-3) / 1e9,
+                     "hbm_peak_GBps": HBM_PEAK_GBS, "fp64_frac": reps[-1]["bytes_matrix"] / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.skip_solve:
         out["solve"] = {"ms": float(np.mean([s["ms"] for s in sreps])), "iterations": int(sreps[-1]["iterations"]),
                         "matvecs": int(sreps[-1]["matvecs"]), "rel_residual": float(sreps[-1]["rel_residual"]),
@@ -230,6 +249,8 @@ def main():
         note("mixed", mrep, msrep)
         y32 = ctx.matvec(xr)
         e32 = ctx.get_entries(ks, is_, js, ls)
+        mv32 = time_matvec()
+        out["matvec"].update({"mixed_ms": mv32, "mixed_GBps": mrep["bytes_matrix"] / (mv32 * 1e-3) / 1e9})
         mixed = {"assembly_ms": mrep["ms_total"], "regular_ms": mrep["ms_regular"],
                  "value": mrep["quad_evals"] / (mrep["ms_total"] * 1e-3), "matrix_bytes": int(mrep["bytes_matrix"]),
                  "matvec_rel_err_vs_fp64": float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)),
