@@ -591,32 +591,33 @@ static tdbem_status build_tables(tdbem_ctx* c)
 static tdbem_status build_layout(tdbem_ctx* c, int prec)
 {
     const int64_t M = c->M, N = c->N;
-    const int64_t T = (M + kBT - 1) / kBT;
-    const int64_t per_k = T * (T + 1) / 2 * kBT * kBT;     // tile slots of one time row
+    const int64_t T = (M + kBT - 1) / kBT, nt = T * (T + 1) / 2;
+    const int64_t per_k = nt * kBT * kBT;     // tile slots of one time row
     ALLOC(c, c->d_ilo, sizeof(int16_t) * (size_t)(N * per_k));
     HIPCHK(c, hipMemsetAsync(c->d_ilo.p, 0, sizeof(int16_t) * (size_t)(N * per_k), c->stream));
-    ALLOC(c, c->d_B, sizeof(int32_t) * N);
-    HIPCHK(c, hipMemsetAsync(c->d_B.p, 0, sizeof(int32_t) * N, c->stream));
+    ALLOC(c, c->d_B, sizeof(int32_t) * (size_t)(N * nt));
     launch_layout(c->band(), c->d_xyz.as<double>(), c->d_rho.as<double>(), c->d_t.as<double>(), c->d_ilo.as<int16_t>(),
                   c->d_B.as<int32_t>(), c->stream);
     HIPCHK(c, hipGetLastError());
-    c->Bk.assign(N, 0);
-    HIPCHK(c, hipMemcpyAsync(c->Bk.data(), c->d_B.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, c->stream));
+    c->Bk.assign((size_t)(N * nt), 0);
+    HIPCHK(c, hipMemcpyAsync(c->Bk.data(), c->d_B.p, sizeof(int32_t) * (size_t)(N * nt), hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->voff.assign(N, 0);
+    c->voff.assign((size_t)(N * nt), 0);
     int64_t tot = 0;
-    for (int k = 0; k < N; ++k) {
-        c->voff[k] = tot;
-        tot += (int64_t)c->Bk[k] * per_k;
+    for (int64_t q = 0; q < N * nt; ++q) {
+        c->voff[q] = tot;
+        tot += (int64_t)c->Bk[q] * kBT * kBT;
     }
     c->nvals = tot;
     TRY(upload(c, c->d_voff, c->voff.data(), c->voff.size()));
     const size_t esz = prec == TDBEM_FP64 ? sizeof(double) : sizeof(float);
+    c->d_val.release();                    // a previous assembly's values count as free memory
     size_t freeb = 0, totb = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemGetInfo(&freeb, &totb));
     const size_t need = esz * (size_t)std::max<int64_t>(tot, 1);
     if (need + (size_t)(1ull << 30) > freeb) {
-        c->d_val.release();
         FAIL(c, TDBEM_ENOMEM, "band storage needs %.2f GB, %.2f GB free on the device", need / 1e9, freeb / 1e9);
     }
     ALLOC(c, c->d_val, need);

@@ -71,22 +71,29 @@ k_geometry(const double* __restrict__ xyz, const int32_t* __restrict__ tri, int 
 }
 
 // Band of trial indices i for the time row k and a distance range (dmin, dmax): those with
-// lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).  Block
-// (j chunk, l); lanes with j > l idle (lower triangle only).
+// lo_{k,i} < dmax and hi_{k,i} > dmin.  Both bounds move right with k (two pointers).  Block =
+// one 64 x 64 vertex tile t; lane (row l, column j) for 16 rows per wave; pairs with j > l or past
+// M idle.  The tile's band width per time row is the maximum over its pairs (LDS), written whole.
 __global__ void __launch_bounds__(256)
 k_layout(BandView band, const double* __restrict__ xyz, const double* __restrict__ rho,
-         const double* __restrict__ t, int16_t* __restrict__ ilo, int32_t* __restrict__ Bk)
+         const double* __restrict__ t, int16_t* __restrict__ ilo, int32_t* __restrict__ Bt)
 {
     const int M = band.M, N = band.N;
     extern __shared__ int32_t sB[];
     for (int k = threadIdx.x; k < N; k += blockDim.x) sB[k] = 0;
     __syncthreads();
-    const int l = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j <= l) {
+    const int tt = blockIdx.x;
+    int tl = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+    while ((tl + 1) * (tl + 2) / 2 <= tt) ++tl;
+    while (tl * (tl + 1) / 2 > tt) --tl;
+    const int tj = tt - tl * (tl + 1) / 2;
+    const int j = tj * kBT + (threadIdx.x & 63);
+    const double slack = 1e-12 * (1.0 + t[N - 1]);
+    for (int m = 0; m < 16; ++m) {
+        const int l = tl * kBT + (threadIdx.x >> 6) + 4 * m;
+        if (l >= M || j > l) continue;
         const double dx = xyz[3 * l] - xyz[3 * j], dy = xyz[3 * l + 1] - xyz[3 * j + 1], dz = xyz[3 * l + 2] - xyz[3 * j + 2];
         const double d = sqrt(dx * dx + dy * dy + dz * dz);
-        const double slack = 1e-12 * (1.0 + t[N - 1]);
         const double dmax = d + rho[l] + rho[j] + slack;
         double dmin = d - rho[l] - rho[j] - slack;
         dmin = dmin > 0.0 ? dmin : 0.0;
@@ -111,8 +118,7 @@ k_layout(BandView band, const double* __restrict__ xyz, const double* __restrict
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < N; k += blockDim.x)
-        if (sB[k] > 0) atomicMax(&Bk[k], sB[k]);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) Bt[(int64_t)k * band.nt + tt] = sB[k];
 }
 
 __device__ inline double wave_min(double v)
@@ -148,7 +154,7 @@ __device__ inline void scatter_half(const BandView& band, double* val, float* va
     if (j > l) { const int tmp = j; j = l; l = tmp; }
     if (j == l) v *= 2.0;
     const int s = i - (int)band.ilo[band_ilo_index(band, k, l, j)];
-    const int B = band.B[k];
+    const int B = band_width(band, k, l, j);
     if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
     const int64_t idx = band_value_index(band, k, l, j, s, B);
     if (valf) atomicAdd(valf + idx, (float)v);
@@ -711,7 +717,7 @@ k_get_entries(BandView band, const double* __restrict__ val, const float* __rest
     if (jj > ll) { const int tmp = jj; jj = ll; ll = tmp; }   // symmetric blocks: lower triangle
     double v = 0.0;
     if (kk >= 0 && kk < band.N && ii >= 0 && ii < band.N && jj >= 0 && ll < band.M) {
-        const int B = band.B[kk];
+        const int B = band_width(band, kk, ll, jj);
         const int sl = ii - (int)band.ilo[band_ilo_index(band, kk, ll, jj)];
         if (sl >= 0 && sl < B) {
             const int64_t idx = band_value_index(band, kk, ll, jj, sl, B);
@@ -730,11 +736,11 @@ void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P
                        geo_curl, geo_qp, geo_v);
 }
 
-void launch_layout(BandView band, const double* xyz, const double* rho, const double* t, int16_t* ilo, int32_t* Bk,
+void launch_layout(BandView band, const double* xyz, const double* rho, const double* t, int16_t* ilo, int32_t* Bt,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layout, dim3(grid_for(band.M, 256), band.M), dim3(256), sizeof(int32_t) * band.N, s, band,
-                       xyz, rho, t, ilo, Bk);
+    hipLaunchKernelGGL(k_layout, dim3((unsigned)band.nt), dim3(256), sizeof(int32_t) * band.N, s, band, xyz, rho, t,
+                       ilo, Bt);
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,

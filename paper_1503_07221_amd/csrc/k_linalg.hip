@@ -90,9 +90,9 @@ k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, 
 {
     const int M = band.M;
     const int k = k0 + blockIdx.y;
-    const int B = band.B[k];
-    if (B == 0) return;                        // no stored values in this time row
     const int t = blockIdx.x;
+    const int B = band.B[(int64_t)k * band.nt + t];
+    if (B == 0) return;                        // no stored values in this (time row, tile)
     int tl = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((tl + 1) * (tl + 2) / 2 <= t) ++tl;
     while (tl * (tl + 1) / 2 > t) --tl;
@@ -100,7 +100,7 @@ k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = tj * kBT + lane;
     const int16_t* __restrict__ il = band.ilo + ((int64_t)k * band.nt + t) * (kBT * kBT) + lane;
-    const VT* __restrict__ vt = val + band.voff[k] + (int64_t)t * kBT * kBT * B + lane;
+    const VT* __restrict__ vt = val + band.voff[(int64_t)k * band.nt + t] + lane;
     double* __restrict__ yk = y + (int64_t)(k - k0) * M;
     __shared__ double s_row[4][16][65];
     __shared__ double s_col[4][64];

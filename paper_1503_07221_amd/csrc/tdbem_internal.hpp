@@ -238,13 +238,14 @@ struct GeomView {
 
 // Band storage of the blocks.  Every block is symmetric in (j, l), so only the lower triangle
 // j <= l is kept.  For every vertex pair (l, j <= l) and time row k the trial indices
-// i = ilo + s, s < B_k, are those whose kernel support meets the conservative distance range of
-// the two hats (eq. (SparsitySmallBlock)).  The triangle is cut into 64 x 64 vertex tiles
-// (tl, tj <= tl), numbered t = tl(tl+1)/2 + tj (nt of them); per time row k the tiles follow
-// each other and a tile holds [row l % 64][slot s][column j % 64], so the values a workgroup of
-// the matvec reads form one contiguous stretch:
+// i = ilo + s, s < B, are those whose kernel support meets the conservative distance range of the
+// two hats (eq. (SparsitySmallBlock)).  The triangle is cut into 64 x 64 vertex tiles
+// (tl, tj <= tl), numbered t = tl(tl+1)/2 + tj (nt of them).  Each (time row k, tile t) has its
+// own band width B = B[k nt + t] (the widest band of its vertex pairs) and holds
+// [row l % 64][slot s][column j % 64] from voff[k nt + t] on, so the values a workgroup of the
+// matvec reads form one contiguous stretch:
 //   ilo[(k nt + t) 4096 + (l % 64) 64 + j % 64]
-//   val[voff[k] + ((t 64 + l % 64) B_k + s) 64 + j % 64]
+//   val[voff[k nt + t] + ((l % 64) B + s) 64 + j % 64]
 // Tile entries outside the triangle or past M stay zero.
 constexpr int kBT = 64;
 __host__ __device__ inline int64_t tri_index(int64_t l, int64_t j) { return l * (l + 1) / 2 + j; }
@@ -252,8 +253,8 @@ __host__ __device__ inline int64_t band_tile(int64_t l, int64_t j) { return tri_
 
 struct BandView {
     const int16_t* ilo;    // first trial index of every (k, l, j <= l), tiled as above
-    const int32_t* B;      // B[k]
-    const int64_t* voff;   // voff[k]
+    const int32_t* B;      // B[k nt + t]
+    const int64_t* voff;   // voff[k nt + t]
     int32_t M, N;
     int64_t nt;            // tiles per time row
 };
@@ -263,9 +264,15 @@ __host__ __device__ inline int64_t band_ilo_index(const BandView& b, int k, int6
     return ((int64_t)k * b.nt + band_tile(l, j)) * (kBT * kBT) + (l % kBT) * kBT + j % kBT;
 }
 
+// Band width and first value of the (k, tile of (l, j)) block.
+__device__ inline int band_width(const BandView& b, int k, int64_t l, int64_t j)
+{
+    return b.B[(int64_t)k * b.nt + band_tile(l, j)];
+}
+
 __device__ inline int64_t band_value_index(const BandView& b, int k, int64_t l, int64_t j, int s, int B)
 {
-    return b.voff[k] + ((band_tile(l, j) * kBT + l % kBT) * (int64_t)B + s) * kBT + j % kBT;
+    return b.voff[(int64_t)k * b.nt + band_tile(l, j)] + ((l % kBT) * (int64_t)B + s) * kBT + j % kBT;
 }
 
 }  // namespace tdbem
