@@ -58,7 +58,8 @@ typedef enum {
 typedef struct {
     int32_t device;              /* HIP device ordinal */
     void *stream;                /* hipStream_t to run on; NULL: the library creates one */
-    int32_t ss_order;            /* Gauss points per direction of the Sauter-Schwab rules (4) */
+    int32_t ss_order;            /* Gauss points per direction of the Sauter-Schwab rules, 1..5
+                                    (<= 0: 4); larger values give TDBEM_EINVAL */
 } tdbem_options;
 
 typedef struct {

@@ -287,7 +287,7 @@ tdbem_status tdbem_create(tdbem_ctx** out, const tdbem_options* opt)
     tdbem_ctx* c = new tdbem_ctx();
     c->device = opt ? opt->device : 0;
     c->ss_order = opt && opt->ss_order > 0 ? opt->ss_order : 4;
-    if (c->ss_order > 12) { delete c; return TDBEM_EINVAL; }
+    if (c->ss_order > 5) { delete c; return TDBEM_EINVAL; }   // <= 6 * 5^4 points per pair (sorted in LDS)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
         (void)hipGetLastError();
@@ -658,9 +658,10 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
                    c->ntiles, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
     launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
-                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), v64, v32, cnt + 1,
-                    c->stream);
+                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, v64, v32,
+                    cnt + 1, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

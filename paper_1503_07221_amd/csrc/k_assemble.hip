@@ -553,156 +553,182 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Singular pairs.  One lane per (pair, k).  pairs[9*s..]: tau, sigma, kind (0 coincident,
-// 1 edge, 2 vertex), the local indices of the reference vertices (A, B, C) in tau and in sigma.
-// The rule rows are (x1, x2, y1, y2, w) on the reference triangle {0 <= x2 <= x1 <= 1}, the
-// physical point A + x1 (B - A) + x2 (C - B) with barycentrics (1 - x1, x1 - x2, x2).
+// Singular pairs.  pairs[9*s..]: tau, sigma, kind (0 coincident, 1 edge, 2 vertex), the local
+// indices of the reference vertices (A, B, C) in tau and in sigma.  The rule rows are
+// (x1, x2, y1, y2, w) on the reference triangle {0 <= x2 <= x1 <= 1}, the physical point
+// A + x1 (B - A) + x2 (C - B) with barycentrics (1 - x1, x1 - x2, x2).
+// One workgroup per pair: the distances of the pair's Sauter-Schwab points are sorted once in
+// LDS; the lanes then take (k, i) kernels, each walking the contiguous range of sorted points
+// inside its support with the piece record of its current Chebyshev piece in registers (sorted
+// distances move through the pieces in order), the nine local sums in registers, and nine
+// scatters at the end.
 // ---------------------------------------------------------------------------------------------
-constexpr int kSingBand = 6;
+constexpr int kSingThreads = 256;
+constexpr int kSingU = 8;      // trial indices of one time row taken in one round
 
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(kSingThreads)
 k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, const int32_t* __restrict__ pairs,
-           int64_t npairs, const double* __restrict__ rules, const int32_t* __restrict__ roff,
-           const int32_t* __restrict__ rcnt, double* val, float* valf, unsigned long long* counter)
+           const double* __restrict__ rules, const int32_t* __restrict__ roff, const int32_t* __restrict__ rcnt,
+           int P, double* val, float* valf, unsigned long long* counter)
 {
-    __shared__ PieceTable spt;
-    load_piece_table(spt, tv.pt);
-    __syncthreads();
-    const int N = tv.N;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long nq = 0;
-    if (gid < npairs * N) {
-        const int64_t s = gid / N;
-        const int k = (int)(gid - s * N);
-        const int E = g.E;
-        const int32_t* pr = pairs + 9 * s;
-        const int tau = pr[0], sig = pr[1], kind = pr[2];
-        int px[3] = {pr[3], pr[4], pr[5]}, py[3] = {pr[6], pr[7], pr[8]};
-        double X[3][3], Y[3][3];   // reference vertices A, B, C
-        for (int a = 0; a < 3; ++a)
+    extern __shared__ double sing_lds[];
+    double* key = sing_lds;                                   // P sorted distances
+    uint16_t* idx = reinterpret_cast<uint16_t*>(sing_lds + P);   // their rule rows
+    const int tid = threadIdx.x;
+    const int E = g.E, N = tv.N;
+    const int32_t* pr = pairs + 9 * (int64_t)blockIdx.x;
+    const int tau = pr[0], sig = pr[1], kind = pr[2];
+    const int px[3] = {pr[3], pr[4], pr[5]}, py[3] = {pr[6], pr[7], pr[8]};
+    double X[3][3], Y[3][3];   // reference vertices A, B, C
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) {
+            X[a][c] = g.P[(3 * px[a] + c) * E + tau];
+            Y[a][c] = g.P[(3 * py[a] + c) * E + sig];
+        }
+    const int npts = rcnt[kind];
+    const double* rule = rules + 5 * (int64_t)roff[kind];
+    for (int q = tid; q < P; q += kSingThreads) {
+        double r = INFINITY;
+        if (q < npts) {
+            const double* R = rule + 5 * q;
+            const double x1 = R[0], x2 = R[1], y1 = R[2], y2 = R[3];
+            const double lx0 = 1.0 - x1, lx1 = x1 - x2, lx2 = x2;
+            const double ly0 = 1.0 - y1, ly1 = y1 - y2, ly2 = y2;
+            double d2 = 0.0;
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
-                X[a][c] = g.P[(3 * px[a] + c) * E + tau];
-                Y[a][c] = g.P[(3 * py[a] + c) * E + sig];
+                const double xc = lx0 * X[0][c] + lx1 * X[1][c] + lx2 * X[2][c];
+                const double yc = ly0 * Y[0][c] + ly1 * Y[1][c] + ly2 * Y[2][c];
+                d2 += (xc - yc) * (xc - yc);
             }
-        double rmax = 0.0;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                const double d0 = X[a][0] - Y[b][0], d1 = X[a][1] - Y[b][1], d2 = X[a][2] - Y[b][2];
-                rmax = fmax(rmax, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+            r = sqrt(d2);
+        }
+        key[q] = r;
+        idx[q] = (uint16_t)q;
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int u = tid; u < P / 2; u += kSingThreads) {
+                const int lo = 2 * stride * (u / stride) + (u % stride);
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double ka = key[lo], kb = key[hi];
+                if ((ka > kb) == up) {
+                    key[lo] = kb;
+                    key[hi] = ka;
+                    const uint16_t ia = idx[lo];
+                    idx[lo] = idx[hi];
+                    idx[hi] = ia;
+                }
             }
-        rmax *= 1.0 + 1e-12;
-        int ia = 0;
-        while (ia < N) {
+        }
+    __syncthreads();
+    const double rmax = key[npts - 1];
+    const double nn = g.n[tau] * g.n[sig] + g.n[E + tau] * g.n[E + sig] + g.n[2 * E + tau] * g.n[2 * E + sig];
+    const double jac = 4.0 * g.area[tau] * g.area[sig];
+    unsigned long long nq = 0;
+    for (int c = tid; c < N * kSingU; c += kSingThreads) {
+        const int k = c / kSingU, u = c - kSingU * (c / kSingU);
+        // first trial index whose support starts below rmax (lo_{k,i} falls as i grows); the
+        // supports of i > k + 1 are empty
+        int ia = 0, span = k + 2 < N ? k + 2 : N;
+        while (span > 0) {
+            const int h = span >> 1;
             double lo, hi;
-            kernel_support(t, N, k, ia, lo, hi);
-            if (lo < rmax) break;
-            ++ia;
+            kernel_support(t, N, k, ia + h, lo, hi);
+            if (lo < rmax) span = h;
+            else { ia += h + 1; span -= h + 1; }
         }
-        int ib = ia - 1;
-        while (ib + 1 < N) {
-            double lo, hi;
-            kernel_support(t, N, k, ib + 1, lo, hi);
-            if (!(hi > 0.0)) break;
-            ++ib;
-        }
-        const double nn = g.n[tau] * g.n[sig] + g.n[E + tau] * g.n[E + sig] + g.n[2 * E + tau] * g.n[2 * E + sig];
-        const double jac = 4.0 * g.area[tau] * g.area[sig];
-        const double scale = 0.07957747154594767;   // 1/(4 pi)
-        // reference-order vertex ids and curl products (static register indices below)
-        int vtr[3], vsr[3];
-        double Cr[3][3];
-        for (int al = 0; al < 3; ++al) {
-            vtr[al] = g.v[px[al] * E + tau];
-            vsr[al] = g.v[py[al] * E + sig];
-        }
-        for (int al = 0; al < 3; ++al)
-            for (int be = 0; be < 3; ++be)
-                Cr[al][be] = g.curl[(3 * px[al]) * E + tau] * g.curl[(3 * py[be]) * E + sig] +
-                             g.curl[(3 * px[al] + 1) * E + tau] * g.curl[(3 * py[be] + 1) * E + sig] +
-                             g.curl[(3 * px[al] + 2) * E + tau] * g.curl[(3 * py[be] + 2) * E + sig];
-        const int npts = rcnt[kind];
-        const double* rule = rules + 5 * (int64_t)roff[kind];
-        for (int i0 = ia; i0 <= ib; i0 += kSingBand) {
-            const int nb = (ib - i0 + 1) < kSingBand ? (ib - i0 + 1) : kSingBand;
-            KernelDesc kd[kSingBand];
-            bool have[kSingBand];
-#pragma unroll
-            for (int u = 0; u < kSingBand; ++u) {
-                const int f = u < nb ? tv.fid[k * N + i0 + u] : -1;
-                have[u] = f >= 0;
-                if (have[u]) kd[u] = tv.desc[f];
-                else { kd[u].lo = 1.0; kd[u].hi = 0.0; kd[u].nint = 0; kd[u].bp_off = 0; kd[u].coef_off = 0; }
+        const int ib = k + 1 < N - 1 ? k + 1 : N - 1;
+        for (int i = ia + u; i <= ib; i += kSingU) {
+            const int f = tv.fid[k * N + i];
+            if (f < 0) continue;
+            const KernelDesc kd = tv.desc[f];
+            // sorted range inside the open support (lo, hi)
+            int s0 = 0, s1 = 0;
+            {
+                int b = 0, n = npts;
+                while (n > 0) { const int h = n >> 1; if (key[b + h] <= kd.lo) { b += h + 1; n -= h + 1; } else n = h; }
+                s0 = b;
+                b = 0; n = npts;
+                while (n > 0) { const int h = n >> 1; if (key[b + h] < kd.hi) { b += h + 1; n -= h + 1; } else n = h; }
+                s1 = b;
             }
-            double S1[kSingBand][9], S2[kSingBand];
+            if (s1 <= s0) continue;
+            double S1[9], S2 = 0.0;
 #pragma unroll
-            for (int u = 0; u < kSingBand; ++u) {
-                S2[u] = 0.0;
+            for (int m = 0; m < 9; ++m) S1[m] = 0.0;
+            double2 cc[kNc];
+            double rhi = -1.0, rc = 0.0, ra = 0.0;
+            int64_t gcur = -1;
+            for (int sidx = s0; sidx < s1; ++sidx) {
+                const double r = key[sidx];
+                if (r >= rhi) {
+                    int64_t gp;
+                    if (gcur < 0) {
+                        int cl = (int)((r - kd.lo) * kd.cell_scale);
+                        cl = cl < 0 ? 0 : (cl < kCells ? cl : kCells - 1);
+                        gp = kd.coef_off / kNc + tv.cell[kd.cell_off + cl];
+                    } else {
+                        gp = gcur + 1;
+                    }
+                    double4 mt = tv.meta[gp];
+                    while (r >= mt.x) mt = tv.meta[++gp];
+                    gcur = gp;
+                    rhi = mt.x;
+                    rc = mt.y;
+                    ra = mt.z;
 #pragma unroll
-                for (int m = 0; m < 9; ++m) S1[u][m] = 0.0;
-            }
-            for (int q = 0; q < npts; ++q) {
-                const double* R = rule + 5 * q;
+                    for (int m = 0; m < kNc; ++m) cc[m] = tv.coef[gp * kNc + m];
+                }
+                double ps, pt;
+                cheb_sums(cc, (r - rc) * ra, ps, pt);
+                const double* R = rule + 5 * idx[sidx];
                 const double x1 = R[0], x2 = R[1], y1 = R[2], y2 = R[3];
-                const double w = R[4] * jac;
+                const double wr = R[4] * jac / r;
                 const double lx0 = 1.0 - x1, lx1 = x1 - x2, lx2 = x2;
                 const double ly0 = 1.0 - y1, ly1 = y1 - y2, ly2 = y2;
-                double d2 = 0.0;
+                const double f1 = ps * wr;
+                const double R0 = f1 * ly0, R1 = f1 * ly1, R2 = f1 * ly2;
+                S1[0] = fma(lx0, R0, S1[0]); S1[1] = fma(lx0, R1, S1[1]); S1[2] = fma(lx0, R2, S1[2]);
+                S1[3] = fma(lx1, R0, S1[3]); S1[4] = fma(lx1, R1, S1[4]); S1[5] = fma(lx1, R2, S1[5]);
+                S1[6] = fma(lx2, R0, S1[6]); S1[7] = fma(lx2, R1, S1[7]); S1[8] = fma(lx2, R2, S1[8]);
+                S2 = fma(pt, wr, S2);
+            }
+            nq += (unsigned long long)(s1 - s0);
+            const double scale = 0.07957747154594767;   // 1/(4 pi)
+            double loc[3][3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double xc = lx0 * X[0][c] + lx1 * X[1][c] + lx2 * X[2][c];
-                    const double yc = ly0 * Y[0][c] + ly1 * Y[1][c] + ly2 * Y[2][c];
-                    d2 += (xc - yc) * (xc - yc);
+            for (int al = 0; al < 3; ++al)
+#pragma unroll
+                for (int be = 0; be < 3; ++be) {
+                    const double C = g.curl[(3 * px[al]) * E + tau] * g.curl[(3 * py[be]) * E + sig] +
+                                     g.curl[(3 * px[al] + 1) * E + tau] * g.curl[(3 * py[be] + 1) * E + sig] +
+                                     g.curl[(3 * px[al] + 2) * E + tau] * g.curl[(3 * py[be] + 2) * E + sig];
+                    loc[al][be] = (nn * S1[3 * al + be] + C * S2) * scale;
                 }
-                const double rr = sqrt(d2);
-                const double wr = w / rr;
+            if (kind == 0) {
+                // identical triangles: reference order = local order; symmetrise in (a, b)
 #pragma unroll
-                for (int u = 0; u < kSingBand; ++u) {
-                    double ps, pt;
-                    if (have[u] && table_eval(kd[u], tv.ivl, tv.coef, spt, rr, ps, pt)) {
-                        ++nq;
-                        const double f1 = ps * wr;
-                        const double R0 = f1 * ly0, R1 = f1 * ly1, R2 = f1 * ly2;
-                        S1[u][0] = fma(lx0, R0, S1[u][0]); S1[u][1] = fma(lx0, R1, S1[u][1]); S1[u][2] = fma(lx0, R2, S1[u][2]);
-                        S1[u][3] = fma(lx1, R0, S1[u][3]); S1[u][4] = fma(lx1, R1, S1[u][4]); S1[u][5] = fma(lx1, R2, S1[u][5]);
-                        S1[u][6] = fma(lx2, R0, S1[u][6]); S1[u][7] = fma(lx2, R1, S1[u][7]); S1[u][8] = fma(lx2, R2, S1[u][8]);
-                        S2[u] = fma(pt, wr, S2[u]);
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = a + 1; b < 3; ++b) {
+                        const double m = 0.5 * (loc[a][b] + loc[b][a]);
+                        loc[a][b] = m;
+                        loc[b][a] = m;
                     }
-                }
             }
+            const double half = kind == 0 ? 0.5 : 1.0;
 #pragma unroll
-            for (int u = 0; u < kSingBand; ++u) {
-                if (u >= nb || !have[u]) continue;
-                const int i = i0 + u;
-                double loc[3][3];
+            for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int al = 0; al < 3; ++al)
-#pragma unroll
-                    for (int be = 0; be < 3; ++be) loc[al][be] = (nn * S1[u][3 * al + be] + Cr[al][be] * S2[u]) * scale;
-                if (kind == 0) {
-                    // identical triangles: reference order = local order; symmetrise in (a, b)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-#pragma unroll
-                        for (int b = a + 1; b < 3; ++b) {
-                            const double m = 0.5 * (loc[a][b] + loc[b][a]);
-                            loc[a][b] = m;
-                            loc[b][a] = m;
-                        }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) scatter_half(band, val, valf, k, i, vtr[a], vsr[b], 0.5 * loc[a][b]);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) scatter_half(band, val, valf, k, i, vtr[a], vsr[b], loc[a][b]);
-                }
-            }
+                for (int b = 0; b < 3; ++b)
+                    scatter_half(band, val, valf, k, i, g.v[px[a] * E + tau], g.v[py[b] * E + sig], half * loc[a][b]);
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
-    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(counter, tot);
+    if ((tid & 63) == 0 && tot) atomicAdd(counter, tot);
 }
 
 __global__ void __launch_bounds__(256)
@@ -771,13 +797,15 @@ std::vector<int32_t> regular_tiles(int E)
 }
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,
-                     const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt, double* val, float* valf,
-                     unsigned long long* counter, hipStream_t s)
+                     const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt, int max_points, double* val,
+                     float* valf, unsigned long long* counter, hipStream_t s)
 {
-    const int64_t n = npairs * tv.N;
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_singular, dim3(grid_for(n, 128)), dim3(128), 0, s, g, tv, t, band, pairs, npairs, ss_rules,
-                       ss_off, ss_cnt, val, valf, counter);
+    if (npairs <= 0) return;
+    int P = 64;
+    while (P < max_points) P <<= 1;
+    const size_t lds = (size_t)P * (sizeof(double) + sizeof(uint16_t));
+    hipLaunchKernelGGL(k_singular, dim3((unsigned)npairs), dim3(kSingThreads), lds, s, g, tv, t, band, pairs, ss_rules,
+                       ss_off, ss_cnt, P, val, valf, counter);
 }
 
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,

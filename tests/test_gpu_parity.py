@@ -202,6 +202,32 @@ def test_mixed_sampled_entries(ctx, tb, oracle_mod, name):
     assert worst <= MIXED_TOL, worst
 
 
+def test_mixed_torus_full_size(ctx, tb, oracle_mod):
+    """The 20480-triangle torus with 128 graded bases in mixed precision (about 210 GB of FP32
+    band storage, one launch of each assembly kernel): all (k, i) blocks at sampled vertex
+    pairs against the FP64 oracle, Hessenberg zeros exact."""
+    c = get_config("torus20480_graded128")
+    xyz, tri = c["mesh"]; grid = c["grid"]
+    ctx.set_mesh(xyz, tri)
+    ctx.set_time_grid(grid, c["cutoff"])
+    rep = ctx.assemble(tb.MIXED)
+    assert rep["quad_evals"] > 4e12
+    N = len(grid)
+    l0 = int(tri[0][0])
+    d = np.linalg.norm(xyz - xyz[l0], axis=1)
+    sj = np.array([int(tri[0][1]), int(np.argmin(np.abs(d - 1.0))), int(np.argmax(d))])
+    sl = np.full(len(sj), l0)
+    ref = oracle_mod.assemble_entries(xyz, tri, grid, sj, sl, kind=c["cutoff"])
+    K, I = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    for s in range(len(sj)):
+        got = ctx.get_entries(K.ravel(), I.ravel(), sj[s], sl[s]).reshape(N, N)
+        assert np.abs(got - ref[s]).max() <= MIXED_TOL * np.abs(ref[s]).max(), (sj[s], sl[s])
+        assert np.all(got[np.triu_indices(N, 2)] == 0.0)
+    ctx.set_mesh(*icosphere(0))            # release the band storage
+    ctx.set_time_grid(equidistant_grid(3, 2.0))
+    ctx.assemble()
+
+
 def test_mixed_solve_config1(ctx, tb):
     """The mixed operator's solution of the 320-triangle workload to 1e-8 (its own residual),
     then its residual against the FP64 operator and its distance to the FP64 solution."""
@@ -293,6 +319,9 @@ def test_solve_config1_to_1e8(ctx):
 # --- error handling --------------------------------------------------------------------------
 def test_error_paths(tb):
     import torch
+    with pytest.raises(tb.TdbemError) as e:
+        tb.Context(0, ss_order=6)            # Sauter-Schwab rules beyond 5 points per direction
+    assert e.value.status == -1
     ctx = tb.Context(0)
     xyz, tri = icosphere(0)
     with pytest.raises(tb.TdbemError) as e:
