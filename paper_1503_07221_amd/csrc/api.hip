@@ -75,7 +75,7 @@ void gauss_legendre(int n, double* x, double* w)
 // 0.004 until a piece would exceed 1/8, uniform pieces of width <= 1/8 in the middle, mirrored.
 PieceTable make_piece_table()
 {
-    const double q = 1.6, fmin = 0.004, wmax = 1.0 / 8.0;
+    const double q = 1.6, fmin = 0.02, wmax = 0.2;
     std::vector<double> left{fmin};
     double x = fmin;
     while (x * (q - 1.0) < wmax) {

@@ -16,14 +16,14 @@ namespace tdbem {
 // Piecewise Chebyshev tables of psi_{k,i} and tilde psi_{k,i} (Section 3.1).
 // The support of each kernel is cut at every node difference t_c - t_a (the points where the
 // kernel stops being analytic) into "intervals"; every interval is cut by one fixed partition
-// of [0, 1] that is graded geometrically (ratio 1.6, down to 0.004) towards both ends, where
-// the kernels are flat, and uniform (width 1/8) in the middle: kPieces pieces.  On each piece
+// of [0, 1] that is graded geometrically (ratio 1.6, down to 0.02) towards both ends, where
+// the kernels are flat, and uniform (width <= 0.2) in the middle: kPieces pieces.  On each piece
 // both kernels are interpolated at kNc Chebyshev points of the first kind (degree kDeg) and
 // evaluated with Clenshaw's recurrence.
 // ---------------------------------------------------------------------------------------------
 constexpr int kDeg = 14;
 constexpr int kNc = kDeg + 1;
-constexpr int kPieces = 24;
+constexpr int kPieces = 16;
 constexpr int kMaxIntervals = 9;   // at most 3 x 3 node differences split a support
 
 struct KernelDesc {
