@@ -75,6 +75,17 @@ k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, d
     atomicAdd(gvec + (int64_t)k * M + g.v[2 * E + e], acc2);
 }
 
+// A load at a wave-uniform index through the constant address space, so that it becomes a
+// scalar (SGPR) load: the vector memory pipeline is left to the matrix stream.
+__device__ inline double load_uniform(const double* p, int idx)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) double*)p)[idx];
+#else
+    return p[idx];
+#endif
+}
+
 // y = A[k0:k1, i0:i1] x on the lower-triangle band storage.  Block = one 64 x 64 vertex tile
 // (rows l, columns j <= l) of one time row k, whose values are one contiguous stretch; wave w
 // takes the 16 rows l = 64 tl + w + 4m, lanes the columns.  A stored entry (l, j) serves
@@ -130,13 +141,29 @@ k_matvec_tri(BandView band, const VT* __restrict__ val, int k0, int i0, int i1, 
             const int le = l < M ? l : M - 1;
             const VT* __restrict__ v = vt + ((int64_t)lr * B + s0) * kBT;
             const double* __restrict__ xj = x + (int64_t)(ibe + s0 - i0) * M + je;
-            const double* __restrict__ xl = x + (int64_t)(ibe + s0 - i0) * M + le;
+            // the row's value x_i(l) is the same for every lane when the band start is (the usual
+            // case): then it is one scalar load per slot instead of a vector load
+            const int ib0 = __builtin_amdgcn_readfirstlane(ibe);
+            const int top0 = __builtin_amdgcn_readfirstlane(top);
+            const bool uni = __ballot(ibe != ib0 || top != top0) == 0;
+            if (uni) {
+                const int xo = __builtin_amdgcn_readfirstlane((ib0 + s0 - i0) * M + le);
 #pragma unroll
-            for (int u = 0; u < kSlots; ++u) {
-                const int su = u < top ? u : top;
-                a[h][u] = (double)v[su * kBT];
-                bj[h][u] = xj[(int64_t)su * M];
-                bl[h][u] = xl[(int64_t)su * M];
+                for (int u = 0; u < kSlots; ++u) {
+                    const int su = u < top0 ? u : top0;
+                    a[h][u] = (double)v[su * kBT];
+                    bj[h][u] = xj[(int64_t)su * M];
+                    bl[h][u] = load_uniform(x, xo + su * M);
+                }
+            } else {
+                const double* __restrict__ xl = x + (int64_t)(ibe + s0 - i0) * M + le;
+#pragma unroll
+                for (int u = 0; u < kSlots; ++u) {
+                    const int su = u < top ? u : top;
+                    a[h][u] = (double)v[su * kBT];
+                    bj[h][u] = xj[(int64_t)su * M];
+                    bl[h][u] = xl[(int64_t)su * M];
+                }
             }
         }
 #pragma unroll
