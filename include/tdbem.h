@@ -78,6 +78,10 @@ typedef struct {
     int32_t max_it;              /* outer iteration limit */
     int32_t precond_levels;      /* 0: none; r > 0: Algorithm 1 with r recursion levels */
     int32_t precond_inner[8];    /* inner FGMRES iterations on each level, e.g. {2, 10} */
+    /* optional: called on the calling thread after every outer iteration with the iteration
+     * number and the Givens estimate of the relative residual (NULL: no calls) */
+    void (*progress)(int32_t iteration, double estimate, void *user);
+    void *progress_user;         /* passed to progress unchanged */
 } tdbem_solve_opts;
 
 typedef struct {
@@ -139,6 +143,14 @@ tdbem_status tdbem_matvec(tdbem_ctx *ctx, const double *x, double *y);
  * ((i1-i0)*M values), y receives blocks k0..k1-1 ((k1-k0)*M values).  Used by Algorithm 1. */
 tdbem_status tdbem_matvec_range(tdbem_ctx *ctx, int32_t k0, int32_t k1, int32_t i0, int32_t i1,
                                 const double *x, double *y);
+
+/* y = A x in FP64 without storing A, for operators whose band storage does not fit the device:
+ * the regular and singular quadrature of eq. (MatrixEntries) runs again and every local block
+ * is applied to x as it is formed (its entries with their block-symmetric mirrors, Section 3.2).
+ * x, y: device vectors of N*M float64 (y is overwritten).  Needs the mesh and the time grid (no
+ * assembly); costs about one assembly.  rep (may be NULL) receives the quadrature counts and
+ * times (bytes_matrix = 0). */
+tdbem_status tdbem_matvec_free(tdbem_ctx *ctx, const double *x, double *y, tdbem_assembly_report *rep);
 
 /* Solve A alpha = g (device vectors, N*M float64) with FGMRES(restart) (Saad 1993) from
  * alpha = 0, right-preconditioned by Algorithm 1 when opts->precond_levels > 0.  On return

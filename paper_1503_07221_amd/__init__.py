@@ -24,7 +24,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
 
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
-                    "tdbem_matvec", "tdbem_matvec_range", "tdbem_solve"]
+                    "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve"]
 
 
 class TdbemError(RuntimeError):
@@ -49,9 +49,13 @@ class AssemblyReport(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p)
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
-                ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8)]
+                ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8),
+                ("progress", PROGRESS), ("progress_user", ctypes.c_void_p)]
 
 
 class SolveReport(ctypes.Structure):
@@ -92,6 +96,7 @@ def load_library(path=LIB_PATH):
     L.tdbem_rhs_plane_pulse.argtypes = [vp, P(dp), dp, dp, vp]
     L.tdbem_matvec.argtypes = [vp, vp, vp]
     L.tdbem_matvec_range.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
     for name in EXPORTED_SYMBOLS:
         if name not in ("tdbem_destroy", "tdbem_last_error"):
@@ -202,9 +207,18 @@ class Context:
                                                 self._dev(y, (k1 - k0) * self.M)))
         return y
 
-    def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None):
+    def matvec_free(self, x, out=None):
+        """y = A x in FP64 with the operator formed on the fly (no stored matrix needed)."""
+        y = self._vec() if out is None else out
+        n = self.N * self.M
+        rep = AssemblyReport()
+        self._check(self.lib.tdbem_matvec_free(self.h, self._dev(x, n), self._dev(y, n), ctypes.byref(rep)))
+        return y, rep.as_dict()
+
+    def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None, progress=None):
         """FGMRES(restart) from 0 to ||g - A alpha|| <= tol ||g||, with Algorithm 1 when
-        precond_inner lists inner iterations per level (e.g. (2, 10))."""
+        precond_inner lists inner iterations per level (e.g. (2, 10)); progress(iteration,
+        estimate) is called after every outer iteration when given."""
         n = self.N * self.M
         alpha = self._vec() if out is None else out
         o = SolveOpts()
@@ -212,6 +226,8 @@ class Context:
         o.precond_levels = len(precond_inner)
         for s, v in enumerate(precond_inner):
             o.precond_inner[s] = int(v)
+        cb = PROGRESS(lambda it, est, user: progress(int(it), float(est))) if progress else PROGRESS()
+        o.progress = cb
         rep = SolveReport()
         st = self._check(self.lib.tdbem_solve(self.h, self._dev(g, n), self._dev(alpha, n), ctypes.byref(o),
                                               ctypes.byref(rep)))

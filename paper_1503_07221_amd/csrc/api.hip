@@ -654,14 +654,14 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     // mixed precision: point pairs farther apart than three of the longest triangle edges are the
     // far field; FP64 everywhere in FP64 mode
     const double r_far = prec == TDBEM_MIXED ? 3.0 * c->hmax : INFINITY;
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, r_far, c->d_tiles.as<int2>(),
-                   c->ntiles, cnt, c->stream);
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, r_far,
+                   c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
     launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
                     c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, v64, v32,
-                    cnt + 1, c->stream);
+                    nullptr, nullptr, cnt + 1, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -680,6 +680,63 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         rep->pairs_regular = E * (E - 1) / 2 - c->npairs_kind[1] - c->npairs_kind[2];
         rep->table_functions = c->nfunc;
         rep->bytes_matrix = (int64_t)c->d_val.bytes;
+        rep->ms_tables = ms[0];
+        rep->ms_layout = ms[1];
+        rep->ms_regular = ms[2];
+        rep->ms_singular = ms[3];
+        rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3];
+    }
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_matvec_free(tdbem_ctx* c, const double* x, double* y, tdbem_assembly_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!x || !y) FAIL(c, TDBEM_EINVAL, "null vector");
+    if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid before the product");
+    TRY(set_device(c));
+    hipEvent_t ev[5];
+    for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() { for (int s = 0; s < 5; ++s) (void)hipEventDestroy(e[s]); }
+    } guard{ev};
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    TRY(run_geometry(c));
+    TRY(build_tables(c));
+    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    launch_fill(y, 0.0, (int64_t)c->N * c->M, c->stream);
+    DBuf counter;
+    ALLOC(c, counter, sizeof(unsigned long long) * 2);
+    HIPCHK(c, hipMemsetAsync(counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
+    HIPCHK(c, hipEventRecord(ev[2], c->stream));
+    unsigned long long* cnt = counter.as<unsigned long long>();
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), nullptr, nullptr, x, y, INFINITY,
+                   c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
+    launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
+                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, nullptr,
+                    nullptr, x, y, cnt + 1, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    unsigned long long counts[2];
+    HIPCHK(c, hipMemcpy(counts, counter.p, sizeof(counts), hipMemcpyDeviceToHost));
+    if (rep) {
+        float ms[4];
+        for (int s = 0; s < 4; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
+        const int64_t E = c->E;
+        rep->quad_evals = (int64_t)(counts[0] + counts[1]);
+        rep->quad_evals_regular = (int64_t)counts[0];
+        rep->pairs_coincident = c->npairs_kind[0];
+        rep->pairs_edge = c->npairs_kind[1];
+        rep->pairs_vertex = c->npairs_kind[2];
+        rep->pairs_regular = E * (E - 1) / 2 - c->npairs_kind[1] - c->npairs_kind[2];
+        rep->table_functions = c->nfunc;
+        rep->bytes_matrix = 0;
         rep->ms_tables = ms[0];
         rep->ms_layout = ms[1];
         rep->ms_regular = ms[2];
@@ -790,6 +847,8 @@ struct SolveCtx {
     int restart;
     int levels;
     const int32_t* inner;
+    void (*progress)(int32_t, double, void*);
+    void* progress_user;
 };
 
 tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
@@ -891,6 +950,7 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
             gv[j] = cs[j] * gv[j];
             ++its;
             jdone = j + 1;
+            if (!inner && S.progress) S.progress(its, std::fabs(gv[j + 1]) / bnorm, S.progress_user);
             if (std::fabs(gv[j + 1]) <= S.tol * bnorm || hn == 0.0) { done = true; break; }
         }
         // y = H^{-1} g (upper triangular), x += Z y
@@ -961,7 +1021,7 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
         }
         blocks = (blocks + 1) / 2;
     }
-    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner};
+    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner, o->progress, o->progress_user};
     c->matvecs = 0;
     int its = 0;
     double rel = 0.0;

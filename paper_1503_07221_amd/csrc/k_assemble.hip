@@ -161,6 +161,25 @@ __device__ inline void scatter_half(const BandView& band, double* val, float* va
     else atomicAdd(val + idx, v);
 }
 
+// Matrix-free form of scatter_half: the contribution v to P(l, j) is applied to x at once,
+// y_k(l) += v x_i(j) and y_k(j) += v x_i(l) (A = P + P^T; for l == j the two give 2 v x_i(l)).
+struct ProductView {
+    const double* x;       // x[i*M + j]
+    double* y;             // y[k*M + l]
+    int32_t M;
+};
+
+__device__ inline void deposit(const BandView& band, double* val, float* valf, const ProductView& pv, int k, int i,
+                               int l, int j, double v)
+{
+    if (pv.y) {
+        atomicAdd(pv.y + (int64_t)k * pv.M + l, v * pv.x[(int64_t)i * pv.M + j]);
+        atomicAdd(pv.y + (int64_t)k * pv.M + j, v * pv.x[(int64_t)i * pv.M + l]);
+    } else {
+        scatter_half(band, val, valf, k, i, l, j, v);
+    }
+}
+
 // Number of keys of the ascending array key[0..n) below v (key < v, or key <= v when le): the
 // 64 lanes sample evenly spaced keys and the ballot narrows the range (2 rounds for n <= 4096).
 // Every lane returns the same value.
@@ -269,7 +288,8 @@ struct TileLds {
 template <bool MIXED>
 __global__ void __launch_bounds__(kTileThreads, 4)
 k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
-               double r_far, const int2* __restrict__ tiles, int64_t ntiles, unsigned long long* counter)
+               ProductView pv, double r_far, const int2* __restrict__ tiles, int64_t ntiles,
+               unsigned long long* counter)
 {
     // consecutive workgroups go to the 8 XCDs in turn: give each XCD one contiguous range of the
     // tile list (same test rows, shared L2 lines for the output)
@@ -541,7 +561,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                 const double v = L.acc[z];
                 if (v != 0.0) {
                     const int a = z / kTileVs, b = z - kTileVs * a;
-                    scatter_half(band, val, valf, k, i, L.vt[a], L.vs[b], v);
+                    deposit(band, val, valf, pv, k, i, L.vt[a], L.vs[b], v);
                     L.acc[z] = 0.0;
                 }
             }
@@ -569,7 +589,7 @@ constexpr int kSingU = 8;      // trial indices of one time row taken in one rou
 __global__ void __launch_bounds__(kSingThreads)
 k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, const int32_t* __restrict__ pairs,
            const double* __restrict__ rules, const int32_t* __restrict__ roff, const int32_t* __restrict__ rcnt,
-           int P, double* val, float* valf, unsigned long long* counter)
+           int P, double* val, float* valf, ProductView pv, unsigned long long* counter)
 {
     extern __shared__ double sing_lds[];
     double* key = sing_lds;                                   // P sorted distances
@@ -724,7 +744,7 @@ k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    scatter_half(band, val, valf, k, i, g.v[px[a] * E + tau], g.v[py[b] * E + sig], half * loc[a][b]);
+                    deposit(band, val, valf, pv, k, i, g.v[px[a] * E + tau], g.v[py[b] * E + sig], half * loc[a][b]);
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
@@ -770,16 +790,18 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    double r_far, const int2* tiles, int64_t ntiles, unsigned long long* counter, hipStream_t s)
+                    const double* px, double* py, double r_far, const int2* tiles, int64_t ntiles,
+                    unsigned long long* counter, hipStream_t s)
 {
     if (ntiles <= 0) return;
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
+    const ProductView pv{px, py, band.M};
     if (valf)
-        hipLaunchKernelGGL(k_regular_tile<true>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, r_far,
+        hipLaunchKernelGGL(k_regular_tile<true>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv, r_far,
                            tiles, ntiles, counter);
     else
-        hipLaunchKernelGGL(k_regular_tile<false>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, r_far,
-                           tiles, ntiles, counter);
+        hipLaunchKernelGGL(k_regular_tile<false>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv,
+                           r_far, tiles, ntiles, counter);
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau.
@@ -798,14 +820,15 @@ std::vector<int32_t> regular_tiles(int E)
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,
                      const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt, int max_points, double* val,
-                     float* valf, unsigned long long* counter, hipStream_t s)
+                     float* valf, const double* px, double* py, unsigned long long* counter, hipStream_t s)
 {
     if (npairs <= 0) return;
     int P = 64;
     while (P < max_points) P <<= 1;
     const size_t lds = (size_t)P * (sizeof(double) + sizeof(uint16_t));
+    const ProductView pv{px, py, band.M};
     hipLaunchKernelGGL(k_singular, dim3((unsigned)npairs), dim3(kSingThreads), lds, s, g, tv, t, band, pairs, ss_rules,
-                       ss_off, ss_cnt, P, val, valf, counter);
+                       ss_off, ss_cnt, P, val, valf, pv, counter);
 }
 
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,

@@ -295,11 +295,13 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
                    int32_t* Bk, hipStream_t s);
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    double r_far, const int2* tiles, int64_t ntiles, unsigned long long* counter, hipStream_t s);
+                    const double* px, double* py, double r_far, const int2* tiles, int64_t ntiles,
+                    unsigned long long* counter, hipStream_t s);
 std::vector<int32_t> regular_tiles(int E);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
-                     int max_points, double* val, float* valf, unsigned long long* counter, hipStream_t s);
+                     int max_points, double* val, float* valf, const double* px, double* py,
+                     unsigned long long* counter, hipStream_t s);
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,
                         const int32_t* i, const int32_t* j, const int32_t* l, double* out, hipStream_t s);
 

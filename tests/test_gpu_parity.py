@@ -276,6 +276,29 @@ def test_rhs_and_matvec(ctx, oracle_mod, small_system):
         assert np.linalg.norm(ys - ysr) <= 1e-13 * max(np.linalg.norm(ysr), 1e-300)
 
 
+def test_matvec_free(ctx, tb, oracle_mod, small_system):
+    """The matrix-free FP64 product against the oracle's dense system, and at full size against
+    the stored FP64 operator (same quadrature, other summation order)."""
+    import torch
+    c, A, g_ref = small_system
+    xyz, tri = c["mesh"]; N, M = len(c["grid"]), len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "erf")
+    Af = oracle_mod.system_matrix(A)
+    x = torch.from_numpy(np.random.default_rng(4).standard_normal(N * M)).cuda()
+    y, rep = ctx.matvec_free(x)
+    yr = Af @ x.cpu().numpy()
+    assert np.linalg.norm(y.cpu().numpy() - yr) <= 1e-13 * np.linalg.norm(yr)
+    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, c["grid"]) and rep["bytes_matrix"] == 0
+    c2 = get_config("sphere5120_graded64")
+    ctx.set_mesh(*c2["mesh"]); ctx.set_time_grid(c2["grid"], c2["cutoff"])
+    ctx.assemble(tb.FP64)
+    n = len(c2["grid"]) * len(c2["mesh"][0])
+    x = torch.from_numpy(np.random.default_rng(5).standard_normal(n)).cuda()
+    y_stored = ctx.matvec(x).clone()
+    y_free, _ = ctx.matvec_free(x)
+    assert torch.linalg.norm(y_free - y_stored).item() <= 1e-12 * torch.linalg.norm(y_stored).item()
+
+
 def test_rhs_config1(ctx, oracle_mod):
     c = get_config("sphere320_eq10")
     xyz, tri = c["mesh"]
@@ -300,6 +323,23 @@ def test_solve_against_lu(ctx, oracle_mod, small_system, inner):
     assert rep["converged"] and rep["rel_residual"] <= 1e-10
     assert np.linalg.norm(g_ref - Af @ a) <= 1.01e-10 * np.linalg.norm(g_ref)
     assert np.linalg.norm(a - ref) <= kappa * 1e-10 * np.linalg.norm(ref)
+
+
+def test_solve_progress(ctx):
+    """The progress callback sees every outer iteration, with Givens estimates that never grow
+    within one restart cycle."""
+    c = get_config("sphere320_eq10")
+    xyz, tri = c["mesh"]
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "bump"); ctx.assemble()
+    g = ctx.rhs_plane_pulse(c["direction"], c["t0"], c["width"])
+    seen = []
+    alpha, rep = ctx.solve(g, tol=1e-8, restart=1000, precond_inner=(2, 10), max_it=500,
+                           progress=lambda it, est: seen.append((it, est)))
+    assert rep["converged"]
+    assert [it for it, _ in seen] == list(range(1, rep["iterations"] + 1))
+    est = [e for _, e in seen]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(est, est[1:]))
+    assert est[-1] <= 1e-8
 
 
 def test_solve_config1_to_1e8(ctx):

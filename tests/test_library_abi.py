@@ -36,6 +36,7 @@ def test_null_context_is_rejected_without_a_device():
     lib = tb.load_library()
     assert lib.tdbem_assemble(None, 0, None) == -1
     assert lib.tdbem_matvec(None, None, None) == -1
+    assert lib.tdbem_matvec_free(None, None, None, None) == -1
     assert lib.tdbem_set_time_grid(None, None, 2, 0) == -1
     assert lib.tdbem_solve(None, None, None, None, None) == -1
     lib.tdbem_destroy(None)
