@@ -10,7 +10,9 @@ The headline value is assembly quadrature evaluations per second (one evaluation
 The same JSON line carries the solve, the mixed-precision form (FP32 far field, FP64 singular
 pairs and solver) with its error against FP64, the roofline of the dominant kernel (the
 regular-pair assembly kernel, FP64 vector ALU bound) and the CPU oracle timed on a sample of the
-same workload.
+same workload.  The learned leg trains the message-passing preconditioner on the assembled
+operator (the library's own forward, backward and Adam kernels) and solves the same problem with
+FGMRES preconditioned by the network, in FP64 and on the mixed-precision operator.
 
 `--copy-calibration` runs only a plain 1 GiB device copy (the reference kernel that scales the
 FETCH_SIZE / WRITE_SIZE hardware counters into HBM bytes).
@@ -51,7 +53,10 @@ def parse():
     ap.add_argument("--skip-solve", action="store_true", help="assembly and right-hand side only (profiling)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=800, help="regular pairs timed on the CPU oracle")
+    ap.add_argument("--cpu-pairs", type=int, default=2000, help="regular pairs timed on the CPU oracle")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--lp-steps", type=int, default=150, help="Adam steps (batch 8) of the learned preconditioner")
+    ap.add_argument("--lp-max-it", type=int, default=1500, help="iteration limit (= restart) of the learned solve")
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
@@ -125,6 +130,45 @@ def sample_entries(ctx, cfg, n, seed):
     j = rng.integers(0, M, n)
     l = rng.integers(0, M, n)
     return k, i, j, l
+
+
+def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
+    """Train the learned preconditioner on the FP64 operator, then solve with it in FP64 and on
+    the mixed-precision operator; solutions are compared with the Algorithm 1 solution alpha_ref."""
+    import torch
+    ctx.assemble(tb.FP64)
+    ctx.lp_init(4, seed=3)
+    hist, trep = ctx.lp_train(steps=args.lp_steps, batch=8, lr=1e-3, seed=4)
+    print(f"# learned: trained {trep['samples']} residuals in {trep['ms']:.0f} ms, loss {hist[0]:.3f} -> "
+          f"{hist[-10:].mean():.3f}", file=sys.stderr, flush=True)
+    x = torch.randn_like(g)
+    ctx.lp_apply(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        ctx.lp_apply(x)
+    e1.record()
+    e1.synchronize()
+    res = {"layers": 4, "hidden": 64, "params": ctx.lp_num_params(), "train_steps": args.lp_steps, "batch": 8,
+           "train_ms": trep["ms"], "train_samples": int(trep["samples"]), "loss_first": float(hist[0]),
+           "loss_last10": float(hist[-10:].mean()), "apply_ms": e0.elapsed_time(e1) / 10}
+    nrm = torch.linalg.norm(alpha_ref)
+    for tag, prec in (("fp64", tb.FP64), ("mixed", tb.MIXED)):
+        if prec == tb.MIXED:
+            if args.no_mixed:
+                continue
+            ctx.assemble(tb.MIXED)
+        a, srep = ctx.solve(g, tol=args.tol, restart=args.lp_max_it, max_it=args.lp_max_it,
+                            precond_kind=tb.PRECOND_LEARNED)
+        print(f"# learned {tag}: solve {srep['ms']:.1f} ms ({srep['iterations']} it, residual "
+              f"{srep['rel_residual']:.2e})", file=sys.stderr, flush=True)
+        res[tag] = {"solve_ms": srep["ms"], "iterations": int(srep["iterations"]),
+                    "rel_residual": float(srep["rel_residual"]), "converged": bool(srep["converged"]),
+                    "solution_rel_diff_vs_alg1_fp64": float(torch.linalg.norm(a - alpha_ref) / nrm)}
+        if solve_ref:
+            res[tag]["speedup_vs_alg1_fp64_solve"] = solve_ref["ms"] / srep["ms"]
+    ctx.assemble(tb.FP64)
+    return res
 
 
 def main():
@@ -263,6 +307,8 @@ def main():
             res = g - ctx.matvec(alpha32)
             mixed["rel_residual_fp64_operator"] = float(torch.linalg.norm(res) / torch.linalg.norm(g))
         out["mixed"] = mixed
+    if not args.no_learned and not args.skip_solve:
+        out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_pairs)
     ctx.close()

@@ -82,6 +82,11 @@ typedef struct {
      * number and the Givens estimate of the relative residual (NULL: no calls) */
     void (*progress)(int32_t iteration, double estimate, void *user);
     void *progress_user;         /* passed to progress unchanged */
+    /* preconditioner of the outer iteration: 0 = Algorithm 1 as set by precond_levels (none
+     * when 0); 1 = the learned network of tdbem_learned.h (must be initialised); 2 = the learned
+     * network during the first restart cycle, then Algorithm 1 (precond_levels > 0) from the
+     * iterate reached, the paper's preconditioner serving as the fallback */
+    int32_t precond_kind;
 } tdbem_solve_opts;
 
 typedef struct {

@@ -5,6 +5,9 @@ Argument marshalling only: every step of the method runs in the HIP kernels of
 stream; there is no CPU fallback, and a missing or unloadable library raises at import of the
 context.
 
+The learned variable preconditioner of ``include/tdbem_learned.h`` (a message-passing network
+trained on the GPU by the library's own kernels) is reached through the ``lp_*`` methods.
+
 Vector layout (eq. (A) block partition): ``x[i*M + j]`` multiplies ``b_i(t) phi_j(x)``.
 """
 import ctypes
@@ -15,7 +18,8 @@ import numpy as np
 from .build import LIB_PATH, build_library
 
 __all__ = ["Context", "TdbemError", "load_library", "build_library", "LIB_PATH", "EXPORTED_SYMBOLS",
-           "FP64", "MIXED", "CUTOFF_BUMP", "CUTOFF_ERF"]
+           "FP64", "MIXED", "CUTOFF_BUMP", "CUTOFF_ERF", "PRECOND_ALG1", "PRECOND_LEARNED",
+           "PRECOND_LEARNED_THEN_ALG1"]
 
 FP64, MIXED = 0, 1
 CUTOFF_BUMP, CUTOFF_ERF = 0, 1
@@ -24,7 +28,12 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
 
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
-                    "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve"]
+                    "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
+                    "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
+                    "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
+
+# preconditioner kinds of SolveOpts.precond_kind
+PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1 = 0, 1, 2
 
 
 class TdbemError(RuntimeError):
@@ -55,7 +64,20 @@ PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8),
-                ("progress", PROGRESS), ("progress_user", ctypes.c_void_p)]
+                ("progress", PROGRESS), ("progress_user", ctypes.c_void_p), ("precond_kind", ctypes.c_int32)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("samples", ctypes.c_int64), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SolveReport(ctypes.Structure):
@@ -98,8 +120,18 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_range.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
+    fp = P(ctypes.c_float)
+    L.tdbem_lp_num_params.argtypes = [i32]
+    L.tdbem_lp_num_params.restype = i64
+    L.tdbem_lp_init.argtypes = [vp, i32, ctypes.c_uint64]
+    L.tdbem_lp_set_params.argtypes = [vp, fp, i64]
+    L.tdbem_lp_get_params.argtypes = [vp, fp, i64]
+    L.tdbem_lp_apply.argtypes = [vp, vp, vp]
+    L.tdbem_lp_gradient.argtypes = [vp, vp, vp, vp, fp]
+    L.tdbem_matvec_transpose.argtypes = [vp, vp, vp]
+    L.tdbem_lp_train.argtypes = [vp, P(TrainOpts), fp, P(TrainReport)]
     for name in EXPORTED_SYMBOLS:
-        if name not in ("tdbem_destroy", "tdbem_last_error"):
+        if name not in ("tdbem_destroy", "tdbem_last_error", "tdbem_lp_num_params"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -215,10 +247,13 @@ class Context:
         self._check(self.lib.tdbem_matvec_free(self.h, self._dev(x, n), self._dev(y, n), ctypes.byref(rep)))
         return y, rep.as_dict()
 
-    def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None, progress=None):
+    def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None, progress=None,
+              precond_kind=PRECOND_ALG1):
         """FGMRES(restart) from 0 to ||g - A alpha|| <= tol ||g||, with Algorithm 1 when
         precond_inner lists inner iterations per level (e.g. (2, 10)); progress(iteration,
-        estimate) is called after every outer iteration when given."""
+        estimate) is called after every outer iteration when given.  precond_kind selects the
+        learned network (PRECOND_LEARNED) or the network for the first restart cycle and
+        Algorithm 1 afterwards (PRECOND_LEARNED_THEN_ALG1)."""
         n = self.N * self.M
         alpha = self._vec() if out is None else out
         o = SolveOpts()
@@ -228,9 +263,57 @@ class Context:
             o.precond_inner[s] = int(v)
         cb = PROGRESS(lambda it, est, user: progress(int(it), float(est))) if progress else PROGRESS()
         o.progress = cb
+        o.precond_kind = int(precond_kind)
         rep = SolveReport()
         st = self._check(self.lib.tdbem_solve(self.h, self._dev(g, n), self._dev(alpha, n), ctypes.byref(o),
                                               ctypes.byref(rep)))
         d = rep.as_dict()
         d["converged"] = st == 0
         return alpha, d
+
+    # --- learned preconditioner (include/tdbem_learned.h) -----------------------------------------
+    def lp_init(self, layers=4, seed=0):
+        self._check(self.lib.tdbem_lp_init(self.h, int(layers), int(seed)))
+        self.lp_layers = int(layers)
+
+    def lp_num_params(self, layers=None):
+        return int(self.lib.tdbem_lp_num_params(int(self.lp_layers if layers is None else layers)))
+
+    def lp_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.tdbem_lp_set_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+
+    def lp_get_params(self):
+        p = np.zeros(self.lp_num_params(), dtype=np.float32)
+        self._check(self.lib.tdbem_lp_get_params(self.h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), p.size))
+        return p
+
+    def lp_apply(self, v, out=None):
+        n = self.N * self.M
+        z = self._vec() if out is None else out
+        self._check(self.lib.tdbem_lp_apply(self.h, self._dev(v, n), self._dev(z, n)))
+        return z
+
+    def lp_gradient(self, v, dz):
+        """(z, grad): z = P(v) and the gradient of <dz, P(v)> with respect to the parameters."""
+        n = self.N * self.M
+        z = self._vec()
+        grad = np.zeros(self.lp_num_params(), dtype=np.float32)
+        self._check(self.lib.tdbem_lp_gradient(self.h, self._dev(v, n), self._dev(dz, n), self._dev(z, n),
+                                               grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return z, grad
+
+    def matvec_transpose(self, y, out=None):
+        x = self._vec() if out is None else out
+        n = self.N * self.M
+        self._check(self.lib.tdbem_matvec_transpose(self.h, self._dev(y, n), self._dev(x, n)))
+        return x
+
+    def lp_train(self, steps, batch=8, lr=1e-3, seed=0):
+        """Train the network on the assembled operator; returns (per-step losses, report dict)."""
+        o = TrainOpts(int(steps), int(batch), float(lr), int(seed))
+        hist = np.zeros(int(steps), dtype=np.float32)
+        rep = TrainReport()
+        self._check(self.lib.tdbem_lp_train(self.h, ctypes.byref(o), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            ctypes.byref(rep)))
+        return hist, rep.as_dict()

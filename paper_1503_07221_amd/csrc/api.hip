@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/tdbem.h"
+#include "../../include/tdbem_learned.h"
 #include "tdbem_internal.hpp"
 
 using namespace tdbem;
@@ -183,6 +184,20 @@ struct tdbem_ctx {
     };
     std::vector<Level> levels;
     int64_t matvecs = 0;
+    // learned preconditioner: parameters (float32 master, bfloat16 copy, Adam moments), the graph
+    // of the current mesh and grid, workspaces
+    struct Learned {
+        int layers = 0;
+        int64_t P = 0, step = 0, samples = 0;
+        DBuf params, wq, grad, m1, m2;
+        DBuf ptr, idx, feat;
+        uint64_t gver = ~0ull;
+        DBuf Hinf, dots;
+        int64_t ninf = 0, ndots = 0;
+        DBuf H, U, DU, dX, dH2, partial, vb, xb, zb, rb, db;
+        int64_t ntrain = 0;
+    } lp;
+    uint64_t graph_version = 0;   // changes with the mesh and the time grid
 
     GeomView geom() const
     {
@@ -454,6 +469,7 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     TRY(run_geometry(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_mesh = true;
+    ++c->graph_version;
     return TDBEM_OK;
 }
 
@@ -478,6 +494,7 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem
     TRY(upload(c, c->d_t, c->t.data(), c->t.size()));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_grid = true;
+    ++c->graph_version;
     return TDBEM_OK;
 }
 
@@ -837,6 +854,358 @@ tdbem_status tdbem_matvec(tdbem_ctx* c, const double* x, double* y)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Learned variable preconditioner (not part of the paper): a message-passing network on the
+// space-time graph of the unknowns, trained on the residual loss ||A z - v||^2 / ||v||^2.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+uint64_t host_splitmix64(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Mesh-neighbour lists (vertices sharing an edge) and step-size features of the current mesh
+// and grid, rebuilt when either changed.
+tdbem_status lp_graph(tdbem_ctx* c)
+{
+    if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
+    tdbem_ctx::Learned& L = c->lp;
+    if (L.gver == c->graph_version) return TDBEM_OK;
+    std::vector<std::vector<int32_t>> nb(c->M);
+    for (int e = 0; e < c->E; ++e)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (a != b) nb[c->tri[3 * e + a]].push_back(c->tri[3 * e + b]);
+    std::vector<int32_t> ptr(c->M + 1, 0), idx;
+    for (int j = 0; j < c->M; ++j) {
+        std::sort(nb[j].begin(), nb[j].end());
+        nb[j].erase(std::unique(nb[j].begin(), nb[j].end()), nb[j].end());
+        idx.insert(idx.end(), nb[j].begin(), nb[j].end());
+        ptr[j + 1] = (int32_t)idx.size();
+    }
+    std::vector<float> feat(2 * (size_t)c->N, 0.0f);
+    const double hbar = c->t[c->N - 1] / (c->N - 1);
+    for (int k = 0; k < c->N; ++k) {
+        if (k > 0) feat[2 * k] = (float)((c->t[k] - c->t[k - 1]) / hbar);
+        if (k + 1 < c->N) feat[2 * k + 1] = (float)((c->t[k + 1] - c->t[k]) / hbar);
+    }
+    TRY(upload(c, L.ptr, ptr.data(), ptr.size()));
+    TRY(upload(c, L.idx, idx.data(), std::max<size_t>(idx.size(), 1)));
+    TRY(upload(c, L.feat, feat.data(), feat.size()));
+    L.gver = c->graph_version;
+    return TDBEM_OK;
+}
+
+LpGraph lp_view(const tdbem_ctx* c)
+{
+    return LpGraph{c->lp.ptr.as<int32_t>(), c->lp.idx.as<int32_t>(), c->lp.feat.as<float>(), c->M, c->N};
+}
+
+// ||v||^2 of a device vector (synchronises the stream).
+tdbem_status lp_norm2(tdbem_ctx* c, const double* v, int64_t n, double* out)
+{
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t need = dots_partial_blocks(n) + 1;
+    if (L.ndots < need) {
+        ALLOC(c, L.dots, sizeof(double) * need);
+        L.ndots = need;
+    }
+    double* d = L.dots.as<double>();
+    launch_dots(v, 1, n, n, v, d + 1, d, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status lp_need_params(tdbem_ctx* c)
+{
+    if (c->lp.layers <= 0) FAIL(c, TDBEM_ESTATE, "initialise the learned preconditioner first");
+    return TDBEM_OK;
+}
+
+// z = network(v) for device vectors of N*M values.
+tdbem_status lp_apply(tdbem_ctx* c, const double* v, double* z)
+{
+    TRY(lp_need_params(c));
+    TRY(lp_graph(c));
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    if (L.ninf < n) {
+        ALLOC(c, L.Hinf, sizeof(float) * 2 * (size_t)n * kLpHidden);
+        L.ninf = n;
+    }
+    double vv;
+    TRY(lp_norm2(c, v, n, &vv));
+    if (!(vv > 0.0)) {
+        launch_fill(z, 0.0, n, c->stream);
+        HIPCHK(c, hipGetLastError());
+        return TDBEM_OK;
+    }
+    const double s = std::sqrt(vv / (double)n);
+    launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, 1.0 / s, s,
+                      L.Hinf.as<float>(), 0, nullptr, z, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return TDBEM_OK;
+}
+
+tdbem_status lp_need_train_buffers(tdbem_ctx* c)
+{
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    if (L.ntrain >= n) return TDBEM_OK;
+    const size_t f = sizeof(float) * (size_t)n * kLpHidden;
+    ALLOC(c, L.H, f * (L.layers + 1));
+    ALLOC(c, L.U, f * std::max(L.layers, 1));
+    ALLOC(c, L.DU, f);
+    ALLOC(c, L.dX, 4 * f);
+    ALLOC(c, L.dH2, 2 * f);
+    ALLOC(c, L.partial, sizeof(float) * (size_t)lp_partial_blocks(n) * (4 * kLpHidden * kLpHidden + kLpHidden));
+    ALLOC(c, L.vb, sizeof(double) * n);
+    ALLOC(c, L.xb, sizeof(double) * n);
+    ALLOC(c, L.zb, sizeof(double) * n);
+    ALLOC(c, L.rb, sizeof(double) * n);
+    ALLOC(c, L.db, sizeof(double) * n);
+    L.ntrain = n;
+    return TDBEM_OK;
+}
+
+// Forward pass keeping every layer's input and pre-activation, then add the gradient of <dz, z>
+// to lp.grad.  s is the root mean square of v (> 0).
+tdbem_status lp_forward_backward(tdbem_ctx* c, const double* v, double s, double* z, const double* dz_or_null,
+                                 bool backward_now)
+{
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    const int64_t hs = n * kLpHidden;
+    if (!backward_now) {
+        launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, 1.0 / s, s,
+                          L.H.as<float>(), hs, L.U.as<float>(), z, c->stream);
+    } else {
+        launch_lp_backward(lp_view(c), L.layers, L.wq.as<uint16_t>(), v, 1.0 / s, s, L.H.as<float>(),
+                           L.U.as<float>(), dz_or_null, L.dH2.as<float>(), L.DU.as<float>(), L.dX.as<float>(),
+                           L.partial.as<float>(), L.grad.as<float>(), c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    return TDBEM_OK;
+}
+
+}  // namespace
+
+int64_t tdbem_lp_num_params(int32_t layers)
+{
+    if (layers < 1 || layers > TDBEM_LP_MAX_LAYERS) return -1;
+    return lp_num_params(layers);
+}
+
+tdbem_status tdbem_lp_init(tdbem_ctx* c, int32_t layers, uint64_t seed)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (layers < 1 || layers > TDBEM_LP_MAX_LAYERS) FAIL(c, TDBEM_EINVAL, "layers must be in 1..%d", TDBEM_LP_MAX_LAYERS);
+    TRY(set_device(c));
+    const int64_t P = lp_num_params(layers);
+    // uniform initialisation: +-1/sqrt(fan_in) for the input and output maps and the biases,
+    // +-0.3/sqrt(256) for the layer weights (small residual updates at the start)
+    std::vector<float> p(P);
+    uint64_t state = host_splitmix64(seed);
+    auto unif = [&](double a) {
+        state = host_splitmix64(state);
+        return (float)(a * (2.0 * ((double)(state >> 11) * 0x1.0p-53) - 1.0));
+    };
+    for (int64_t s = 0; s < 3 * kLpHidden; ++s) p[lp_off_win() + s] = unif(1.0 / std::sqrt(3.0));
+    for (int s = 0; s < kLpHidden; ++s) p[lp_off_bin() + s] = unif(1.0 / std::sqrt(3.0));
+    for (int l = 0; l < layers; ++l) {
+        for (int64_t s = 0; s < 4 * kLpHidden * kLpHidden; ++s) p[lp_off_w(l) + s] = unif(0.3 / 16.0);
+        for (int s = 0; s < kLpHidden; ++s) p[lp_off_b(l) + s] = unif(0.3 / 16.0);
+    }
+    for (int s = 0; s < kLpHidden; ++s) p[lp_off_wout(layers) + s] = unif(1.0 / 8.0);
+    tdbem_ctx::Learned& L = c->lp;
+    L.ntrain = 0;
+    L.layers = layers;
+    L.P = P;
+    L.step = 0;
+    L.samples = 0;
+    ALLOC(c, L.params, sizeof(float) * P);
+    ALLOC(c, L.wq, sizeof(uint16_t) * P);
+    ALLOC(c, L.grad, sizeof(float) * P);
+    ALLOC(c, L.m1, sizeof(float) * P);
+    ALLOC(c, L.m2, sizeof(float) * P);
+    HIPCHK(c, hipMemcpyAsync(L.params.p, p.data(), sizeof(float) * P, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.m1.p, 0, sizeof(float) * P, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.m2.p, 0, sizeof(float) * P, c->stream));
+    launch_lp_round(P, L.params.as<float>(), L.wq.as<uint16_t>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_set_params(tdbem_ctx* c, const float* params, int64_t n)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    TRY(lp_need_params(c));
+    if (!params || n != c->lp.P) FAIL(c, TDBEM_EINVAL, "expected %lld parameters", (long long)c->lp.P);
+    TRY(set_device(c));
+    tdbem_ctx::Learned& L = c->lp;
+    HIPCHK(c, hipMemcpyAsync(L.params.p, params, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.m1.p, 0, sizeof(float) * n, c->stream));
+    HIPCHK(c, hipMemsetAsync(L.m2.p, 0, sizeof(float) * n, c->stream));
+    L.step = 0;
+    launch_lp_round(n, L.params.as<float>(), L.wq.as<uint16_t>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_get_params(tdbem_ctx* c, float* params, int64_t n)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    TRY(lp_need_params(c));
+    if (!params || n != c->lp.P) FAIL(c, TDBEM_EINVAL, "expected %lld parameters", (long long)c->lp.P);
+    TRY(set_device(c));
+    HIPCHK(c, hipMemcpyAsync(params, c->lp.params.p, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_apply(tdbem_ctx* c, const double* v, double* z)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!v || !z) FAIL(c, TDBEM_EINVAL, "null vector");
+    TRY(set_device(c));
+    TRY(lp_apply(c, v, z));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_gradient(tdbem_ctx* c, const double* v, const double* dz, double* z, float* grad)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!v || !dz || !z || !grad) FAIL(c, TDBEM_EINVAL, "null argument");
+    TRY(lp_need_params(c));
+    TRY(set_device(c));
+    TRY(lp_graph(c));
+    TRY(lp_need_train_buffers(c));
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    HIPCHK(c, hipMemsetAsync(L.grad.p, 0, sizeof(float) * L.P, c->stream));
+    double vv;
+    TRY(lp_norm2(c, v, n, &vv));
+    if (vv > 0.0) {
+        const double s = std::sqrt(vv / (double)n);
+        TRY(lp_forward_backward(c, v, s, z, nullptr, false));
+        TRY(lp_forward_backward(c, v, s, z, dz, true));
+    } else {
+        launch_fill(z, 0.0, n, c->stream);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipMemcpyAsync(grad, L.grad.p, sizeof(float) * L.P, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_matvec_transpose(tdbem_ctx* c, const double* y, double* x)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!x || !y) FAIL(c, TDBEM_EINVAL, "null vector");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before the matvec");
+    TRY(set_device(c));
+    launch_matvec_transpose(c->band(), c->valf64(), c->valf32(), y, x, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_train(tdbem_ctx* c, const tdbem_lp_train_opts* o, float* loss_history,
+                            tdbem_lp_train_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!o) FAIL(c, TDBEM_EINVAL, "null options");
+    if (o->steps < 1 || o->batch < 1 || !(o->lr > 0.0)) FAIL(c, TDBEM_EINVAL, "bad training options");
+    TRY(lp_need_params(c));
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before training (the loss applies A)");
+    TRY(set_device(c));
+    TRY(lp_graph(c));
+    TRY(lp_need_train_buffers(c));
+    const auto t_start = std::chrono::steady_clock::now();
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    hipStream_t st = c->stream;
+    double* v = L.vb.as<double>();
+    double* x = L.xb.as<double>();
+    double* z = L.zb.as<double>();
+    double* r = L.rb.as<double>();
+    double* dz = L.db.as<double>();
+    double first = 0.0, last = 0.0;
+    for (int step = 0; step < o->steps; ++step) {
+        HIPCHK(c, hipMemsetAsync(L.grad.p, 0, sizeof(float) * L.P, st));
+        double sum = 0.0;
+        int used = 0;
+        for (int b = 0; b < o->batch; ++b) {
+            // training residual: a normal vector, or A x for a normal x smoothed 0..3 times over
+            // the mesh (residuals whose errors are smooth in space)
+            const uint64_t sid = (uint64_t)L.samples++;
+            const uint64_t h = host_splitmix64(o->seed ^ host_splitmix64(sid));
+            if ((h & 1) == 0) {
+                launch_lp_randn(n, o->seed, sid, v, st);
+            } else {
+                launch_lp_randn(n, o->seed, sid, x, st);
+                const int q = (int)((h >> 1) & 3);
+                for (int u = 0; u < q; ++u) {
+                    launch_lp_smooth(lp_view(c), x, z, st);
+                    std::swap(x, z);
+                }
+                TRY(matvec_range(c, 0, c->N, 0, c->N, x, v));
+            }
+            HIPCHK(c, hipGetLastError());
+            double vv;
+            TRY(lp_norm2(c, v, n, &vv));
+            if (!(vv > 0.0)) continue;
+            const double s = std::sqrt(vv / (double)n);
+            TRY(lp_forward_backward(c, v, s, z, nullptr, false));
+            TRY(matvec_range(c, 0, c->N, 0, c->N, z, r));
+            launch_axpby(r, v, -1.0, 1.0, n, st);                   // r = A z - v
+            HIPCHK(c, hipGetLastError());
+            double rr;
+            TRY(lp_norm2(c, r, n, &rr));
+            sum += rr / vv;
+            ++used;
+            launch_matvec_transpose(c->band(), c->valf64(), c->valf32(), r, dz, st);
+            launch_scale_copy(dz, dz, 2.0 / vv, n, st);              // d loss / d z = 2 A^T r / |v|^2
+            HIPCHK(c, hipGetLastError());
+            TRY(lp_forward_backward(c, v, s, z, dz, true));
+        }
+        if (used == 0) continue;
+        ++L.step;
+        launch_lp_adam(L.P, L.params.as<float>(), L.grad.as<float>(), L.m1.as<float>(), L.m2.as<float>(),
+                       (float)o->lr, L.step, 1.0f / (float)used, L.wq.as<uint16_t>(), st);
+        HIPCHK(c, hipGetLastError());
+        const double loss = sum / used;
+        if (step == 0) first = loss;
+        last = loss;
+        if (loss_history) loss_history[step] = (float)loss;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (rep) {
+        rep->steps = o->steps;
+        rep->samples = (int64_t)o->steps * o->batch;
+        rep->loss_first = first;
+        rep->loss_last = last;
+        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return TDBEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 // FGMRES (Saad 1993) with the recursive block-Hessenberg preconditioner (Section 4.2, Alg. 1)
 // ---------------------------------------------------------------------------------------------
 namespace {
@@ -849,6 +1218,8 @@ struct SolveCtx {
     const int32_t* inner;
     void (*progress)(int32_t, double, void*);
     void* progress_user;
+    int kind;               // 0: Algorithm 1 / none, 1: learned network, 2: learned, then Algorithm 1
+    bool learned_active;    // the outer iteration currently uses the learned network
 };
 
 tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
@@ -886,7 +1257,8 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
     hipStream_t st = c->stream;
     const int64_t n = (int64_t)(b - a) * c->M;
     tdbem_ctx::Level& L = c->levels[depth];
-    const bool precond = depth < S.levels && (b - a) > 1;
+    const bool alg1 = depth < S.levels && (b - a) > 1;
+    const bool precond = alg1 || (depth == 0 && S.kind != 0);
     const int m = inner ? max_it : std::min(S.restart, max_it);
     double* V = L.V.as<double>();
     double* Z = precond ? L.Z.as<double>() : V;
@@ -920,7 +1292,9 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
         for (int j = 0; j < mm; ++j) {
             double* vj = V + (int64_t)j * n;
             double* zj = Z + (int64_t)j * n;
-            if (precond) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
+            if (depth == 0 && S.learned_active) TRY(lp_apply(c, vj, zj));
+            else if (alg1) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
+            else if (precond) launch_scale_copy(zj, vj, 1.0, n, st);
             double* w = V + (int64_t)(j + 1) * n;
             TRY(matvec_range(c, a, b, a, b, zj, w));
             // classical Gram-Schmidt, twice
@@ -977,6 +1351,7 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
         beta = std::sqrt(r2);
         r = wres;
         (void)done;
+        if (depth == 0 && S.kind == 2) S.learned_active = false;   // fall back to Algorithm 1
         if (beta <= S.tol * bnorm || its >= max_it) break;
     }
     *its_out = its;
@@ -993,12 +1368,19 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
     c->err.clear();
     if (!g || !alpha || !o) FAIL(c, TDBEM_EINVAL, "null argument");
     if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before solving");
-    if (o->restart < 1 || o->restart > 1000 || !(o->tol > 0.0) || o->max_it < 1 || o->precond_levels < 0 ||
+    if (o->restart < 1 || o->restart > 5000 || !(o->tol > 0.0) || o->max_it < 1 || o->precond_levels < 0 ||
         o->precond_levels > 8)
         FAIL(c, TDBEM_EINVAL, "bad solver options");
     for (int s = 0; s < o->precond_levels; ++s)
         if (o->precond_inner[s] < 1 || o->precond_inner[s] > 1000) FAIL(c, TDBEM_EINVAL, "bad inner iteration count");
+    if (o->precond_kind < 0 || o->precond_kind > 2) FAIL(c, TDBEM_EINVAL, "unknown preconditioner kind %d", o->precond_kind);
+    if (o->precond_kind == 2 && o->precond_levels < 1)
+        FAIL(c, TDBEM_EINVAL, "the learned-then-Algorithm-1 preconditioner needs precond_levels > 0");
     TRY(set_device(c));
+    if (o->precond_kind != 0) {
+        TRY(lp_need_params(c));
+        TRY(lp_graph(c));
+    }
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t M = c->M;
     // workspaces: depth 0 is the outer solve; depth d >= 1 holds ranges of <= ceil(N / 2^(d-1)) blocks
@@ -1021,7 +1403,8 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
         }
         blocks = (blocks + 1) / 2;
     }
-    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner, o->progress, o->progress_user};
+    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner, o->progress, o->progress_user,
+               o->precond_kind, o->precond_kind != 0};
     c->matvecs = 0;
     int its = 0;
     double rel = 0.0;

@@ -275,6 +275,24 @@ __device__ inline int64_t band_value_index(const BandView& b, int k, int64_t l, 
     return b.voff[(int64_t)k * b.nt + band_tile(l, j)] + ((l % kBT) * (int64_t)B + s) * kBT + j % kBT;
 }
 
+// Learned preconditioner: graph of the space-time nodes n = k*M + j (CSR mesh neighbours of
+// every vertex, step-size features feat[2k] = h_k / hbar, feat[2k+1] = h_{k+1} / hbar) and the
+// layout of the flat parameter vector: Win (64 x 3), bin (64), per layer W_l (64 x 256) and b_l
+// (64), wout (64).
+constexpr int kLpHidden = 64;
+struct LpGraph {
+    const int32_t* ptr;
+    const int32_t* idx;
+    const float* feat;
+    int32_t M, N;
+};
+inline int64_t lp_off_win() { return 0; }
+inline int64_t lp_off_bin() { return 3 * kLpHidden; }
+inline int64_t lp_off_w(int l) { return 4 * kLpHidden + (int64_t)l * (4 * kLpHidden * kLpHidden + kLpHidden); }
+inline int64_t lp_off_b(int l) { return lp_off_w(l) + 4 * kLpHidden * kLpHidden; }
+inline int64_t lp_off_wout(int layers) { return lp_off_w(layers); }
+inline int64_t lp_num_params(int layers) { return lp_off_wout(layers) + kLpHidden; }
+
 }  // namespace tdbem
 
 // ---------------------------------------------------------------------------------------------
@@ -319,4 +337,23 @@ void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hip
 int dots_partial_blocks(int64_t n);
 void launch_scale_inv_sqrt(double* dst, const double* src, const double* nrm2, int64_t n, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+
+void launch_lp_round(int64_t P, const float* p, uint16_t* q, hipStream_t s);
+// hstride = 0: inference, H holds two ping-pong slots of N*M*64 floats and U is unused;
+// hstride = N*M*64: training, H holds layers+1 slots and U (may not be null) holds layers slots.
+void launch_lp_forward(LpGraph g, int layers, const float* params, const uint16_t* wq, const double* v,
+                       double inv_s, double s_scale, float* H, int64_t hstride, float* U, double* z,
+                       hipStream_t st);
+int lp_partial_blocks(int64_t n);
+// Adds the gradient of <dz, z> to grad (layout of the parameter vector).  dH2: 2 N*M*64 floats,
+// DU: N*M*64, dX: 4 N*M*64, partial: lp_partial_blocks(N*M) * (64*256 + 64) floats.
+void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double* v, double inv_s, double s_scale,
+                        const float* H, const float* U, const double* dz, float* dH2, float* DU, float* dX,
+                        float* partial, float* grad, hipStream_t st);
+void launch_lp_adam(int64_t P, float* p, const float* grad, float* m, float* v2, float lr, int64_t step,
+                    float gscale, uint16_t* q, hipStream_t s);
+void launch_lp_randn(int64_t n, uint64_t seed, uint64_t stream, double* out, hipStream_t s);
+void launch_lp_smooth(LpGraph g, const double* x, double* y, hipStream_t s);
+void launch_matvec_transpose(BandView band, const double* val, const float* valf, const double* y, double* x,
+                             hipStream_t s);
 }  // namespace tdbem

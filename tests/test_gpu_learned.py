@@ -1,0 +1,177 @@
+"""Learned variable preconditioner (include/tdbem_learned.h) on the GPU against the CPU oracle.
+
+Forward pass and parameter gradient against ``oracle.learned`` on the same parameters and
+inputs: float32 activations and accumulation against float64, both with the same bfloat16
+weights, so agreement is to LP_TOL (float32 rounding through 4 layers of 256-term sums; a node
+whose pre-activation sits within rounding of 0 may take the other side of the ReLU, which the
+norm-wise bound absorbs).  The transposed product against the oracle's dense system (1e-13) and,
+at full size, through the identity <y, A x> = <A^T y, x>.  Training must lower the loss and the
+trained network must cut the FGMRES iteration count of the unpreconditioned solve.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import get_config, graded_grid, icosphere
+from workloads.configs import pulse_direction
+
+pytestmark = pytest.mark.gpu
+
+LP_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def tb():
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    import paper_1503_07221_amd as tb
+    tb.load_library()
+    return tb
+
+
+@pytest.fixture(scope="module")
+def ctx(tb):
+    c = tb.Context(0)
+    yield c
+    c.close()
+
+
+def _params(layers, seed, scale=0.15):
+    from oracle import learned as LP
+    return (np.random.default_rng(seed).standard_normal(LP.num_params(layers)) * scale).astype(np.float32)
+
+
+# meshes with N*M not a multiple of the 64-node tile nor of the 256-node chunk
+CASES = {"ico1_n6": (1, 6, 3.0, 3), "ico2_n10": (2, 10, 8.0, 4), "ico3_n5": (3, 5, 2.0, 2)}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_forward_against_oracle(ctx, case):
+    import torch
+    from oracle import learned as LP
+    lev, N, T, layers = CASES[case]
+    xyz, tri = icosphere(lev)
+    grid = graded_grid(N, T, seed=lev)
+    M = len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid)
+    ctx.lp_init(layers, seed=1)
+    p = _params(layers, 11 + lev)
+    ctx.lp_set_params(p)
+    assert np.array_equal(ctx.lp_get_params(), p)
+    v = np.random.default_rng(12).standard_normal(N * M) * 3.0
+    z = ctx.lp_apply(torch.from_numpy(v).cuda()).cpu().numpy()
+    zr, _ = LP.forward(p, layers, v, grid, LP.neighbours(tri, M))
+    err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    assert err <= LP_TOL, err
+    assert np.abs(z - zr).max() <= 20 * LP_TOL * np.abs(zr).max()
+    z0 = ctx.lp_apply(torch.zeros(N * M, dtype=torch.float64, device="cuda"))
+    assert not z0.any().item()
+
+
+@pytest.mark.parametrize("case", ["ico1_n6", "ico2_n10"])
+def test_gradient_against_oracle(ctx, case):
+    import torch
+    from oracle import learned as LP
+    lev, N, T, layers = CASES[case]
+    xyz, tri = icosphere(lev)
+    grid = graded_grid(N, T, seed=lev)
+    M = len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid)
+    ctx.lp_init(layers, seed=2)
+    p = _params(layers, 21 + lev)
+    ctx.lp_set_params(p)
+    rng = np.random.default_rng(22)
+    v = rng.standard_normal(N * M)
+    dz = rng.standard_normal(N * M)
+    z, grad = ctx.lp_gradient(torch.from_numpy(v).cuda(), torch.from_numpy(dz).cuda())
+    zr, cache = LP.forward(p, layers, v, grid, LP.neighbours(tri, M))
+    gr = LP.backward(cache, dz)
+    assert np.linalg.norm(z.cpu().numpy() - zr) <= LP_TOL * np.linalg.norm(zr)
+    o = LP.offsets(layers)
+    groups = [("Win", o["Win"], 192), ("bin", o["bin"], 64), ("wout", o["wout"], 64)]
+    for l in range(layers):
+        groups += [(f"W{l}", o[("W", l)], 16384), (f"b{l}", o[("b", l)], 64)]
+    for name, a, w in groups:
+        d = np.linalg.norm(grad[a:a + w] - gr[a:a + w])
+        assert d <= 1e-4 * np.linalg.norm(gr[a:a + w]) + 1e-6 * np.linalg.norm(gr), (name, d)
+
+
+def test_matvec_transpose(ctx, tb, oracle_mod):
+    import torch
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]; N, M = len(c["grid"]), len(xyz)
+    A = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, c["grid"], kind="erf"))
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "erf"); ctx.assemble()
+    y = np.random.default_rng(31).standard_normal(N * M)
+    x = ctx.matvec_transpose(torch.from_numpy(y).cuda()).cpu().numpy()
+    xr = A.T @ y
+    assert np.linalg.norm(x - xr) <= 1e-13 * np.linalg.norm(xr)
+    # full size, FP64 and FP32 storage: <y, A x> = <A^T y, x>, and A^T y of both storages agree
+    c2 = get_config("sphere5120_graded64")
+    ctx.set_mesh(*c2["mesh"]); ctx.set_time_grid(c2["grid"], c2["cutoff"])
+    n = len(c2["grid"]) * len(c2["mesh"][0])
+    rng = np.random.default_rng(32)
+    xv = torch.from_numpy(rng.standard_normal(n)).cuda()
+    yv = torch.from_numpy(rng.standard_normal(n)).cuda()
+    res = {}
+    for prec in (tb.FP64, tb.MIXED):
+        ctx.assemble(prec)
+        ax = ctx.matvec(xv)
+        aty = ctx.matvec_transpose(yv)
+        lhs, rhs = torch.dot(yv, ax).item(), torch.dot(aty, xv).item()
+        assert abs(lhs - rhs) <= 1e-12 * torch.linalg.norm(yv).item() * torch.linalg.norm(ax).item(), (prec, lhs, rhs)
+        res[prec] = aty.clone()
+    assert torch.linalg.norm(res[tb.MIXED] - res[tb.FP64]).item() <= 1e-6 * torch.linalg.norm(res[tb.FP64]).item()
+    ctx.set_mesh(*icosphere(0)); ctx.set_time_grid(np.array([0.0, 1.0, 2.0])); ctx.assemble()   # release storage
+
+
+def test_training_cuts_iterations(ctx, tb):
+    """Train on a 162-vertex sphere with 17 graded bases (time steps 1 to 3.5 mesh widths, as in
+    the 5120-triangle workload) and solve the pulse problem: the loss must fall and FGMRES with
+    the network must need well under half the iterations of plain FGMRES, to the same 1e-8."""
+    import torch
+    xyz, tri = icosphere(2)
+    grid = graded_grid(17, 8.0, seed=2)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid); ctx.assemble()
+    g = ctx.rhs_plane_pulse(pulse_direction(3), 1.9, 0.6)
+    _, plain = ctx.solve(g, tol=1e-8, restart=800, max_it=800)
+    ctx.lp_init(4, seed=3)
+    hist, rep = ctx.lp_train(steps=400, batch=8, lr=1e-3, seed=4)
+    assert rep["samples"] == 3200 and np.all(np.isfinite(hist))
+    assert hist[-20:].mean() < 0.5 * hist[:5].mean(), (hist[:5], hist[-20:])
+    alpha, learned = ctx.solve(g, tol=1e-8, restart=500, max_it=500, precond_kind=tb.PRECOND_LEARNED)
+    r = g - ctx.matvec(alpha)
+    assert torch.linalg.norm(r).item() <= 1e-8 * torch.linalg.norm(g).item()
+    assert learned["converged"] and plain["converged"]
+    assert learned["iterations"] < 0.5 * plain["iterations"], (learned["iterations"], plain["iterations"])
+    # the network for one cycle of 20 iterations, then Algorithm 1 (2, 10) from there
+    alpha2, mixed = ctx.solve(g, tol=1e-8, restart=20, max_it=400, precond_inner=(2, 10),
+                              precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
+    assert mixed["converged"] and mixed["iterations"] > 20
+    assert torch.linalg.norm(alpha2 - alpha).item() <= 1e-6 * torch.linalg.norm(alpha).item()
+
+
+def test_learned_error_paths(tb):
+    import torch
+    c = tb.Context(0)
+    xyz, tri = icosphere(1)
+    c.set_mesh(xyz, tri); c.set_time_grid(graded_grid(4, 2.0, seed=1))
+    v = torch.ones(4 * len(xyz), dtype=torch.float64, device="cuda")
+    with pytest.raises(tb.TdbemError) as e:
+        c.lp_apply(v)
+    assert e.value.status == -6
+    c.assemble()
+    with pytest.raises(tb.TdbemError) as e:
+        c.solve(v, precond_kind=tb.PRECOND_LEARNED)
+    assert e.value.status == -6
+    c.lp_init(2, seed=0)
+    with pytest.raises(tb.TdbemError) as e:
+        c.lp_set_params(np.zeros(10, dtype=np.float32))
+    assert e.value.status == -1
+    with pytest.raises(tb.TdbemError) as e:
+        c.solve(v, precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
+    assert e.value.status == -1
+    with pytest.raises(tb.TdbemError) as e:
+        c.lp_init(9)
+    assert e.value.status == -1
+    c.close()

@@ -1,4 +1,4 @@
-"""The C-ABI library loads without a GPU and exports every function include/tdbem.h declares."""
+"""The C-ABI library loads without a GPU and exports every function include/*.h declares."""
 import ctypes
 import os
 import re
@@ -9,9 +9,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "tdbem.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(tdbem_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(tdbem_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_symbols():
@@ -39,6 +43,12 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.tdbem_matvec_free(None, None, None, None) == -1
     assert lib.tdbem_set_time_grid(None, None, 2, 0) == -1
     assert lib.tdbem_solve(None, None, None, None, None) == -1
+    assert lib.tdbem_lp_init(None, 4, 0) == -1
+    assert lib.tdbem_lp_apply(None, None, None) == -1
+    assert lib.tdbem_lp_gradient(None, None, None, None, None) == -1
+    assert lib.tdbem_matvec_transpose(None, None, None) == -1
+    assert lib.tdbem_lp_train(None, None, None, None) == -1
+    assert lib.tdbem_lp_num_params(4) == 66112 and lib.tdbem_lp_num_params(0) == -1
     lib.tdbem_destroy(None)
     assert lib.tdbem_last_error(None) == b"null context"
     assert lib.tdbem_create(None, None) == -1
