@@ -55,8 +55,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=2000, help="regular pairs timed on the CPU oracle")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
-    ap.add_argument("--lp-steps", type=int, default=150, help="Adam steps (batch 8) of the learned preconditioner")
-    ap.add_argument("--lp-max-it", type=int, default=1500, help="iteration limit (= restart) of the learned solve")
+    ap.add_argument("--lp-steps", type=int, default=300,
+                    help="Adam steps (batch 8, lr 1e-3) of the learned preconditioner, then half as many at 5e-4")
+    ap.add_argument("--lp-restart", type=int, default=600, help="FGMRES restart of the learned solve")
+    ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
@@ -135,10 +137,14 @@ def sample_entries(ctx, cfg, n, seed):
 def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
     """Train the learned preconditioner on the FP64 operator, then solve with it in FP64 and on
     the mixed-precision operator; solutions are compared with the Algorithm 1 solution alpha_ref."""
+    import numpy as np
     import torch
     ctx.assemble(tb.FP64)
     ctx.lp_init(4, seed=3)
     hist, trep = ctx.lp_train(steps=args.lp_steps, batch=8, lr=1e-3, seed=4)
+    hist2, trep2 = ctx.lp_train(steps=max(1, args.lp_steps // 2), batch=8, lr=5e-4, seed=5)
+    hist = np.concatenate([hist, hist2])
+    trep = {"ms": trep["ms"] + trep2["ms"], "samples": trep["samples"] + trep2["samples"]}
     print(f"# learned: trained {trep['samples']} residuals in {trep['ms']:.0f} ms, loss {hist[0]:.3f} -> "
           f"{hist[-10:].mean():.3f}", file=sys.stderr, flush=True)
     x = torch.randn_like(g)
@@ -149,7 +155,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
         ctx.lp_apply(x)
     e1.record()
     e1.synchronize()
-    res = {"layers": 4, "hidden": 64, "params": ctx.lp_num_params(), "train_steps": args.lp_steps, "batch": 8,
+    res = {"layers": 4, "hidden": 64, "params": ctx.lp_num_params(), "train_steps": len(hist), "batch": 8,
            "train_ms": trep["ms"], "train_samples": int(trep["samples"]), "loss_first": float(hist[0]),
            "loss_last10": float(hist[-10:].mean()), "apply_ms": e0.elapsed_time(e1) / 10}
     nrm = torch.linalg.norm(alpha_ref)
@@ -158,7 +164,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
             if args.no_mixed:
                 continue
             ctx.assemble(tb.MIXED)
-        a, srep = ctx.solve(g, tol=args.tol, restart=args.lp_max_it, max_it=args.lp_max_it,
+        a, srep = ctx.solve(g, tol=args.tol, restart=args.lp_restart, max_it=args.lp_max_it,
                             precond_kind=tb.PRECOND_LEARNED)
         print(f"# learned {tag}: solve {srep['ms']:.1f} ms ({srep['iterations']} it, residual "
               f"{srep['rel_residual']:.2e})", file=sys.stderr, flush=True)
