@@ -59,6 +59,8 @@ def parse():
                     help="Adam steps (batch 8, lr 1e-3) of the learned preconditioner, then half as many at 5e-4")
     ap.add_argument("--lp-restart", type=int, default=600, help="FGMRES restart of the learned solve")
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
+    ap.add_argument("--batch-rhs", type=int, default=32,
+                    help="right-hand sides of the batched learned solve (0 = skip the batched leg)")
     ap.add_argument("--copy-calibration", action="store_true")
     return ap.parse_args()
 
@@ -173,8 +175,44 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
                     "solution_rel_diff_vs_alg1_fp64": float(torch.linalg.norm(a - alpha_ref) / nrm)}
         if solve_ref:
             res[tag]["speedup_vs_alg1_fp64_solve"] = solve_ref["ms"] / srep["ms"]
+    if args.batch_rhs > 0:
+        res["batched"] = batched_leg(ctx, tb, args, res["fp64"]["solve_ms"])
     ctx.assemble(tb.FP64)
     return res
+
+
+def batched_leg(ctx, tb, args, single_ms):
+    """32 plane pulses (seeded directions on S^2, widths uniform in [0.1, 0.3], t0 = 1 + 6 w) on the
+    same sphere solved together with the learned preconditioner: one multi-right-hand-side product
+    per iteration.  Also the product alone: time per right-hand side for 1 and for 32 vectors."""
+    import numpy as np
+    import torch
+    from workloads.configs import pulse_direction
+    ctx.assemble(tb.FP64)
+    R = args.batch_rhs
+    rng = np.random.default_rng(7)
+    G = torch.stack([ctx.rhs_plane_pulse(pulse_direction(1000 + r), 1.0 + 6 * w, w)
+                     for r, w in enumerate(rng.uniform(0.1, 0.3, R))])
+    X = torch.randn_like(G)
+    ctx.matvec_multi(X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        ctx.matvec_multi(X)
+    e1.record()
+    e1.synchronize()
+    multi_ms = e0.elapsed_time(e1) / 3
+    A, reps, ok = ctx.solve_multi(G, tol=args.tol, restart=args.lp_restart + 200, max_it=args.lp_max_it,
+                                  precond_kind=tb.PRECOND_LEARNED)
+    ms = reps[0]["ms"]
+    its = [r["iterations"] for r in reps]
+    print(f"# batched: {R} right-hand sides in {ms:.0f} ms (iterations {min(its)}..{max(its)}), product "
+          f"{multi_ms:.1f} ms for {R} vectors", file=sys.stderr, flush=True)
+    return {"rhs": R, "solve_ms": ms, "ms_per_rhs": ms / R, "converged": bool(ok),
+            "iterations_min": int(min(its)), "iterations_max": int(max(its)),
+            "max_rel_residual": float(max(r["rel_residual"] for r in reps)),
+            "speedup_vs_single_learned_solves": single_ms * R / ms,
+            "product_ms": multi_ms, "product_ms_per_rhs": multi_ms / R}
 
 
 def main():

@@ -164,6 +164,23 @@ tdbem_status tdbem_matvec_free(tdbem_ctx *ctx, const double *x, double *y, tdbem
 tdbem_status tdbem_solve(tdbem_ctx *ctx, const double *g, double *alpha, const tdbem_solve_opts *opts,
                          tdbem_solve_report *rep);
 
+/* Y_r = A X_r for nrhs right-hand sides at once (the block matvec of Section 3.2; every stored
+ * value is read once per group of 8 right-hand sides): X, Y device arrays of nrhs*N*M float64,
+ * vector r at offset r*N*M.  1 <= nrhs <= 1024.  Requires tdbem_assemble. */
+tdbem_status tdbem_matvec_multi(tdbem_ctx *ctx, int32_t nrhs, const double *X, double *Y);
+
+/* Solve A alpha_r = g_r for nrhs right-hand sides together: FGMRES(restart) from alpha_r = 0 on
+ * every right-hand side with its own Krylov basis, sharing one multi-right-hand-side product per
+ * iteration (tdbem_matvec_multi).  G, Alpha: device arrays of nrhs*N*M float64 (vector r at
+ * offset r*N*M).  Preconditioner: none (precond_kind 0, precond_levels 0) or the learned network
+ * of tdbem_learned.h (precond_kind 1); Algorithm 1 is not batched (TDBEM_EINVAL).  progress, if
+ * set, receives the iteration and the largest estimate over the right-hand sides still
+ * iterating.  rep (may be NULL) is an array of nrhs reports (matvecs = multi-products, ms = the
+ * whole batch).  Needs nrhs*(2*restart+2)*N*M*8 bytes of device workspace.  TDBEM_NOT_CONVERGED
+ * if any right-hand side ends above tol. */
+tdbem_status tdbem_solve_multi(tdbem_ctx *ctx, int32_t nrhs, const double *G, double *Alpha,
+                               const tdbem_solve_opts *opts, tdbem_solve_report *rep);
+
 #ifdef __cplusplus
 }
 #endif

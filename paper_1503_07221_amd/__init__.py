@@ -29,6 +29,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
+                    "tdbem_matvec_multi", "tdbem_solve_multi",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
 
@@ -120,6 +121,8 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_range.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
+    L.tdbem_matvec_multi.argtypes = [vp, i32, vp, vp]
+    L.tdbem_solve_multi.argtypes = [vp, i32, vp, vp, P(SolveOpts), P(SolveReport)]
     fp = P(ctypes.c_float)
     L.tdbem_lp_num_params.argtypes = [i32]
     L.tdbem_lp_num_params.restype = i64
@@ -270,6 +273,38 @@ class Context:
         d = rep.as_dict()
         d["converged"] = st == 0
         return alpha, d
+
+    # --- many right-hand sides ------------------------------------------------------------------------
+    def _dev2(self, X):
+        n = self.N * self.M
+        if not (X.is_cuda and X.dtype == self.torch.float64 and X.is_contiguous() and X.dim() == 2
+                and X.shape[1] == n):
+            raise ValueError(f"expected a contiguous float64 device tensor of shape (nrhs, {n})")
+        return ctypes.c_void_p(X.data_ptr())
+
+    def matvec_multi(self, X, out=None):
+        """Y[r] = A X[r] for the rows of X (shape (nrhs, N*M))."""
+        Y = self.torch.empty_like(X) if out is None else out
+        self._check(self.lib.tdbem_matvec_multi(self.h, X.shape[0], self._dev2(X), self._dev2(Y)))
+        return Y
+
+    def solve_multi(self, G, tol=1e-8, restart=600, max_it=2000, precond_kind=PRECOND_ALG1, out=None,
+                    progress=None):
+        """Solve A alpha_r = G[r] for every row of G together (one shared product per iteration);
+        precond_kind PRECOND_LEARNED uses the learned network, PRECOND_ALG1 here means none."""
+        R = G.shape[0]
+        A = self.torch.empty_like(G) if out is None else out
+        o = SolveOpts()
+        o.restart, o.tol, o.max_it = int(restart), float(tol), int(max_it)
+        cb = PROGRESS(lambda it, est, user: progress(int(it), float(est))) if progress else PROGRESS()
+        o.progress = cb
+        o.precond_kind = int(precond_kind)
+        reps = (SolveReport * R)()
+        st = self._check(self.lib.tdbem_solve_multi(self.h, R, self._dev2(G), self._dev2(A), ctypes.byref(o), reps))
+        out_reps = [r.as_dict() for r in reps]
+        for d in out_reps:
+            d["converged"] = d["rel_residual"] <= tol
+        return A, out_reps, st == 0
 
     # --- learned preconditioner (include/tdbem_learned.h) -----------------------------------------
     def lp_init(self, layers=4, seed=0):

@@ -1426,4 +1426,205 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
     return TDBEM_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// Many right-hand sides: one product per iteration serves all of them (the stored operator is
+// read once per group of 8 right-hand sides); FGMRES runs per right-hand side on its own Krylov
+// basis, with all Gram-Schmidt coefficients of an iteration fetched in one host round trip.
+// ---------------------------------------------------------------------------------------------
+tdbem_status tdbem_matvec_multi(tdbem_ctx* c, int32_t nrhs, const double* X, double* Y)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!X || !Y) FAIL(c, TDBEM_EINVAL, "null array");
+    if (nrhs < 1 || nrhs > 1024) FAIL(c, TDBEM_EINVAL, "need 1 <= nrhs <= 1024, got %d", nrhs);
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before the matvec");
+    TRY(set_device(c));
+    const int64_t n = (int64_t)c->N * c->M;
+    launch_matvec_multi(c->band(), c->valf64(), c->valf32(), nrhs, X, n, Y, n, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_solve_multi(tdbem_ctx* c, int32_t nrhs, const double* G, double* Alpha, const tdbem_solve_opts* o,
+                               tdbem_solve_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!G || !Alpha || !o) FAIL(c, TDBEM_EINVAL, "null argument");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before solving");
+    if (nrhs < 1 || nrhs > 1024) FAIL(c, TDBEM_EINVAL, "need 1 <= nrhs <= 1024, got %d", nrhs);
+    if (o->restart < 1 || o->restart > 5000 || !(o->tol > 0.0) || o->max_it < 1)
+        FAIL(c, TDBEM_EINVAL, "bad solver options");
+    if (o->precond_levels != 0 || (o->precond_kind != 0 && o->precond_kind != 1))
+        FAIL(c, TDBEM_EINVAL, "the batched solve takes no preconditioner or the learned one (precond_kind 1)");
+    TRY(set_device(c));
+    const bool learned = o->precond_kind == 1;
+    if (learned) {
+        TRY(lp_need_params(c));
+        TRY(lp_graph(c));
+    }
+    const auto t_start = std::chrono::steady_clock::now();
+    hipStream_t st = c->stream;
+    const int64_t n = (int64_t)c->N * c->M;
+    const int m = std::min(o->restart, o->max_it);
+    const int R = nrhs;
+    const int np = dots_partial_blocks(n);
+    const int hw = 2 * (m + 1) + 2;                       // per right-hand side: h1, h2, |w|^2, spare
+    DBuf V, Z, W, part, hb;
+    ALLOC(c, V, sizeof(double) * (size_t)R * (m + 1) * n);
+    ALLOC(c, Z, sizeof(double) * (size_t)R * m * n);
+    ALLOC(c, W, sizeof(double) * (size_t)R * n);
+    ALLOC(c, part, sizeof(double) * (size_t)R * (m + 2) * np);
+    ALLOC(c, hb, sizeof(double) * (size_t)R * hw);
+    double* Vd = V.as<double>();
+    double* Zd = Z.as<double>();
+    double* Wd = W.as<double>();
+    double* Pd = part.as<double>();
+    double* Hd = hb.as<double>();
+    auto Vr = [&](int r, int q) { return Vd + ((int64_t)r * (m + 1) + q) * n; };
+    auto Zr = [&](int r, int q) { return Zd + ((int64_t)r * m + q) * n; };
+    auto Pr = [&](int r) { return Pd + (int64_t)r * (m + 2) * np; };
+    auto Hr = [&](int r) { return Hd + (int64_t)r * hw; };
+    std::vector<double> hhost((size_t)R * hw);
+    auto fetch = [&]() -> tdbem_status {
+        HIPCHK(c, hipMemcpyAsync(hhost.data(), Hd, sizeof(double) * hhost.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        return TDBEM_OK;
+    };
+    // ||g_r||
+    for (int r = 0; r < R; ++r) launch_dots(G + r * n, 1, n, n, G + r * n, Pr(r), Hr(r) + 2 * (m + 1), st);
+    HIPCHK(c, hipGetLastError());
+    TRY(fetch());
+    std::vector<double> bnorm(R), beta(R);
+    std::vector<int> its(R, 0);
+    std::vector<char> live(R);
+    for (int r = 0; r < R; ++r) {
+        bnorm[r] = std::sqrt(hhost[(size_t)r * hw + 2 * (m + 1)]);
+        beta[r] = bnorm[r];
+        live[r] = bnorm[r] > 0.0;
+        launch_fill(Alpha + r * n, 0.0, n, st);
+    }
+    std::vector<std::vector<double>> H(R, std::vector<double>((size_t)(m + 1) * m)), cs(R, std::vector<double>(m)),
+        sn(R, std::vector<double>(m)), gv(R, std::vector<double>(m + 1));
+    std::vector<int> jdone(R);
+    std::vector<char> run(R);
+    int64_t products = 0;
+    bool first = true;
+    while (true) {
+        bool any = false;
+        for (int r = 0; r < R; ++r) {
+            run[r] = live[r] && its[r] < o->max_it && beta[r] > o->tol * bnorm[r];
+            jdone[r] = 0;
+            if (!run[r]) continue;
+            any = true;
+            // the residual of this cycle: g at the start, then W (computed below)
+            launch_scale_copy(Vr(r, 0), first ? G + r * n : Wd + r * n, 1.0 / beta[r], n, st);
+            std::fill(gv[r].begin(), gv[r].end(), 0.0);
+            gv[r][0] = beta[r];
+        }
+        first = false;
+        if (!any) break;
+        for (int j = 0; j < m; ++j) {
+            bool active = false;
+            for (int r = 0; r < R; ++r) {
+                if (!run[r]) continue;
+                active = true;
+                if (learned) TRY(lp_apply(c, Vr(r, j), Zr(r, j)));
+                else launch_scale_copy(Zr(r, j), Vr(r, j), 1.0, n, st);
+            }
+            if (!active) break;
+            // w_r = A z_r for every right-hand side (finished ones too: their columns are unused)
+            launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, Zd + (int64_t)j * n, (int64_t)m * n,
+                                Vd + (int64_t)(j + 1) * n, (int64_t)(m + 1) * n, st);
+            HIPCHK(c, hipGetLastError());
+            ++products;
+            for (int r = 0; r < R; ++r) {
+                if (!run[r]) continue;
+                double* w = Vr(r, j + 1);
+                double* h = Hr(r);
+                launch_dots(Vr(r, 0), j + 1, n, n, w, Pr(r), h, st);
+                launch_sub_combination(w, Vr(r, 0), j + 1, n, n, h, -1.0, st);
+                launch_dots(Vr(r, 0), j + 1, n, n, w, Pr(r), h + (m + 1), st);
+                launch_sub_combination(w, Vr(r, 0), j + 1, n, n, h + (m + 1), -1.0, st);
+                launch_dots(w, 1, n, n, w, Pr(r), h + 2 * (m + 1), st);
+                launch_scale_inv_sqrt(w, w, h + 2 * (m + 1), n, st);
+            }
+            HIPCHK(c, hipGetLastError());
+            TRY(fetch());
+            for (int r = 0; r < R; ++r) {
+                if (!run[r]) continue;
+                const double* hh = hhost.data() + (size_t)r * hw;
+                std::vector<double>& Hm = H[r];
+                for (int q = 0; q <= j; ++q) Hm[(size_t)q * m + j] = hh[q] + hh[m + 1 + q];
+                const double hn = std::sqrt(std::max(hh[2 * (m + 1)], 0.0));
+                Hm[(size_t)(j + 1) * m + j] = hn;
+                for (int q = 0; q < j; ++q) {
+                    const double t1 = cs[r][q] * Hm[(size_t)q * m + j] + sn[r][q] * Hm[(size_t)(q + 1) * m + j];
+                    Hm[(size_t)(q + 1) * m + j] = -sn[r][q] * Hm[(size_t)q * m + j] + cs[r][q] * Hm[(size_t)(q + 1) * m + j];
+                    Hm[(size_t)q * m + j] = t1;
+                }
+                const double den = std::hypot(Hm[(size_t)j * m + j], Hm[(size_t)(j + 1) * m + j]);
+                cs[r][j] = den != 0.0 ? Hm[(size_t)j * m + j] / den : 1.0;
+                sn[r][j] = den != 0.0 ? Hm[(size_t)(j + 1) * m + j] / den : 0.0;
+                Hm[(size_t)j * m + j] = cs[r][j] * Hm[(size_t)j * m + j] + sn[r][j] * Hm[(size_t)(j + 1) * m + j];
+                Hm[(size_t)(j + 1) * m + j] = 0.0;
+                gv[r][j + 1] = -sn[r][j] * gv[r][j];
+                gv[r][j] = cs[r][j] * gv[r][j];
+                ++its[r];
+                jdone[r] = j + 1;
+                if (std::fabs(gv[r][j + 1]) <= o->tol * bnorm[r] || hn == 0.0 || its[r] >= o->max_it) run[r] = 0;
+            }
+            if (o->progress) {
+                double worst = 0.0;
+                for (int r = 0; r < R; ++r)
+                    if (live[r] && jdone[r] == j + 1) worst = std::max(worst, std::fabs(gv[r][j + 1]) / bnorm[r]);
+                o->progress(j + 1, worst, o->progress_user);
+            }
+        }
+        // x_r += Z_r y_r, y_r = H_r^{-1} g_r
+        for (int r = 0; r < R; ++r) {
+            const int jd = jdone[r];
+            if (jd == 0) continue;
+            std::vector<double> y(jd);
+            for (int q = jd - 1; q >= 0; --q) {
+                double s = gv[r][q];
+                for (int u = q + 1; u < jd; ++u) s -= H[r][(size_t)q * m + u] * y[u];
+                y[q] = s / H[r][(size_t)q * m + q];
+            }
+            HIPCHK(c, hipMemcpyAsync(Hr(r), y.data(), sizeof(double) * jd, hipMemcpyHostToDevice, st));
+            launch_sub_combination(Alpha + r * n, Zr(r, 0), jd, n, n, Hr(r), 1.0, st);
+        }
+        // true residuals W_r = g_r - A alpha_r
+        launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, Alpha, n, Wd, n, st);
+        ++products;
+        for (int r = 0; r < R; ++r) {
+            launch_axpby(Wd + r * n, G + r * n, 1.0, -1.0, n, st);
+            launch_dots(Wd + r * n, 1, n, n, Wd + r * n, Pr(r), Hr(r) + 2 * (m + 1), st);
+        }
+        HIPCHK(c, hipGetLastError());
+        TRY(fetch());
+        for (int r = 0; r < R; ++r) beta[r] = std::sqrt(std::max(hhost[(size_t)r * hw + 2 * (m + 1)], 0.0));
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    bool all = true;
+    for (int r = 0; r < R; ++r) {
+        const double rel = bnorm[r] > 0.0 ? beta[r] / bnorm[r] : 0.0;
+        all = all && rel <= o->tol;
+        if (rep) {
+            rep[r].iterations = its[r];
+            rep[r].matvecs = products;
+            rep[r].rel_residual = rel;
+            rep[r].ms = ms;
+        }
+    }
+    if (!all) {
+        c->err = "not converged: some right-hand sides are above tol after max_it iterations";
+        return TDBEM_NOT_CONVERGED;
+    }
+    return TDBEM_OK;
+}
+
 }  // extern "C"

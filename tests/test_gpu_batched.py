@@ -1,0 +1,95 @@
+"""Many right-hand sides: the multi-vector block product and the batched FGMRES.
+
+The product against the oracle's dense system (1e-13) with a right-hand-side count that is not a
+multiple of the kernel's group of 8, and at full size against the single-vector product in FP64
+and FP32 storage (same values, other summation order: 1e-13).  The batched solve against separate
+solves of every right-hand side (the Krylov processes are the same up to rounding), to the
+1e-8 true residual, with and without the learned preconditioner.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import get_config, graded_grid, icosphere
+from workloads.configs import pulse_direction
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tb():
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    import paper_1503_07221_amd as tb
+    tb.load_library()
+    return tb
+
+
+@pytest.fixture(scope="module")
+def ctx(tb):
+    c = tb.Context(0)
+    yield c
+    c.close()
+
+
+def test_matvec_multi(ctx, tb, oracle_mod):
+    import torch
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]; N, M = len(c["grid"]), len(xyz)
+    A = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, c["grid"], kind="erf"))
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "erf"); ctx.assemble()
+    X = np.random.default_rng(41).standard_normal((11, N * M))
+    Y = ctx.matvec_multi(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr = X @ A.T
+    for r in range(11):
+        assert np.linalg.norm(Y[r] - Yr[r]) <= 1e-13 * np.linalg.norm(Yr[r]), r
+    c2 = get_config("sphere5120_graded64")
+    ctx.set_mesh(*c2["mesh"]); ctx.set_time_grid(c2["grid"], c2["cutoff"])
+    n = len(c2["grid"]) * len(c2["mesh"][0])
+    Xg = torch.from_numpy(np.random.default_rng(42).standard_normal((9, n))).cuda()
+    for prec in (tb.FP64, tb.MIXED):
+        ctx.assemble(prec)
+        Yg = ctx.matvec_multi(Xg)
+        for r in (0, 7, 8):
+            y1 = ctx.matvec(Xg[r].contiguous())
+            assert torch.linalg.norm(Yg[r] - y1).item() <= 1e-13 * torch.linalg.norm(y1).item(), (prec, r)
+    ctx.set_mesh(*icosphere(0)); ctx.set_time_grid(np.array([0.0, 1.0, 2.0])); ctx.assemble()   # release storage
+
+
+def _pulses(ctx, R):
+    import torch
+    rng = np.random.default_rng(43)
+    G = []
+    for r in range(R):
+        w = rng.uniform(0.3, 0.9)
+        G.append(ctx.rhs_plane_pulse(pulse_direction(100 + r), 1.0 + 6 * w, w))
+    return torch.stack(G)
+
+
+def test_solve_multi_matches_single_solves(ctx, tb):
+    import torch
+    xyz, tri = icosphere(2)
+    grid = graded_grid(17, 8.0, seed=2)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid); ctx.assemble()
+    G = _pulses(ctx, 5)
+    Alpha, reps, ok = ctx.solve_multi(G, tol=1e-8, restart=800, max_it=800)
+    assert ok and all(r["converged"] for r in reps)
+    for r in range(5):
+        a1, d1 = ctx.solve(G[r].contiguous(), tol=1e-8, restart=800, max_it=800)
+        assert d1["converged"]
+        assert abs(reps[r]["iterations"] - d1["iterations"]) <= 2, (r, reps[r]["iterations"], d1["iterations"])
+        res = G[r] - ctx.matvec(Alpha[r].contiguous())
+        assert torch.linalg.norm(res).item() <= 1e-8 * torch.linalg.norm(G[r]).item()
+        assert torch.linalg.norm(Alpha[r] - a1).item() <= 1e-6 * torch.linalg.norm(a1).item()
+    # with the learned preconditioner
+    ctx.lp_init(4, seed=3)
+    ctx.lp_train(steps=200, batch=8, lr=1e-3, seed=4)
+    Al, repl, okl = ctx.solve_multi(G, tol=1e-8, restart=400, max_it=400, precond_kind=tb.PRECOND_LEARNED)
+    assert okl
+    for r in range(5):
+        assert repl[r]["iterations"] < reps[r]["iterations"]
+        res = G[r] - ctx.matvec(Al[r].contiguous())
+        assert torch.linalg.norm(res).item() <= 1e-8 * torch.linalg.norm(G[r]).item()
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.solve_multi(G, precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
+    assert e.value.status == -1
