@@ -165,7 +165,7 @@ tdbem_status tdbem_solve(tdbem_ctx *ctx, const double *g, double *alpha, const t
                          tdbem_solve_report *rep);
 
 /* Y_r = A X_r for nrhs right-hand sides at once (the block matvec of Section 3.2; every stored
- * value is read once per group of 8 right-hand sides): X, Y device arrays of nrhs*N*M float64,
+ * value is read once per group of 4 right-hand sides): X, Y device arrays of nrhs*N*M float64,
  * vector r at offset r*N*M.  1 <= nrhs <= 1024.  Requires tdbem_assemble. */
 tdbem_status tdbem_matvec_multi(tdbem_ctx *ctx, int32_t nrhs, const double *X, double *Y);
 

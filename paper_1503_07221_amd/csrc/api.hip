@@ -1429,7 +1429,7 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
 
 // ---------------------------------------------------------------------------------------------
 // Many right-hand sides: one product per iteration serves all of them (the stored operator is
-// read once per group of 8 right-hand sides); FGMRES runs per right-hand side on its own Krylov
+// read once per group of 4 right-hand sides); FGMRES runs per right-hand side on its own Krylov
 // basis, with all Gram-Schmidt coefficients of an iteration fetched in one host round trip.
 // ---------------------------------------------------------------------------------------------
 tdbem_status tdbem_matvec_multi(tdbem_ctx* c, int32_t nrhs, const double* X, double* Y)

@@ -1,13 +1,16 @@
 // Block matvec for many right-hand sides at once: Y_r = A X_r, r < nrhs, on the lower-triangle
 // band storage (Section 3.2).  The single-vector product streams every stored value from HBM for
-// two FMAs; here a value is read once per group of kRC right-hand sides and serves 2 kRC FMAs,
-// which moves the product from the HBM bound towards the FP64 ALU bound.
+// two FMAs; here a value is read once per group of kRC right-hand sides and serves 2 kRC FMAs.
+// The trial values of a tile's columns are staged in LDS, whose size sets the group: 4 right-hand
+// sides over a trial range of up to 24 indices (48 KB) measured fastest on the 5120-triangle
+// sphere (1.9 ms per right-hand side against 3.75 ms for the single product; 8 right-hand sides
+// with 12 or 19 indices and 4 with 32 were slower, because more tiles fall back to memory or fewer
+// workgroups fit a CU).
 #include "tdbem_internal.hpp"
 
 namespace tdbem {
 
-constexpr int kRC = 8;        // right-hand sides per workgroup pass
-constexpr int kSlotChunk = 8; // band slots loaded together
+constexpr int kRC = 4;        // right-hand sides per workgroup pass
 
 __device__ inline double wave_sum(double v)
 {
@@ -15,11 +18,76 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// A load at a wave-uniform index through the constant address space: a scalar (SGPR) load.
+__device__ inline double load_scalar(const double* p, int64_t idx)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) double*)p)[idx];
+#else
+    return p[idx];
+#endif
+}
+
+constexpr int kSpanM = 24;    // trial range of a tile staged in LDS
+constexpr int kSlotGroup = 4; // band slots whose values are loaded together
+
+// One row l of a tile: for every band slot s (values loaded kSlotGroup at a time) and right-hand
+// side rr, row[rr] += a X_{ib+s}(j) and col[rr] += a X_{ib+s}(l) off the diagonal.  STAGED: X_i(j)
+// from the LDS tile xs[rr][i - ibase][lane]; UNI: the band start is the same on every active lane,
+// so X_i(l) is a scalar load.  Right-hand sides beyond nr reuse the first one (their sums are
+// dropped by the caller).
+template <bool STAGED, bool UNI, typename VT>
+__device__ inline void row_pass(const VT* __restrict__ v, int B, bool act, bool off, int ib, int ib0, int slo, int shi,
+                                int ibase, int span, int N, int M, int l, int je, int lane, int nr, int r0,
+                                const double* __restrict__ X, int64_t ldx, const double (*xs)[kSpanM][kBT],
+                                double (&row)[kRC], double (&col)[kRC])
+{
+    for (int s0 = 0; s0 < B; s0 += kSlotGroup) {
+        double a[kSlotGroup];
+        int ii[kSlotGroup];
+#pragma unroll
+        for (int u = 0; u < kSlotGroup; ++u) {
+            const int s = s0 + u;
+            const bool in = act && s >= slo && s < shi;
+            a[u] = in ? (double)v[(s < B ? s : B - 1) * kBT] : 0.0;
+            if (UNI) {
+                const int iu = ib0 + s;
+                ii[u] = __builtin_amdgcn_readfirstlane(iu < 0 ? 0 : (iu < N ? iu : N - 1));
+            } else {
+                ii[u] = in ? ib + s : (STAGED ? ibase : 0);   // masked slots: 0 times a valid value
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSlotGroup; ++u) {
+            const double ao = off ? a[u] : 0.0;
+            // with UNI every active lane has ib = ib0, so ii is its trial index (a = 0 elsewhere)
+            // (masked slots of a uniform row are clamped into the staged rows: 0 times a finite value)
+            const int si = STAGED ? (UNI ? (ii[u] - ibase < 0 ? 0 : (ii[u] - ibase < span ? ii[u] - ibase : span - 1))
+                                         : ii[u] - ibase)
+                                  : 0;
+#pragma unroll
+            for (int rr = 0; rr < kRC; ++rr) {
+                const double* __restrict__ Xr = X + (int64_t)(rr < nr ? r0 + rr : r0) * ldx;
+                double xj, xl;
+                if (STAGED) xj = xs[rr < nr ? rr : 0][si][lane];
+                else xj = Xr[(int64_t)ii[u] * M + je];
+                // a vector load at a lane-uniform address (one request): a scalar load here would
+                // share the LDS counter and serialise the LDS reads of xj behind it
+                xl = Xr[(int64_t)ii[u] * M + l];
+                row[rr] = fma(a[u], xj, row[rr]);
+                col[rr] = fma(ao, xl, col[rr]);
+            }
+        }
+    }
+}
+
 // Workgroup = (vertex tile t, time row k, group of kRC right-hand sides); wave w takes the rows
 // l = 64 tl + w + 4m, lanes the columns j.  A stored a = A_{k,i}(l, j), j <= l, adds a X_i(j) to
 // the row sum of (k, l) and, off the diagonal, a X_i(l) to the column sum of (k, j), for every
-// right-hand side of the group.  Row sums are reduced over the wave (one atomic per row and
-// right-hand side), column sums over the 4 waves through LDS.
+// right-hand side of the group.  The trial values X_i(j) of the tile's columns over its trial
+// range [ibase, ibase + span) are staged in LDS once (span <= kSpanM; wider tiles read them from
+// memory); X_i(l) is a scalar load when the row's band start is wave-uniform.  Row sums are reduced
+// over the wave (one atomic per row and right-hand side), column sums over the 4 waves.
 template <typename VT>
 __global__ void __launch_bounds__(256)
 k_matvec_multi(BandView band, const VT* __restrict__ val, int nrhs, const double* __restrict__ X, int64_t ldx,
@@ -41,7 +109,37 @@ k_matvec_multi(BandView band, const VT* __restrict__ val, int nrhs, const double
     const int je = j < M ? j : M - 1;
     const int16_t* __restrict__ il = band.ilo + ((int64_t)k * band.nt + t) * (kBT * kBT) + lane;
     const VT* __restrict__ vt = val + band.voff[(int64_t)k * band.nt + t] + lane;
-    __shared__ double s_col[4][kRC][kBT];
+    __shared__ double xs[kRC][kSpanM][kBT];      // after the main loop: the column sums [4][kRC][64]
+    __shared__ int s_range[4][2];
+    // trial range of the tile's stored slots
+    int lo = 0x7fffffff, hi = -0x7fffffff;
+    for (int m = 0; m < 16; ++m) {
+        const int lr = wave + 4 * m;
+        const int l = tl * kBT + lr;
+        if (l < M && j <= l) {
+            const int ib = il[lr * kBT];
+            lo = min(lo, max(ib, 0));
+            hi = max(hi, min(ib + B, N));
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) { s_range[wave][0] = lo; s_range[wave][1] = hi; }
+    __syncthreads();
+    const int ibase = min(min(s_range[0][0], s_range[1][0]), min(s_range[2][0], s_range[3][0]));
+    const int itop = max(max(s_range[0][1], s_range[1][1]), max(s_range[2][1], s_range[3][1]));
+    const int span = itop - ibase;
+    const bool staged = span > 0 && span <= kSpanM;
+    if (staged) {
+        for (int e = threadIdx.x; e < nr * span * kBT; e += 256) {
+            const int rr = e / (span * kBT), rest = e - rr * span * kBT, si = rest / kBT, c = rest % kBT;
+            const int jj = tj * kBT + c;
+            xs[rr][si][c] = jj < M ? X[(int64_t)(r0 + rr) * ldx + (int64_t)(ibase + si) * M + jj] : 0.0;
+        }
+    }
+    __syncthreads();
     double col[kRC];
 #pragma unroll
     for (int rr = 0; rr < kRC; ++rr) col[rr] = 0.0;
@@ -52,37 +150,24 @@ k_matvec_multi(BandView band, const VT* __restrict__ val, int nrhs, const double
         const bool act = j <= l;
         const bool off = j < l;
         const int ib = il[lr * kBT];
-        const int lo = ib < 0 ? -ib : 0;
-        const int hi = N - ib < B ? N - ib : B;
+        const int slo = ib < 0 ? -ib : 0;
+        const int shi = N - ib < B ? N - ib : B;
+        const unsigned long long am = __ballot(act);
+        if (am == 0) continue;
+        const int first = __ffsll((long long)am) - 1;
+        const int ib0 = __shfl(ib, first, 64);
+        const bool uni = __ballot(act && ib != ib0) == 0;
         const VT* __restrict__ v = vt + (int64_t)lr * B * kBT;
         double row[kRC];
 #pragma unroll
         for (int rr = 0; rr < kRC; ++rr) row[rr] = 0.0;
-        for (int s0 = 0; s0 < B; s0 += kSlotChunk) {
-            double a[kSlotChunk];
-            int xi[kSlotChunk];
-#pragma unroll
-            for (int u = 0; u < kSlotChunk; ++u) {
-                const int s = s0 + u;
-                const bool in = act && s >= lo && s < hi;
-                a[u] = in ? (double)v[(s < B ? s : B - 1) * kBT] : 0.0;
-                const int ii = ib + s;
-                xi[u] = in ? ii : 0;             // masked slots read block 0 and multiply by 0
-            }
-#pragma unroll
-            for (int rr = 0; rr < kRC; ++rr) {
-                if (rr >= nr) break;
-                const double* __restrict__ Xr = X + (int64_t)(r0 + rr) * ldx;
-                double rs = row[rr], cs = 0.0;
-#pragma unroll
-                for (int u = 0; u < kSlotChunk; ++u) {
-                    const int64_t base = (int64_t)xi[u] * M;
-                    rs = fma(a[u], Xr[base + je], rs);
-                    cs = fma(a[u], Xr[base + l], cs);
-                }
-                row[rr] = rs;
-                col[rr] += off ? cs : 0.0;
-            }
+        // wave-uniform choice of where the trial values come from
+        if (staged) {
+            if (uni) row_pass<true, true, VT>(v, B, act, off, ib, ib0, slo, shi, ibase, span, N, M, l, je, lane, nr, r0, X, ldx, xs, row, col);
+            else row_pass<true, false, VT>(v, B, act, off, ib, ib0, slo, shi, ibase, span, N, M, l, je, lane, nr, r0, X, ldx, xs, row, col);
+        } else {
+            if (uni) row_pass<false, true, VT>(v, B, act, off, ib, ib0, slo, shi, ibase, span, N, M, l, je, lane, nr, r0, X, ldx, xs, row, col);
+            else row_pass<false, false, VT>(v, B, act, off, ib, ib0, slo, shi, ibase, span, N, M, l, je, lane, nr, r0, X, ldx, xs, row, col);
         }
 #pragma unroll
         for (int rr = 0; rr < kRC; ++rr) {
@@ -91,6 +176,9 @@ k_matvec_multi(BandView band, const VT* __restrict__ val, int nrhs, const double
             if (lane == 0 && rs != 0.0) atomicAdd(Y + (int64_t)(r0 + rr) * ldy + (int64_t)k * M + l, rs);
         }
     }
+    static_assert(kRC * kSpanM >= 4 * kRC, "column sums reuse the staging array");
+    double (*s_col)[kRC][kBT] = reinterpret_cast<double (*)[kRC][kBT]>(&xs[0][0][0]);
+    __syncthreads();                             // every wave is done with the staged values
 #pragma unroll
     for (int rr = 0; rr < kRC; ++rr) s_col[wave][rr][lane] = col[rr];
     __syncthreads();

@@ -1,7 +1,7 @@
 """Many right-hand sides: the multi-vector block product and the batched FGMRES.
 
 The product against the oracle's dense system (1e-13) with a right-hand-side count that is not a
-multiple of the kernel's group of 8, and at full size against the single-vector product in FP64
+multiple of the kernel's group of 4, and at full size against the single-vector product in FP64
 and FP32 storage (same values, other summation order: 1e-13).  The batched solve against separate
 solves of every right-hand side (the Krylov processes are the same up to rounding), to the
 1e-8 true residual, with and without the learned preconditioner.
