@@ -66,6 +66,9 @@ def lib():
         L.orc_local_batch.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_local_batch.restype = ctypes.c_int64
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_potential_dl.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp,
+                                       ctypes.c_int, dp, ctypes.c_int, dp, dp]
+        L.orc_potential_dl.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -206,6 +209,17 @@ def local_batch(xyz, tri, taus, sigmas, grid, kind="bump", ss_order=4):
     chk = ctypes.c_double()
     n = lib().orc_local_batch(xp, tp, len(a), ap, bp, gp, len(g), CUTOFF[kind], ss_order, ctypes.byref(chk))
     return int(n), chk.value
+
+
+def potential_dl(xyz, tri, grid, alpha, pts, times, kind="bump"):
+    """Retarded double layer potential u(x_p, t_s) of eq. (RetardedPotential) of the density
+    sum alpha[i*M + j] b_i(t) phi_j(y); returns an array [len(times), len(pts)]."""
+    x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
+    a, ap = _d(np.ravel(alpha)); P, Pp = _d(np.reshape(pts, (-1, 3))); T, Tp = _d(np.ravel(times))
+    out = np.zeros(len(T) * len(P))
+    lib().orc_potential_dl(xp, len(x), tp, len(t), gp, len(g), CUTOFF[kind], ap, len(P), Pp, len(T), Tp,
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out.reshape(len(T), len(P))
 
 
 def num_threads():

@@ -710,6 +710,53 @@ int orc_rhs_plane_pulse(const double *xyz, int M, const int32_t *tri, int E, con
     return 0;
 }
 
+/* ------------------------------------------------------------------------------------------
+ * Retarded double layer potential of eq. (RetardedPotential) for the discrete density
+ * phi(y, t) = sum_i sum_j alpha[i*M + j] b_i(t) phi_j(y):
+ *   u(x, t) = -1/(4 pi) int_Gamma (n_y . (x - y)) / r * ( phi(y, t - r) / r^2
+ *                                                       + d_t phi(y, t - r) / r ) dGamma_y,
+ * r = |x - y|, for points x off Gamma and 0 <= t <= T.  Space: the 7-point rule on every flat
+ * triangle; every basis b_i is evaluated at the retarded time (zero outside its support).
+ * Output out[s*npts + p] for point p (pts[3p..3p+2]) and time times[s].
+ * ---------------------------------------------------------------------------------------- */
+int orc_potential_dl(const double *xyz, int M, const int32_t *tri, int E, const double *t, int N, int cut,
+                     const double *alpha, int npts, const double *pts, int ntimes, const double *times,
+                     double *out)
+{
+    double B[21], W[7];
+    orc_rule7(B, W);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int ps = 0; ps < npts * ntimes; ++ps) {
+        const int p = ps % npts, s = ps / npts;
+        const double *x = pts + 3 * p;
+        double u = 0.0;
+        for (int e = 0; e < E; ++e) {
+            tri_t X;
+            tri_build(xyz, tri, e, &X);
+            for (int q = 0; q < 7; ++q) {
+                double d[3];
+                for (int c = 0; c < 3; ++c)
+                    d[c] = x[c] - (B[3 * q] * X.P[0][c] + B[3 * q + 1] * X.P[1][c] + B[3 * q + 2] * X.P[2][c]);
+                const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const double nd = X.n[0] * d[0] + X.n[1] * d[1] + X.n[2] * d[2];
+                double phi = 0.0, dphi = 0.0;
+                for (int i = 0; i < N; ++i) {
+                    double bi[3];
+                    orc_basis(t, N, cut, i, times[s] - r, bi);
+                    if (bi[0] == 0.0 && bi[1] == 0.0) continue;
+                    double dens = 0.0;
+                    for (int a = 0; a < 3; ++a) dens += B[3 * q + a] * alpha[(size_t)i * M + X.v[a]];
+                    phi += bi[0] * dens;
+                    dphi += bi[1] * dens;
+                }
+                u += -X.area * W[q] / (4.0 * ORC_PI) * nd / r * (phi / (r * r) + dphi / r);
+            }
+        }
+        out[(size_t)s * npts + p] = u;
+    }
+    return 0;
+}
+
 /* Quadrature-point count of the method (one unit = one (x_q, y_q', k, i) with r inside the open
  * support of psi_{k,i}), over unordered triangle pairs, computed by brute force. */
 int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E, const double *t,
