@@ -164,6 +164,16 @@ tdbem_status tdbem_matvec_free(tdbem_ctx *ctx, const double *x, double *y, tdbem
 tdbem_status tdbem_solve(tdbem_ctx *ctx, const double *g, double *alpha, const tdbem_solve_opts *opts,
                          tdbem_solve_report *rep);
 
+/* The scattered field off the surface: the retarded double layer potential of eq.
+ * (RetardedPotential) of the density phi(y, t) = sum_i sum_j alpha[i*M + j] b_i(t) phi_j(y),
+ *   u(x, t) = -1/(4 pi) int_Gamma (n_y.(x - y))/r (phi(y, t - r)/r^2 + d_t phi(y, t - r)/r) dGamma_y,
+ * r = |x - y|, with the 7-point rule on every triangle.  alpha: device vector of N*M float64 (e.g.
+ * the solution of tdbem_solve); pts: host array of 3*npts coordinates (points off Gamma); times:
+ * host array of ntimes values in [0, T]; u: device array of ntimes*npts float64, u[s*npts + p].
+ * Needs the mesh and the grid (no assembly).  TDBEM_EINVAL for a time outside [0, T]. */
+tdbem_status tdbem_potential_dl(tdbem_ctx *ctx, const double *alpha, int64_t npts, const double *pts,
+                                int32_t ntimes, const double *times, double *u);
+
 /* Y_r = A X_r for nrhs right-hand sides at once (the block matvec of Section 3.2; every stored
  * value is read once per group of 4 right-hand sides): X, Y device arrays of nrhs*N*M float64,
  * vector r at offset r*N*M.  1 <= nrhs <= 1024.  Requires tdbem_assemble. */

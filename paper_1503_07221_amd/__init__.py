@@ -29,7 +29,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
-                    "tdbem_matvec_multi", "tdbem_solve_multi",
+                    "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
 
@@ -122,6 +122,7 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
     L.tdbem_matvec_multi.argtypes = [vp, i32, vp, vp]
+    L.tdbem_potential_dl.argtypes = [vp, vp, i64, P(dp), i32, P(dp), vp]
     L.tdbem_solve_multi.argtypes = [vp, i32, vp, vp, P(SolveOpts), P(SolveReport)]
     fp = P(ctypes.c_float)
     L.tdbem_lp_num_params.argtypes = [i32]
@@ -273,6 +274,16 @@ class Context:
         d = rep.as_dict()
         d["converged"] = st == 0
         return alpha, d
+
+    def potential_dl(self, alpha, pts, times, out=None):
+        """Retarded double layer potential u[s, p] at the points pts (npts x 3, host) and the
+        times (host), from the density coefficients alpha (device, N*M)."""
+        P = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        T = np.ascontiguousarray(times, dtype=np.float64).ravel()
+        u = self.torch.empty(len(T), len(P), dtype=self.torch.float64, device=self.device) if out is None else out
+        self._check(self.lib.tdbem_potential_dl(self.h, self._dev(alpha, self.N * self.M), len(P), _dptr(P), len(T),
+                                                _dptr(T), ctypes.c_void_p(u.data_ptr())))
+        return u
 
     # --- many right-hand sides ------------------------------------------------------------------------
     def _dev2(self, X):

@@ -1428,6 +1428,34 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
 
 
 // ---------------------------------------------------------------------------------------------
+// Retarded double layer potential (eq. (RetardedPotential)): the field off the surface.
+// ---------------------------------------------------------------------------------------------
+tdbem_status tdbem_potential_dl(tdbem_ctx* c, const double* alpha, int64_t npts, const double* pts, int32_t ntimes,
+                                const double* times, double* u)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!alpha || !pts || !times || !u) FAIL(c, TDBEM_EINVAL, "null argument");
+    if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
+    if (npts < 1 || ntimes < 1) FAIL(c, TDBEM_EINVAL, "need at least one point and one time");
+    const double T = c->t[c->N - 1];
+    for (int s = 0; s < ntimes; ++s)
+        if (!(times[s] >= 0.0 && times[s] <= T)) FAIL(c, TDBEM_EINVAL, "time %d = %g outside [0, T]", s, times[s]);
+    for (int64_t p = 0; p < 3 * npts; ++p)
+        if (!std::isfinite(pts[p])) FAIL(c, TDBEM_EINVAL, "point coordinate %lld is not finite", (long long)p);
+    TRY(set_device(c));
+    DBuf dp, dt, phiq;
+    TRY(upload(c, dp, pts, (size_t)(3 * npts)));
+    TRY(upload(c, dt, times, (size_t)ntimes));
+    ALLOC(c, phiq, sizeof(double) * (size_t)c->E * 7 * c->N);
+    launch_potential(c->geom(), c->d_t.as<double>(), c->N, c->cut, c->M, alpha, phiq.as<double>(), npts,
+                     dp.as<double>(), ntimes, dt.as<double>(), u, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Many right-hand sides: one product per iteration serves all of them (the stored operator is
 // read once per group of 4 right-hand sides); FGMRES runs per right-hand side on its own Krylov
 // basis, with all Gram-Schmidt coefficients of an iteration fetched in one host round trip.

@@ -356,6 +356,10 @@ void launch_lp_randn(int64_t n, uint64_t seed, uint64_t stream, double* out, hip
 void launch_lp_smooth(LpGraph g, const double* x, double* y, hipStream_t s);
 void launch_matvec_transpose(BandView band, const double* val, const float* valf, const double* y, double* x,
                              hipStream_t s);
+// u[s*npts + p] = retarded double layer potential at pts[3p..] and times[s] (device arrays);
+// phiq: workspace of E*7*N doubles.
+void launch_potential(GeomView g, const double* t, int N, int cut, int M, const double* alpha, double* phiq,
+                      int64_t npts, const double* pts, int ntimes, const double* times, double* u, hipStream_t s);
 // Y[r*ldy + .] = A X[r*ldx + .] for r < nrhs (full operator).
 void launch_matvec_multi(BandView band, const double* val, const float* valf, int nrhs, const double* X, int64_t ldx,
                          double* Y, int64_t ldy, hipStream_t s);
