@@ -59,6 +59,7 @@ def parse():
                     help="Adam steps (batch 8, lr 1e-3) of the learned preconditioner, then half as many at 5e-4")
     ap.add_argument("--lp-restart", type=int, default=600, help="FGMRES restart of the learned solve")
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
+    ap.add_argument("--no-potential", action="store_true", help="skip the field evaluation leg")
     ap.add_argument("--batch-rhs", type=int, default=32,
                     help="right-hand sides of the batched learned solve (0 = skip the batched leg)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -134,6 +135,30 @@ def sample_entries(ctx, cfg, n, seed):
     j = rng.integers(0, M, n)
     l = rng.integers(0, M, n)
     return k, i, j, l
+
+
+def potential_leg(ctx, tb, alpha, cfg):
+    """The scattered field of the FP64 solution on a 257 x 257 grid of the plane z = 0 over
+    [-3, 3]^2 (66049 points, as in the paper's field evaluation) at 40 equally spaced times."""
+    import numpy as np
+    import torch
+    T = float(cfg["grid"][-1])
+    g1 = np.linspace(-3.0, 3.0, 257)
+    X, Y = np.meshgrid(g1, g1, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    times = np.linspace(T / 40, T, 40)
+    u = ctx.potential_dl(alpha, pts[:1024], times[:8])       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = ctx.potential_dl(alpha, pts, times)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    E = len(cfg["mesh"][1])
+    evals = len(pts) * len(times) * E * 7
+    print(f"# potential: {len(pts)} points x {len(times)} times in {ms:.0f} ms", file=sys.stderr, flush=True)
+    return {"points": int(len(pts)), "times": int(len(times)), "ms": ms,
+            "point_time_per_s": len(pts) * len(times) / (ms * 1e-3),
+            "quadrature_evals_per_s": evals / (ms * 1e-3), "max_abs_u": float(u.abs().max())}
 
 
 def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
@@ -351,6 +376,8 @@ def main():
             res = g - ctx.matvec(alpha32)
             mixed["rel_residual_fp64_operator"] = float(torch.linalg.norm(res) / torch.linalg.norm(g))
         out["mixed"] = mixed
+    if not args.no_potential and not args.skip_solve:
+        out["potential"] = potential_leg(ctx, tb, alpha, cfg)
     if not args.no_learned and not args.skip_solve:
         out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"))
     if not args.no_cpu_baseline:

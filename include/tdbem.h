@@ -170,7 +170,8 @@ tdbem_status tdbem_solve(tdbem_ctx *ctx, const double *g, double *alpha, const t
  * r = |x - y|, with the 7-point rule on every triangle.  alpha: device vector of N*M float64 (e.g.
  * the solution of tdbem_solve); pts: host array of 3*npts coordinates (points off Gamma); times:
  * host array of ntimes values in [0, T]; u: device array of ntimes*npts float64, u[s*npts + p].
- * Needs the mesh and the grid (no assembly).  TDBEM_EINVAL for a time outside [0, T]. */
+ * Needs the mesh and the grid (no assembly).  TDBEM_EINVAL for a time outside [0, T] or more than
+ * 1024 time nodes. */
 tdbem_status tdbem_potential_dl(tdbem_ctx *ctx, const double *alpha, int64_t npts, const double *pts,
                                 int32_t ntimes, const double *times, double *u);
 

@@ -1438,6 +1438,7 @@ tdbem_status tdbem_potential_dl(tdbem_ctx* c, const double* alpha, int64_t npts,
     if (!alpha || !pts || !times || !u) FAIL(c, TDBEM_EINVAL, "null argument");
     if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
     if (npts < 1 || ntimes < 1) FAIL(c, TDBEM_EINVAL, "need at least one point and one time");
+    if (c->N > 1024) FAIL(c, TDBEM_EINVAL, "the field evaluation takes at most 1024 time nodes");
     const double T = c->t[c->N - 1];
     for (int s = 0; s < ntimes; ++s)
         if (!(times[s] >= 0.0 && times[s] <= T)) FAIL(c, TDBEM_EINVAL, "time %d = %g outside [0, T]", s, times[s]);

@@ -28,6 +28,7 @@ __device__ inline void pot_rule7(int q, double& l0, double& l1, double& l2, doub
 
 constexpr int kPotTimes = 8;     // evaluation times per lane
 constexpr int kPotTri = 64;      // triangles staged in LDS per pass
+constexpr int kPotMaxN = 1024;   // time nodes staged in LDS (the entry point rejects more)
 
 // phiq[(e*7 + q)*N + i] = sum_a lam_a(q) alpha[i*M + v_a(e)]: the density of b_i at point q of e.
 __global__ void __launch_bounds__(256)
@@ -55,6 +56,8 @@ k_potential(GeomView g, const double* __restrict__ tg, int N, int cut, const dou
     __shared__ double sy[kPotTri][7][3];
     __shared__ double sc[kPotTri][7];
     __shared__ double sn[kPotTri][3];
+    __shared__ double tsh[kPotMaxN];
+    for (int z = threadIdx.x; z < N; z += blockDim.x) tsh[z] = tg[z];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s0 = blockIdx.y * kPotTimes;
     const int E = g.E;
@@ -101,17 +104,27 @@ k_potential(GeomView g, const double* __restrict__ tg, int N, int cut, const dou
                 for (int s = 0; s < kPotTimes; ++s) {
                     const double tr = ts[s] - r;
                     if (!(tr > 0.0)) continue;
-                    // interval [t_i0, t_i0+1) holding tr (tr < t_{N-1} since r > 0 and t <= T)
+                    // interval [t_lo, t_lo+1) holding tr (tr < t_{N-1} since r > 0 and t <= T)
                     int lo = 0, hi = N - 1;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
-                        if (tg[mid] <= tr) lo = mid;
+                        if (tsh[mid] <= tr) lo = mid;
                         else hi = mid;
                     }
-                    double b0, db0, dd, b1 = 0.0, db1 = 0.0;
-                    basis_eval(tg, N, cut, lo, tr, b0, db0, dd);
-                    if (lo + 1 < N) basis_eval(tg, N, cut, lo + 1, tr, b1, db1, dd);
-                    const double pa = ph[lo], pb = lo + 1 < N ? ph[lo + 1] : 0.0;
+                    // on that interval b_lo = 1 - F(u) and b_lo+1 = F(u), u = (tr - t_lo)/h, one
+                    // cutoff evaluation for both; b_0 carries the causal factor 8 (t/h_1)^2
+                    const double ih = 1.0 / (tsh[lo + 1] - tsh[lo]);
+                    const double uu = (tr - tsh[lo]) * ih;
+                    double F, F1, F2;
+                    cutoff_eval(cut, uu, F, F1, F2);
+                    double b0 = 1.0 - F, db0 = -F1 * ih;
+                    const double b1 = F, db1 = F1 * ih;
+                    if (lo == 0) {
+                        const double c = 8.0 * uu * uu, c1 = 16.0 * uu * ih;
+                        db0 = c1 * b0 + c * db0;
+                        b0 = c * b0;
+                    }
+                    const double pa = ph[lo], pb = ph[lo + 1];
                     const double phi = b0 * pa + b1 * pb, dphi = db0 * pa + db1 * pb;
                     acc[s] = fma(f, (phi * ir + dphi) * ir, acc[s]);
                 }
