@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--lp-steps", type=int, default=300,
                     help="Adam steps (batch 8, lr 1e-3) of the learned preconditioner, then half as many at 5e-4")
+    ap.add_argument("--lp-layers", type=int, default=4, help="message-passing layers of the learned preconditioner")
     ap.add_argument("--lp-restart", type=int, default=600, help="FGMRES restart of the learned solve")
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
     ap.add_argument("--no-potential", action="store_true", help="skip the field evaluation leg")
@@ -167,7 +168,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
     import numpy as np
     import torch
     ctx.assemble(tb.FP64)
-    ctx.lp_init(4, seed=3)
+    ctx.lp_init(args.lp_layers, seed=3)
     hist, trep = ctx.lp_train(steps=args.lp_steps, batch=8, lr=1e-3, seed=4)
     hist2, trep2 = ctx.lp_train(steps=max(1, args.lp_steps // 2), batch=8, lr=5e-4, seed=5)
     hist = np.concatenate([hist, hist2])
@@ -182,7 +183,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
         ctx.lp_apply(x)
     e1.record()
     e1.synchronize()
-    res = {"layers": 4, "hidden": 64, "params": ctx.lp_num_params(), "train_steps": len(hist), "batch": 8,
+    res = {"layers": args.lp_layers, "hidden": 64, "params": ctx.lp_num_params(), "train_steps": len(hist), "batch": 8,
            "train_ms": trep["ms"], "train_samples": int(trep["samples"]), "loss_first": float(hist[0]),
            "loss_last10": float(hist[-10:].mean()), "apply_ms": e0.elapsed_time(e1) / 10}
     nrm = torch.linalg.norm(alpha_ref)
