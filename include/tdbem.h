@@ -176,9 +176,21 @@ tdbem_status tdbem_potential_dl(tdbem_ctx *ctx, const double *alpha, int64_t npt
                                 int32_t ntimes, const double *times, double *u);
 
 /* Y_r = A X_r for nrhs right-hand sides at once (the block matvec of Section 3.2; every stored
- * value is read once per group of 4 right-hand sides): X, Y device arrays of nrhs*N*M float64,
- * vector r at offset r*N*M.  1 <= nrhs <= 1024.  Requires tdbem_assemble. */
+ * value is read once per group of right-hand sides, see tdbem_matvec_multi_tuning): X, Y device
+ * arrays of nrhs*N*M float64, vector r at offset r*N*M.  1 <= nrhs <= 1024.  Requires tdbem_assemble. */
 tdbem_status tdbem_matvec_multi(tdbem_ctx *ctx, int32_t nrhs, const double *X, double *Y);
+
+/* The multi-vector product has kernel variants (right-hand sides per pass, trial range staged in
+ * LDS); on its first use after an assembly the library times each on 8 vectors of the assembled
+ * operator and keeps the fastest.  This call runs that tuning if needed and reports the choice
+ * and its time per right-hand side in ms (any output pointer may be NULL). */
+tdbem_status tdbem_matvec_multi_tuning(tdbem_ctx *ctx, int32_t *rhs_per_pass, int32_t *staged_range,
+                                       double *ms_per_rhs);
+
+/* Use variant v (0 <= v < the number of variants, which the call returns through nvariants when
+ * not NULL) of the multi-vector product until the next assembly instead of the timed choice;
+ * v = -1 returns to timing.  TDBEM_EINVAL for another v. */
+tdbem_status tdbem_matvec_multi_set_variant(tdbem_ctx *ctx, int32_t v, int32_t *nvariants);
 
 /* Solve A alpha_r = g_r for nrhs right-hand sides together: FGMRES(restart) from alpha_r = 0 on
  * every right-hand side with its own Krylov basis, sharing one multi-right-hand-side product per

@@ -30,6 +30,7 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
                     "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
+                    "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
 
@@ -122,6 +123,8 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
     L.tdbem_matvec_multi.argtypes = [vp, i32, vp, vp]
+    L.tdbem_matvec_multi_tuning.argtypes = [vp, P(i32), P(i32), P(dp)]
+    L.tdbem_matvec_multi_set_variant.argtypes = [vp, i32, P(i32)]
     L.tdbem_potential_dl.argtypes = [vp, vp, i64, P(dp), i32, P(dp), vp]
     L.tdbem_solve_multi.argtypes = [vp, i32, vp, vp, P(SolveOpts), P(SolveReport)]
     fp = P(ctypes.c_float)
@@ -298,6 +301,20 @@ class Context:
         Y = self.torch.empty_like(X) if out is None else out
         self._check(self.lib.tdbem_matvec_multi(self.h, X.shape[0], self._dev2(X), self._dev2(Y)))
         return Y
+
+    def matvec_multi_tuning(self):
+        """(right-hand sides per pass, staged trial range, ms per right-hand side) of the variant
+        of the multi-vector product chosen by timing on the assembled operator."""
+        rc, sp, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(self.lib.tdbem_matvec_multi_tuning(self.h, ctypes.byref(rc), ctypes.byref(sp), ctypes.byref(ms)))
+        return rc.value, sp.value, ms.value
+
+    def matvec_multi_set_variant(self, v):
+        """Force variant v of the multi-vector product (-1: timed choice); returns the number of
+        variants."""
+        nv = ctypes.c_int32()
+        self._check(self.lib.tdbem_matvec_multi_set_variant(self.h, int(v), ctypes.byref(nv)))
+        return nv.value
 
     def solve_multi(self, G, tol=1e-8, restart=600, max_it=2000, precond_kind=PRECOND_ALG1, out=None,
                     progress=None):

@@ -198,6 +198,9 @@ struct tdbem_ctx {
         int64_t ntrain = 0;
     } lp;
     uint64_t graph_version = 0;   // changes with the mesh and the time grid
+    // multi-vector product: variant chosen by timing on the assembled operator (-1: not yet)
+    int mm_variant = -1;
+    std::vector<double> mm_ms;    // measured time per right-hand side of every variant
 
     GeomView geom() const
     {
@@ -685,6 +688,7 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     unsigned long long counts[2];
     HIPCHK(c, hipMemcpy(counts, c->d_counter.p, sizeof(counts), hipMemcpyDeviceToHost));
     c->assembled = true;
+    c->mm_variant = -1;
     if (rep) {
         float ms[4];
         for (int s = 0; s < 4; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
@@ -1461,6 +1465,72 @@ tdbem_status tdbem_potential_dl(tdbem_ctx* c, const double* alpha, int64_t npts,
 // read once per group of 4 right-hand sides); FGMRES runs per right-hand side on its own Krylov
 // basis, with all Gram-Schmidt coefficients of an iteration fetched in one host round trip.
 // ---------------------------------------------------------------------------------------------
+namespace {
+// Autotuning of the multi-vector product: every variant runs twice on 8 vectors of ones over the
+// assembled operator, timed with HIP events on the context's stream; the fastest is kept until the
+// next assembly.
+tdbem_status multi_tune(tdbem_ctx* c)
+{
+    if (c->mm_variant >= 0) return TDBEM_OK;
+    const int64_t n = (int64_t)c->N * c->M;
+    const int R = 8;
+    DBuf X, Y;
+    ALLOC(c, X, sizeof(double) * (size_t)R * n);
+    ALLOC(c, Y, sizeof(double) * (size_t)R * n);
+    launch_fill(X.as<double>(), 1.0, R * n, c->stream);
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int nv = matvec_multi_variants();
+    c->mm_ms.assign(nv, 0.0);
+    int best = 0;
+    for (int v = 0; v < nv; ++v) {
+        launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, X.as<double>(), n, Y.as<double>(), n, v, c->stream);
+        (void)hipEventRecord(e0, c->stream);
+        for (int rep = 0; rep < 2; ++rep)
+            launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, X.as<double>(), n, Y.as<double>(), n, v,
+                                c->stream);
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        c->mm_ms[v] = ms / (2.0 * R);
+        if (c->mm_ms[v] < c->mm_ms[best]) best = v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(c, hipGetLastError());
+    c->mm_variant = best;
+    return TDBEM_OK;
+}
+}  // namespace
+
+tdbem_status tdbem_matvec_multi_tuning(tdbem_ctx* c, int32_t* rhs_per_pass, int32_t* staged_range,
+                                       double* ms_per_rhs)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before tuning the multi-vector product");
+    TRY(set_device(c));
+    TRY(multi_tune(c));
+    if (rhs_per_pass) *rhs_per_pass = matvec_multi_variant_rc(c->mm_variant);
+    if (staged_range) *staged_range = matvec_multi_variant_span(c->mm_variant);
+    if (ms_per_rhs) *ms_per_rhs = c->mm_ms[c->mm_variant];
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_matvec_multi_set_variant(tdbem_ctx* c, int32_t v, int32_t* nvariants)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    const int nv = matvec_multi_variants();
+    if (nvariants) *nvariants = nv;
+    if (v < -1 || v >= nv) FAIL(c, TDBEM_EINVAL, "variant %d outside -1..%d", v, nv - 1);
+    c->mm_variant = v;
+    if (v >= 0 && (int)c->mm_ms.size() != nv) c->mm_ms.assign(nv, 0.0);
+    return TDBEM_OK;
+}
+
 tdbem_status tdbem_matvec_multi(tdbem_ctx* c, int32_t nrhs, const double* X, double* Y)
 {
     if (!c) return TDBEM_EINVAL;
@@ -1469,8 +1539,9 @@ tdbem_status tdbem_matvec_multi(tdbem_ctx* c, int32_t nrhs, const double* X, dou
     if (nrhs < 1 || nrhs > 1024) FAIL(c, TDBEM_EINVAL, "need 1 <= nrhs <= 1024, got %d", nrhs);
     if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before the matvec");
     TRY(set_device(c));
+    TRY(multi_tune(c));
     const int64_t n = (int64_t)c->N * c->M;
-    launch_matvec_multi(c->band(), c->valf64(), c->valf32(), nrhs, X, n, Y, n, c->stream);
+    launch_matvec_multi(c->band(), c->valf64(), c->valf32(), nrhs, X, n, Y, n, c->mm_variant, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return TDBEM_OK;
@@ -1494,6 +1565,8 @@ tdbem_status tdbem_solve_multi(tdbem_ctx* c, int32_t nrhs, const double* G, doub
         TRY(lp_need_params(c));
         TRY(lp_graph(c));
     }
+    TRY(multi_tune(c));
+    const int mv = c->mm_variant;
     const auto t_start = std::chrono::steady_clock::now();
     hipStream_t st = c->stream;
     const int64_t n = (int64_t)c->N * c->M;
@@ -1566,7 +1639,7 @@ tdbem_status tdbem_solve_multi(tdbem_ctx* c, int32_t nrhs, const double* G, doub
             if (!active) break;
             // w_r = A z_r for every right-hand side (finished ones too: their columns are unused)
             launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, Zd + (int64_t)j * n, (int64_t)m * n,
-                                Vd + (int64_t)(j + 1) * n, (int64_t)(m + 1) * n, st);
+                                Vd + (int64_t)(j + 1) * n, (int64_t)(m + 1) * n, mv, st);
             HIPCHK(c, hipGetLastError());
             ++products;
             for (int r = 0; r < R; ++r) {
@@ -1626,7 +1699,7 @@ tdbem_status tdbem_solve_multi(tdbem_ctx* c, int32_t nrhs, const double* G, doub
             launch_sub_combination(Alpha + r * n, Zr(r, 0), jd, n, n, Hr(r), 1.0, st);
         }
         // true residuals W_r = g_r - A alpha_r
-        launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, Alpha, n, Wd, n, st);
+        launch_matvec_multi(c->band(), c->valf64(), c->valf32(), R, Alpha, n, Wd, n, mv, st);
         ++products;
         for (int r = 0; r < R; ++r) {
             launch_axpby(Wd + r * n, G + r * n, 1.0, -1.0, n, st);

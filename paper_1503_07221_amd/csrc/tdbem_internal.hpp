@@ -360,7 +360,11 @@ void launch_matvec_transpose(BandView band, const double* val, const float* valf
 // phiq: workspace of E*7*N doubles.
 void launch_potential(GeomView g, const double* t, int N, int cut, int M, const double* alpha, double* phiq,
                       int64_t npts, const double* pts, int ntimes, const double* times, double* u, hipStream_t s);
-// Y[r*ldy + .] = A X[r*ldx + .] for r < nrhs (full operator).
+// Y[r*ldy + .] = A X[r*ldx + .] for r < nrhs (full operator) with kernel variant `variant`
+// (0 .. matvec_multi_variants()-1: right-hand sides per pass and staged trial range).
 void launch_matvec_multi(BandView band, const double* val, const float* valf, int nrhs, const double* X, int64_t ldx,
-                         double* Y, int64_t ldy, hipStream_t s);
+                         double* Y, int64_t ldy, int variant, hipStream_t s);
+int matvec_multi_variants();
+int matvec_multi_variant_rc(int v);
+int matvec_multi_variant_span(int v);
 }  // namespace tdbem

@@ -39,20 +39,30 @@ def test_matvec_multi(ctx, tb, oracle_mod):
     A = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, c["grid"], kind="erf"))
     ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "erf"); ctx.assemble()
     X = np.random.default_rng(41).standard_normal((11, N * M))
-    Y = ctx.matvec_multi(torch.from_numpy(X).cuda()).cpu().numpy()
     Yr = X @ A.T
-    for r in range(11):
-        assert np.linalg.norm(Y[r] - Yr[r]) <= 1e-13 * np.linalg.norm(Yr[r]), r
+    nv = ctx.matvec_multi_set_variant(-1)
+    with pytest.raises(tb.TdbemError):
+        ctx.matvec_multi_set_variant(nv)
+    for v in range(nv):
+        ctx.matvec_multi_set_variant(v)
+        Y = ctx.matvec_multi(torch.from_numpy(X).cuda()).cpu().numpy()
+        for r in range(11):
+            assert np.linalg.norm(Y[r] - Yr[r]) <= 1e-13 * np.linalg.norm(Yr[r]), (v, r)
     c2 = get_config("sphere5120_graded64")
     ctx.set_mesh(*c2["mesh"]); ctx.set_time_grid(c2["grid"], c2["cutoff"])
     n = len(c2["grid"]) * len(c2["mesh"][0])
     Xg = torch.from_numpy(np.random.default_rng(42).standard_normal((9, n))).cuda()
     for prec in (tb.FP64, tb.MIXED):
         ctx.assemble(prec)
-        Yg = ctx.matvec_multi(Xg)
-        for r in (0, 7, 8):
-            y1 = ctx.matvec(Xg[r].contiguous())
-            assert torch.linalg.norm(Yg[r] - y1).item() <= 1e-13 * torch.linalg.norm(y1).item(), (prec, r)
+        Y1 = [ctx.matvec(Xg[r].contiguous()) for r in (0, 7, 8)]
+        rc, span, ms = ctx.matvec_multi_tuning()        # timed choice on this operator
+        assert rc >= 1 and span >= 1 and ms > 0.0
+        nv = ctx.matvec_multi_set_variant(-1)
+        for v in list(range(nv)) + [-1]:                 # every variant, then the timed one
+            ctx.matvec_multi_set_variant(v)
+            Yg = ctx.matvec_multi(Xg)
+            for y1, r in zip(Y1, (0, 7, 8)):
+                assert torch.linalg.norm(Yg[r] - y1).item() <= 1e-13 * torch.linalg.norm(y1).item(), (prec, v, r)
     ctx.set_mesh(*icosphere(0)); ctx.set_time_grid(np.array([0.0, 1.0, 2.0])); ctx.assemble()   # release storage
 
 
