@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--lp-restart", type=int, default=600, help="FGMRES restart of the learned solve")
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
     ap.add_argument("--no-potential", action="store_true", help="skip the field evaluation leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-meshes group assembly leg")
     ap.add_argument("--batch-rhs", type=int, default=32,
                     help="right-hand sides of the batched learned solve (0 = skip the batched leg)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -136,6 +137,37 @@ def sample_entries(ctx, cfg, n, seed):
     j = rng.integers(0, M, n)
     l = rng.integers(0, M, n)
     return k, i, j, l
+
+
+def uneven_leg(tb):
+    """Eight geodesic spheres (frequency 4..16: 320 to 5120 triangles) with 16 to 64 graded bases,
+    assembled one after the other and then together (one context and stream each)."""
+    import numpy as np
+    from workloads import geodesic_sphere, graded_grid
+    nus = [4, 5, 6, 7, 8, 10, 12, 16]
+    ctxs = []
+    for r, nu in enumerate(nus):
+        c = tb.Context(0, own_stream=True)
+        c.set_mesh(*geodesic_sphere(nu))
+        c.set_time_grid(graded_grid(16 + (64 - 16) * r // 7, 8.0, seed=30 + r))
+        ctxs.append(c)
+    tb.assemble_group(ctxs)                                   # warm-up
+    t0 = time.perf_counter()
+    quad = 0
+    for c in ctxs:
+        quad += c.assemble()["quad_evals"]
+    seq = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    reps = tb.assemble_group(ctxs)
+    grp = (time.perf_counter() - t0) * 1e3
+    assert sum(r["quad_evals"] for r in reps) == quad
+    for c in ctxs:
+        c.close()
+    print(f"# uneven meshes: 8 assemblies {seq:.0f} ms one after the other, {grp:.0f} ms together",
+          file=sys.stderr, flush=True)
+    return {"meshes": [20 * nu * nu for nu in nus], "time_bases": [16 + (64 - 16) * r // 7 for r in range(8)],
+            "quad_evals": int(quad), "sequential_ms": seq, "group_ms": grp,
+            "sequential_quad_evals_per_s": quad / (seq * 1e-3), "group_quad_evals_per_s": quad / (grp * 1e-3)}
 
 
 def potential_leg(ctx, tb, alpha, cfg):
@@ -379,6 +411,8 @@ def main():
         out["mixed"] = mixed
     if not args.no_potential and not args.skip_solve:
         out["potential"] = potential_leg(ctx, tb, alpha, cfg)
+    if not args.no_uneven:
+        out["uneven"] = uneven_leg(tb)
     if not args.no_learned and not args.skip_solve:
         out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"))
     if not args.no_cpu_baseline:

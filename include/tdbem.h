@@ -124,6 +124,15 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdb
  * TDBEM_ESTATE without mesh and grid, TDBEM_ENOMEM if the storage does not fit. */
 tdbem_status tdbem_assemble(tdbem_ctx *ctx, tdbem_precision prec, tdbem_assembly_report *rep);
 
+/* Assemble the problems of n distinct contexts (meshes and grids of any sizes, all on one device)
+ * concurrently: one host thread per context runs tdbem_assemble on that context's stream, so the
+ * kernels of the problems overlap on the device (give every context its own stream for that).
+ * reps: NULL or an array of n reports.  Returns the first non-OK status in context order (its
+ * message is in that context); TDBEM_EINVAL for a NULL context, n outside 1..256 or a context
+ * listed twice. */
+tdbem_status tdbem_assemble_group(tdbem_ctx *const *ctxs, int32_t n, tdbem_precision prec,
+                                  tdbem_assembly_report *reps);
+
 /* Copy selected entries to the host: out[s] = A_{k[s], i[s]}(j[s], l[s]) for s < n (host
  * arrays).  Entries outside the stored band are zero by eq. (SparsitySmallBlock). */
 tdbem_status tdbem_get_entries(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,

@@ -17,7 +17,7 @@ import numpy as np
 
 from .build import LIB_PATH, build_library
 
-__all__ = ["Context", "TdbemError", "load_library", "build_library", "LIB_PATH", "EXPORTED_SYMBOLS",
+__all__ = ["Context", "TdbemError", "assemble_group", "load_library", "build_library", "LIB_PATH", "EXPORTED_SYMBOLS",
            "FP64", "MIXED", "CUTOFF_BUMP", "CUTOFF_ERF", "PRECOND_ALG1", "PRECOND_LEARNED",
            "PRECOND_LEARNED_THEN_ALG1"]
 
@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
                     "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
-                    "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant",
+                    "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
 
@@ -123,6 +123,7 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_free.argtypes = [vp, vp, vp, P(AssemblyReport)]
     L.tdbem_solve.argtypes = [vp, vp, vp, P(SolveOpts), P(SolveReport)]
     L.tdbem_matvec_multi.argtypes = [vp, i32, vp, vp]
+    L.tdbem_assemble_group.argtypes = [P(vp), i32, ctypes.c_int, P(AssemblyReport)]
     L.tdbem_matvec_multi_tuning.argtypes = [vp, P(i32), P(i32), P(dp)]
     L.tdbem_matvec_multi_set_variant.argtypes = [vp, i32, P(i32)]
     L.tdbem_potential_dl.argtypes = [vp, vp, i64, P(dp), i32, P(dp), vp]
@@ -144,6 +145,20 @@ def load_library(path=LIB_PATH):
     return L
 
 
+def assemble_group(contexts, precision=FP64):
+    """Assemble the problems of several contexts concurrently (one host thread per context, each
+    on its context's stream); returns the list of assembly reports."""
+    lib = load_library()
+    n = len(contexts)
+    hs = (ctypes.c_void_p * n)(*[c.h for c in contexts])
+    reps = (AssemblyReport * n)()
+    st = lib.tdbem_assemble_group(hs, n, int(precision), reps)
+    if st != 0:
+        msgs = [c.lib.tdbem_last_error(c.h).decode() for c in contexts]
+        raise TdbemError(st, "; ".join(m for m in msgs if m) or "group assembly failed")
+    return [r.as_dict() for r in reps]
+
+
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -155,14 +170,16 @@ def _iptr(a):
 class Context:
     """One library context on a HIP device, running on torch's current stream of that device."""
 
-    def __init__(self, device=0, ss_order=4):
+    def __init__(self, device=0, ss_order=4, own_stream=False):
+        """own_stream: run on a new stream of default priority (contexts assembled together with
+        assemble_group overlap only on distinct streams) instead of torch's current stream."""
         import torch
         self.torch = torch
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("tdbem needs a HIP device (torch.cuda.is_available() is False)")
         self.device = torch.device("cuda", device)
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = torch.cuda.Stream(self.device) if own_stream else torch.cuda.current_stream(self.device)
         opt = _Options(device, ctypes.c_void_p(self.stream.cuda_stream), ss_order)
         h = ctypes.c_void_p()
         st = self.lib.tdbem_create(ctypes.byref(h), ctypes.byref(opt))

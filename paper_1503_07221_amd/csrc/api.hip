@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tdbem.h"
@@ -707,6 +708,28 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         rep->ms_singular = ms[3];
         rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3];
     }
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_assemble_group(tdbem_ctx* const* ctxs, int32_t n, tdbem_precision prec,
+                                  tdbem_assembly_report* reps)
+{
+    if (!ctxs || n < 1 || n > 256) return TDBEM_EINVAL;
+    for (int a = 0; a < n; ++a) {
+        if (!ctxs[a]) return TDBEM_EINVAL;
+        for (int b = 0; b < a; ++b)
+            if (ctxs[a] == ctxs[b]) FAIL(ctxs[a], TDBEM_EINVAL, "a context appears twice in the group");
+    }
+    // one host thread per context: each runs the whole assembly on its context's stream, so the
+    // kernels of small problems run side by side and fill the device together
+    std::vector<tdbem_status> st(n, TDBEM_OK);
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int a = 0; a < n; ++a)
+        th.emplace_back([&, a]() { st[a] = tdbem_assemble(ctxs[a], prec, reps ? reps + a : nullptr); });
+    for (auto& t : th) t.join();
+    for (int a = 0; a < n; ++a)
+        if (st[a] != TDBEM_OK) return st[a];
     return TDBEM_OK;
 }
 

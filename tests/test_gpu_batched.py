@@ -103,3 +103,34 @@ def test_solve_multi_matches_single_solves(ctx, tb):
     with pytest.raises(tb.TdbemError) as e:
         ctx.solve_multi(G, precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
     assert e.value.status == -1
+
+
+def test_assemble_group_uneven_meshes(tb):
+    """Three geodesic spheres of different sizes and grids assembled together (one stream each)
+    give the entries and quadrature counts of separate assemblies (the atomic sums may add in
+    another order: 1e-13 of the block maximum)."""
+    from workloads import geodesic_sphere
+    probs = [(geodesic_sphere(4), graded_grid(8, 4.0, seed=21)), (geodesic_sphere(5), graded_grid(10, 5.0, seed=22)),
+             (geodesic_sphere(7), graded_grid(12, 6.0, seed=23))]
+    ctxs = []
+    for (xyz, tri), grid in probs:
+        c = tb.Context(0, own_stream=True)
+        c.set_mesh(xyz, tri); c.set_time_grid(grid)
+        ctxs.append(c)
+    reps = tb.assemble_group(ctxs)
+    rng = np.random.default_rng(61)
+    ref = tb.Context(0)
+    for c, rep, ((xyz, tri), grid) in zip(ctxs, reps, probs):
+        M, N = len(xyz), len(grid)
+        K = rng.integers(0, N, 3000); I = np.minimum(K + rng.integers(-3, 2, 3000), N - 1).clip(0)
+        J = rng.integers(0, M, 3000); L = rng.integers(0, M, 3000)
+        eg = c.get_entries(K, I, J, L)
+        ref.set_mesh(xyz, tri); ref.set_time_grid(grid)
+        r1 = ref.assemble()
+        e1 = ref.get_entries(K, I, J, L)
+        assert rep["quad_evals"] == r1["quad_evals"]
+        assert np.abs(eg - e1).max() <= 1e-13 * np.abs(e1).max()
+    with pytest.raises(tb.TdbemError):
+        tb.assemble_group([ctxs[0], ctxs[0]])
+    for c in ctxs + [ref]:
+        c.close()

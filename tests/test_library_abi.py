@@ -48,6 +48,7 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.tdbem_potential_dl(None, None, 1, None, 1, None, None) == -1
     assert lib.tdbem_matvec_multi_tuning(None, None, None, None) == -1
     assert lib.tdbem_matvec_multi_set_variant(None, 0, None) == -1
+    assert lib.tdbem_assemble_group(None, 2, 0, None) == -1
     assert lib.tdbem_solve_multi(None, 2, None, None, None, None) == -1
     assert lib.tdbem_lp_apply(None, None, None) == -1
     assert lib.tdbem_lp_gradient(None, None, None, None, None) == -1

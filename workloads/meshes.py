@@ -65,6 +65,40 @@ def icosphere(level):
     return np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tri, dtype=np.int32)
 
 
+def geodesic_sphere(nu):
+    """Unit sphere, class I geodesic of frequency nu: every face of the regular icosahedron split
+    into nu^2 triangles on its barycentric grid, vertices projected onto the sphere (20 nu^2
+    triangles, 10 nu^2 + 2 vertices).  nu = 4 gives the 320 triangles of icosphere(2)."""
+    ico, faces = icosphere(0)
+    pts, index = [], {}
+
+    def vertex(key, p):
+        if key not in index:
+            index[key] = len(pts)
+            pts.append(p / np.linalg.norm(p))
+        return index[key]
+
+    tri = []
+    for f in faces:
+        A, B, C = ico[f[0]], ico[f[1]], ico[f[2]]
+        ids = {}
+        for a in range(nu + 1):
+            for b in range(nu + 1 - a):
+                c = nu - a - b
+                # a grid point on a shared edge or corner gets the same key from both faces
+                w = {int(f[0]): a, int(f[1]): b, int(f[2]): c}
+                key = tuple(sorted((v, x) for v, x in w.items() if x > 0))
+                ids[(a, b)] = vertex(key, (a * A + b * B + c * C) / nu)
+        for a in range(nu):
+            for b in range(nu - a):
+                tri.append((ids[(a, b)], ids[(a + 1, b)], ids[(a, b + 1)]))
+                if a + b + 1 < nu:
+                    tri.append((ids[(a + 1, b)], ids[(a + 1, b + 1)], ids[(a, b + 1)]))
+    xyz = np.array(pts)
+    tri = _orient_outward(xyz, np.array(tri, dtype=np.int64), lambda c: np.zeros_like(c))
+    return np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tri, dtype=np.int32)
+
+
 def torus(nu, nv, R=1.0, r=0.35):
     """Structured torus: nu x nv quads on the (u, v) parameter grid, each quad
     (i,j),(i+1,j),(i+1,j+1),(i,j+1) split along the (i,j)-(i+1,j+1) diagonal."""
