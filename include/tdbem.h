@@ -87,6 +87,10 @@ typedef struct {
      * network during the first restart cycle, then Algorithm 1 (precond_levels > 0) from the
      * iterate reached, the paper's preconditioner serving as the fallback */
     int32_t precond_kind;
+    /* 1: with the learned network, run each outer iteration's preconditioned operator
+     * (z = P(v), w = A z) as one captured HIP graph, replayed on the context's stream; 0: launch
+     * the kernels one by one.  Requires precond_kind 1 or 2. */
+    int32_t use_graph;
 } tdbem_solve_opts;
 
 typedef struct {

@@ -66,7 +66,8 @@ PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_double, ctypes.c_void
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8),
-                ("progress", PROGRESS), ("progress_user", ctypes.c_void_p), ("precond_kind", ctypes.c_int32)]
+                ("progress", PROGRESS), ("progress_user", ctypes.c_void_p), ("precond_kind", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -272,12 +273,13 @@ class Context:
         return y, rep.as_dict()
 
     def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None, progress=None,
-              precond_kind=PRECOND_ALG1):
+              precond_kind=PRECOND_ALG1, use_graph=False):
         """FGMRES(restart) from 0 to ||g - A alpha|| <= tol ||g||, with Algorithm 1 when
         precond_inner lists inner iterations per level (e.g. (2, 10)); progress(iteration,
         estimate) is called after every outer iteration when given.  precond_kind selects the
         learned network (PRECOND_LEARNED) or the network for the first restart cycle and
-        Algorithm 1 afterwards (PRECOND_LEARNED_THEN_ALG1)."""
+        Algorithm 1 afterwards (PRECOND_LEARNED_THEN_ALG1); use_graph replays the learned
+        iteration's preconditioned operator as one captured HIP graph."""
         n = self.N * self.M
         alpha = self._vec() if out is None else out
         o = SolveOpts()
@@ -288,6 +290,7 @@ class Context:
         cb = PROGRESS(lambda it, est, user: progress(int(it), float(est))) if progress else PROGRESS()
         o.progress = cb
         o.precond_kind = int(precond_kind)
+        o.use_graph = 1 if use_graph else 0
         rep = SolveReport()
         st = self._check(self.lib.tdbem_solve(self.h, self._dev(g, n), self._dev(alpha, n), ctypes.byref(o),
                                               ctypes.byref(rep)))

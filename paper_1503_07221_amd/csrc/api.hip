@@ -197,7 +197,16 @@ struct tdbem_ctx {
         int64_t ninf = 0, ndots = 0;
         DBuf H, U, DU, dX, dH2, partial, vb, xb, zb, rb, db;
         int64_t ntrain = 0;
+        // z = P(v), w = A z captured as one HIP graph on a private stream, replayed on the
+        // context's stream; valid while key (operator, network, buffers) is unchanged
+        hipStream_t cap = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        std::vector<uint64_t> gkey;
+        DBuf gv, gz, gw;
+        int64_t gn = 0;
     } lp;
+    uint64_t assemblies = 0;      // completed assemblies (part of the graph key)
     uint64_t graph_version = 0;   // changes with the mesh and the time grid
     // multi-vector product: variant chosen by timing on the assembled operator (-1: not yet)
     int mm_variant = -1;
@@ -334,6 +343,9 @@ void tdbem_destroy(tdbem_ctx* c)
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     c->levels.clear();
+    if (c->lp.gexec) (void)hipGraphExecDestroy(c->lp.gexec);
+    if (c->lp.graph) (void)hipGraphDestroy(c->lp.graph);
+    if (c->lp.cap) (void)hipStreamDestroy(c->lp.cap);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -689,6 +701,7 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     unsigned long long counts[2];
     HIPCHK(c, hipMemcpy(counts, c->d_counter.p, sizeof(counts), hipMemcpyDeviceToHost));
     c->assembled = true;
+    ++c->assemblies;
     c->mm_variant = -1;
     if (rep) {
         float ms[4];
@@ -931,20 +944,40 @@ LpGraph lp_view(const tdbem_ctx* c)
     return LpGraph{c->lp.ptr.as<int32_t>(), c->lp.idx.as<int32_t>(), c->lp.feat.as<float>(), c->M, c->N};
 }
 
-// ||v||^2 of a device vector (synchronises the stream).
-tdbem_status lp_norm2(tdbem_ctx* c, const double* v, int64_t n, double* out)
+// Device scalars of the learned preconditioner: dots[0] = the last ||v||^2, dots[2] = s =
+// sqrt(||v||^2 / n), dots[3] = 1/s, from dots[4] on the partial sums of the reductions.
+tdbem_status lp_dots(tdbem_ctx* c, int64_t n, double** d)
 {
     tdbem_ctx::Learned& L = c->lp;
-    const int64_t need = dots_partial_blocks(n) + 1;
+    const int64_t need = dots_partial_blocks(n) + 4;
     if (L.ndots < need) {
         ALLOC(c, L.dots, sizeof(double) * need);
         L.ndots = need;
     }
-    double* d = L.dots.as<double>();
-    launch_dots(v, 1, n, n, v, d + 1, d, c->stream);
+    *d = L.dots.as<double>();
+    return TDBEM_OK;
+}
+
+// ||v||^2 of a device vector (synchronises the stream); leaves the scale scalars untouched.
+tdbem_status lp_norm2(tdbem_ctx* c, const double* v, int64_t n, double* out)
+{
+    double* d;
+    TRY(lp_dots(c, n, &d));
+    launch_dots(v, 1, n, n, v, d + 4, d, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(out, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+// The network's scale of v on the device (no host round trip): dots[2..3] from ||v||^2.
+tdbem_status lp_scale(tdbem_ctx* c, const double* v, int64_t n, hipStream_t st)
+{
+    double* d;
+    TRY(lp_dots(c, n, &d));
+    launch_dots(v, 1, n, n, v, d + 4, d, st);
+    launch_lp_scale(d, n, d + 2, st);
+    HIPCHK(c, hipGetLastError());
     return TDBEM_OK;
 }
 
@@ -954,28 +987,69 @@ tdbem_status lp_need_params(tdbem_ctx* c)
     return TDBEM_OK;
 }
 
-// z = network(v) for device vectors of N*M values.
-tdbem_status lp_apply(tdbem_ctx* c, const double* v, double* z)
+tdbem_status lp_need_inference(tdbem_ctx* c)
 {
-    TRY(lp_need_params(c));
-    TRY(lp_graph(c));
     tdbem_ctx::Learned& L = c->lp;
     const int64_t n = (int64_t)c->N * c->M;
     if (L.ninf < n) {
         ALLOC(c, L.Hinf, sizeof(float) * 2 * (size_t)n * kLpHidden);
         L.ninf = n;
     }
-    double vv;
-    TRY(lp_norm2(c, v, n, &vv));
-    if (!(vv > 0.0)) {
-        launch_fill(z, 0.0, n, c->stream);
-        HIPCHK(c, hipGetLastError());
-        return TDBEM_OK;
-    }
-    const double s = std::sqrt(vv / (double)n);
-    launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, 1.0 / s, s,
-                      L.Hinf.as<float>(), 0, nullptr, z, c->stream);
+    double* d;
+    TRY(lp_dots(c, n, &d));
+    return TDBEM_OK;
+}
+
+// z = network(v) for device vectors of N*M values, queued on stream st without a host round
+// trip (the scale s is formed on the device; v = 0 gives z = 0).
+tdbem_status lp_apply_on(tdbem_ctx* c, const double* v, double* z, hipStream_t st)
+{
+    TRY(lp_need_params(c));
+    TRY(lp_graph(c));
+    TRY(lp_need_inference(c));
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    TRY(lp_scale(c, v, n, st));
+    launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, L.dots.as<double>() + 2,
+                      L.Hinf.as<float>(), 0, nullptr, z, st);
     HIPCHK(c, hipGetLastError());
+    return TDBEM_OK;
+}
+
+tdbem_status lp_apply(tdbem_ctx* c, const double* v, double* z) { return lp_apply_on(c, v, z, c->stream); }
+
+// Capture (or reuse) the graph of the preconditioned operator z = P(v), w = A z on the staging
+// vectors lp.gv -> lp.gz, lp.gw.  Every allocation happens before the capture.
+tdbem_status lp_operator_graph(tdbem_ctx* c)
+{
+    TRY(lp_need_params(c));
+    TRY(lp_graph(c));
+    TRY(lp_need_inference(c));
+    tdbem_ctx::Learned& L = c->lp;
+    const int64_t n = (int64_t)c->N * c->M;
+    if (L.gn < n) {
+        ALLOC(c, L.gv, sizeof(double) * n);
+        ALLOC(c, L.gz, sizeof(double) * n);
+        ALLOC(c, L.gw, sizeof(double) * n);
+        L.gn = n;
+    }
+    const std::vector<uint64_t> key{c->graph_version, c->assemblies, (uint64_t)c->prec, (uint64_t)L.layers,
+                                    (uint64_t)(uintptr_t)L.params.p, (uint64_t)(uintptr_t)L.Hinf.p,
+                                    (uint64_t)(uintptr_t)L.dots.p, (uint64_t)(uintptr_t)L.gv.p, (uint64_t)n};
+    if (L.gexec && key == L.gkey) return TDBEM_OK;
+    if (L.gexec) { (void)hipGraphExecDestroy(L.gexec); L.gexec = nullptr; }
+    if (L.graph) { (void)hipGraphDestroy(L.graph); L.graph = nullptr; }
+    if (!L.cap) HIPCHK(c, hipStreamCreateWithFlags(&L.cap, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamBeginCapture(L.cap, hipStreamCaptureModeThreadLocal));
+    tdbem_status st = lp_apply_on(c, L.gv.as<double>(), L.gz.as<double>(), L.cap);
+    if (st == TDBEM_OK)
+        launch_matvec(c->band(), c->valf64(), c->valf32(), 0, c->N, 0, c->N, L.gz.as<double>(), L.gw.as<double>(), L.cap);
+    const hipError_t ee = hipStreamEndCapture(L.cap, &L.graph);
+    if (st != TDBEM_OK) return st;
+    if (ee != hipSuccess) FAIL(c, TDBEM_EHIP, "graph capture failed: %s", hipGetErrorString(ee));
+    HIPCHK(c, hipGraphInstantiate(&L.gexec, L.graph, nullptr, nullptr, 0));
+    L.gkey = key;
     return TDBEM_OK;
 }
 
@@ -1001,19 +1075,20 @@ tdbem_status lp_need_train_buffers(tdbem_ctx* c)
 }
 
 // Forward pass keeping every layer's input and pre-activation, then add the gradient of <dz, z>
-// to lp.grad.  s is the root mean square of v (> 0).
-tdbem_status lp_forward_backward(tdbem_ctx* c, const double* v, double s, double* z, const double* dz_or_null,
+// to lp.grad.  The scale of v must be in dots[2..3] (lp_scale).
+tdbem_status lp_forward_backward(tdbem_ctx* c, const double* v, double* z, const double* dz_or_null,
                                  bool backward_now)
 {
     tdbem_ctx::Learned& L = c->lp;
     const int64_t n = (int64_t)c->N * c->M;
     const int64_t hs = n * kLpHidden;
+    const double* sc = L.dots.as<double>() + 2;
     if (!backward_now) {
-        launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, 1.0 / s, s,
-                          L.H.as<float>(), hs, L.U.as<float>(), z, c->stream);
+        launch_lp_forward(lp_view(c), L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, sc, L.H.as<float>(),
+                          hs, L.U.as<float>(), z, c->stream);
     } else {
-        launch_lp_backward(lp_view(c), L.layers, L.wq.as<uint16_t>(), v, 1.0 / s, s, L.H.as<float>(),
-                           L.U.as<float>(), dz_or_null, L.dH2.as<float>(), L.DU.as<float>(), L.dX.as<float>(),
+        launch_lp_backward(lp_view(c), L.layers, L.wq.as<uint16_t>(), v, sc, L.H.as<float>(), L.U.as<float>(),
+                           dz_or_null, L.dH2.as<float>(), L.DU.as<float>(), L.dX.as<float>(),
                            L.partial.as<float>(), L.grad.as<float>(), c->stream);
     }
     HIPCHK(c, hipGetLastError());
@@ -1123,16 +1198,9 @@ tdbem_status tdbem_lp_gradient(tdbem_ctx* c, const double* v, const double* dz, 
     tdbem_ctx::Learned& L = c->lp;
     const int64_t n = (int64_t)c->N * c->M;
     HIPCHK(c, hipMemsetAsync(L.grad.p, 0, sizeof(float) * L.P, c->stream));
-    double vv;
-    TRY(lp_norm2(c, v, n, &vv));
-    if (vv > 0.0) {
-        const double s = std::sqrt(vv / (double)n);
-        TRY(lp_forward_backward(c, v, s, z, nullptr, false));
-        TRY(lp_forward_backward(c, v, s, z, dz, true));
-    } else {
-        launch_fill(z, 0.0, n, c->stream);
-        HIPCHK(c, hipGetLastError());
-    }
+    TRY(lp_scale(c, v, n, c->stream));                 // v = 0: z = 0 and a zero gradient
+    TRY(lp_forward_backward(c, v, z, nullptr, false));
+    TRY(lp_forward_backward(c, v, z, dz, true));
     HIPCHK(c, hipMemcpyAsync(grad, L.grad.p, sizeof(float) * L.P, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return TDBEM_OK;
@@ -1197,8 +1265,8 @@ tdbem_status tdbem_lp_train(tdbem_ctx* c, const tdbem_lp_train_opts* o, float* l
             double vv;
             TRY(lp_norm2(c, v, n, &vv));
             if (!(vv > 0.0)) continue;
-            const double s = std::sqrt(vv / (double)n);
-            TRY(lp_forward_backward(c, v, s, z, nullptr, false));
+            TRY(lp_scale(c, v, n, st));
+            TRY(lp_forward_backward(c, v, z, nullptr, false));
             TRY(matvec_range(c, 0, c->N, 0, c->N, z, r));
             launch_axpby(r, v, -1.0, 1.0, n, st);                   // r = A z - v
             HIPCHK(c, hipGetLastError());
@@ -1209,7 +1277,7 @@ tdbem_status tdbem_lp_train(tdbem_ctx* c, const tdbem_lp_train_opts* o, float* l
             launch_matvec_transpose(c->band(), c->valf64(), c->valf32(), r, dz, st);
             launch_scale_copy(dz, dz, 2.0 / vv, n, st);              // d loss / d z = 2 A^T r / |v|^2
             HIPCHK(c, hipGetLastError());
-            TRY(lp_forward_backward(c, v, s, z, dz, true));
+            TRY(lp_forward_backward(c, v, z, dz, true));
         }
         if (used == 0) continue;
         ++L.step;
@@ -1247,6 +1315,7 @@ struct SolveCtx {
     void* progress_user;
     int kind;               // 0: Algorithm 1 / none, 1: learned network, 2: learned, then Algorithm 1
     bool learned_active;    // the outer iteration currently uses the learned network
+    bool graph;             // the learned iteration replays the captured z = P(v), w = A z
 };
 
 tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
@@ -1319,11 +1388,21 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
         for (int j = 0; j < mm; ++j) {
             double* vj = V + (int64_t)j * n;
             double* zj = Z + (int64_t)j * n;
-            if (depth == 0 && S.learned_active) TRY(lp_apply(c, vj, zj));
-            else if (alg1) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
-            else if (precond) launch_scale_copy(zj, vj, 1.0, n, st);
             double* w = V + (int64_t)(j + 1) * n;
-            TRY(matvec_range(c, a, b, a, b, zj, w));
+            if (depth == 0 && S.learned_active && S.graph) {
+                // one graph launch for the preconditioned operator, through the staging vectors
+                tdbem_ctx::Learned& Lp = c->lp;
+                HIPCHK(c, hipMemcpyAsync(Lp.gv.p, vj, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+                HIPCHK(c, hipGraphLaunch(Lp.gexec, st));
+                HIPCHK(c, hipMemcpyAsync(zj, Lp.gz.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+                HIPCHK(c, hipMemcpyAsync(w, Lp.gw.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+                ++c->matvecs;
+            } else {
+                if (depth == 0 && S.learned_active) TRY(lp_apply(c, vj, zj));
+                else if (alg1) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
+                else if (precond) launch_scale_copy(zj, vj, 1.0, n, st);
+                TRY(matvec_range(c, a, b, a, b, zj, w));
+            }
             // classical Gram-Schmidt, twice
             launch_dots(V, j + 1, n, n, w, part, dbuf, st);
             launch_sub_combination(w, V, j + 1, n, n, dbuf, -1.0, st);
@@ -1404,10 +1483,14 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
     if (o->precond_kind == 2 && o->precond_levels < 1)
         FAIL(c, TDBEM_EINVAL, "the learned-then-Algorithm-1 preconditioner needs precond_levels > 0");
     TRY(set_device(c));
+    if (o->use_graph != 0 && o->use_graph != 1) FAIL(c, TDBEM_EINVAL, "use_graph must be 0 or 1");
+    if (o->use_graph && o->precond_kind == 0)
+        FAIL(c, TDBEM_EINVAL, "the captured iteration applies the learned preconditioner (precond_kind 1 or 2)");
     if (o->precond_kind != 0) {
         TRY(lp_need_params(c));
         TRY(lp_graph(c));
     }
+    if (o->use_graph) TRY(lp_operator_graph(c));
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t M = c->M;
     // workspaces: depth 0 is the outer solve; depth d >= 1 holds ranges of <= ceil(N / 2^(d-1)) blocks
@@ -1431,7 +1514,7 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
         blocks = (blocks + 1) / 2;
     }
     SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner, o->progress, o->progress_user,
-               o->precond_kind, o->precond_kind != 0};
+               o->precond_kind, o->precond_kind != 0, o->use_graph != 0};
     c->matvecs = 0;
     int its = 0;
     double rel = 0.0;
@@ -1582,6 +1665,7 @@ tdbem_status tdbem_solve_multi(tdbem_ctx* c, int32_t nrhs, const double* G, doub
         FAIL(c, TDBEM_EINVAL, "bad solver options");
     if (o->precond_levels != 0 || (o->precond_kind != 0 && o->precond_kind != 1))
         FAIL(c, TDBEM_EINVAL, "the batched solve takes no preconditioner or the learned one (precond_kind 1)");
+    if (o->use_graph) FAIL(c, TDBEM_EINVAL, "the batched solve launches its kernels directly (use_graph 0)");
     TRY(set_device(c));
     const bool learned = o->precond_kind == 1;
     if (learned) {

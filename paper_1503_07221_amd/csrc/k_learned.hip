@@ -89,7 +89,8 @@ __device__ inline void load_weights_t(float (*wt)[kPad], const uint16_t* __restr
 
 // H0[n][c] = bin[c] + Win[c] . [v_n / s, f1_k, f2_k]
 __global__ void __launch_bounds__(256)
-k_lp_input(int64_t n, LpGraph g, const double* __restrict__ v, double inv_s, const uint16_t* __restrict__ Win,
+k_lp_input(int64_t n, LpGraph g, const double* __restrict__ v, const double* __restrict__ sc,
+           const uint16_t* __restrict__ Win,
            const float* __restrict__ bin, float* __restrict__ H0)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,7 +98,7 @@ k_lp_input(int64_t n, LpGraph g, const double* __restrict__ v, double inv_s, con
     const int64_t node = s / kH;
     const int c = (int)(s - node * kH);
     const int k = (int)(node / g.M);
-    const float x0 = (float)(v[node] * inv_s);
+    const float x0 = (float)(v[node] * sc[1]);
     const float f1 = g.feat[2 * k], f2 = g.feat[2 * k + 1];
     float a = bin[c];
     a = fmaf(bf16_to_float(Win[3 * c + 0]), x0, a);
@@ -165,7 +166,7 @@ k_lp_layer(int64_t n, LpGraph g, const float* __restrict__ Hin, const uint16_t* 
 
 // z_n = s * sum_c wout[c] H[n][c]
 __global__ void __launch_bounds__(256)
-k_lp_output(int64_t n, const float* __restrict__ H, const uint16_t* __restrict__ wout, double s,
+k_lp_output(int64_t n, const float* __restrict__ H, const uint16_t* __restrict__ wout, const double* __restrict__ sc,
             double* __restrict__ z)
 {
     const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -180,12 +181,12 @@ k_lp_output(int64_t n, const float* __restrict__ H, const uint16_t* __restrict__
         a = fmaf(h.z, bf16_to_float(wout[4 * q + 2]), a);
         a = fmaf(h.w, bf16_to_float(wout[4 * q + 3]), a);
     }
-    z[node] = s * (double)a;
+    z[node] = sc[0] * (double)a;
 }
 
 // Backward of the output: dH[n][c] = s dz_n wout[c]; partial[blk][c] = sum_n s dz_n H[n][c].
 __global__ void __launch_bounds__(256)
-k_lp_output_bwd(int64_t n, const float* __restrict__ H, const uint16_t* __restrict__ wout, double s,
+k_lp_output_bwd(int64_t n, const float* __restrict__ H, const uint16_t* __restrict__ wout, const double* __restrict__ sc,
                 const double* __restrict__ dz, float* __restrict__ dH, float* __restrict__ partial)
 {
     __shared__ float red[4][kH];
@@ -195,7 +196,7 @@ k_lp_output_bwd(int64_t n, const float* __restrict__ H, const uint16_t* __restri
     const float w = bf16_to_float(wout[c]);
     float acc = 0.f;
     for (int64_t node = b + q; node < e; node += 4) {
-        const float gz = (float)(s * dz[node]);
+        const float gz = (float)(sc[0] * dz[node]);
         dH[node * kH + c] = gz * w;
         acc = fmaf(gz, H[node * kH + c], acc);
     }
@@ -351,7 +352,8 @@ k_lp_layer_bwd_dw(int64_t n, LpGraph g, const float* __restrict__ Hin, const flo
 // Backward of the input layer: partial[blk][c*3 + f] = sum_n dH0[n][c] x_f(n), partial[blk][192 + c]
 // = sum_n dH0[n][c].
 __global__ void __launch_bounds__(256)
-k_lp_input_bwd(int64_t n, LpGraph g, const double* __restrict__ v, double inv_s, const float* __restrict__ dH0,
+k_lp_input_bwd(int64_t n, LpGraph g, const double* __restrict__ v, const double* __restrict__ sc,
+               const float* __restrict__ dH0,
                float* __restrict__ partial)
 {
     __shared__ float red[4][kH][4];
@@ -362,7 +364,7 @@ k_lp_input_bwd(int64_t n, LpGraph g, const double* __restrict__ v, double inv_s,
     for (int64_t node = b + q; node < e; node += 4) {
         const int k = (int)(node / g.M);
         const float d = dH0[node * kH + c];
-        a0 = fmaf(d, (float)(v[node] * inv_s), a0);
+        a0 = fmaf(d, (float)(v[node] * sc[1]), a0);
         a1 = fmaf(d, g.feat[2 * k], a1);
         a2 = fmaf(d, g.feat[2 * k + 1], a2);
         a3 += d;
@@ -551,12 +553,26 @@ void launch_lp_round(int64_t P, const float* p, uint16_t* q, hipStream_t s)
     hipLaunchKernelGGL(k_lp_round, dim3(blocks_for(P, 256)), dim3(256), 0, s, P, p, q);
 }
 
+// sc[0] = s = sqrt(vv / n), sc[1] = 1/s (0 for s = 0: then the network's output is exactly 0)
+__global__ void k_lp_scale(const double* __restrict__ vv, int64_t n, double* __restrict__ sc)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double s = sqrt(fmax(vv[0], 0.0) / (double)n);
+        sc[0] = s;
+        sc[1] = s > 0.0 ? 1.0 / s : 0.0;
+    }
+}
+
+void launch_lp_scale(const double* vv, int64_t n, double* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lp_scale, dim3(1), dim3(64), 0, st, vv, n, sc);
+}
+
 void launch_lp_forward(LpGraph g, int layers, const float* params, const uint16_t* wq, const double* v,
-                       double inv_s, double s_scale, float* H, int64_t hstride, float* U, double* z,
-                       hipStream_t st)
+                       const double* sc, float* H, int64_t hstride, float* U, double* z, hipStream_t st)
 {
     const int64_t n = (int64_t)g.N * g.M;
-    hipLaunchKernelGGL(k_lp_input, dim3(blocks_for(n * kH, 256)), dim3(256), 0, st, n, g, v, inv_s,
+    hipLaunchKernelGGL(k_lp_input, dim3(blocks_for(n * kH, 256)), dim3(256), 0, st, n, g, v, sc,
                        wq + lp_off_win(), params + lp_off_bin(), H);
     for (int l = 0; l < layers; ++l) {
         const float* hin = H + (hstride ? l * hstride : (l & 1) * n * kH);
@@ -566,12 +582,12 @@ void launch_lp_forward(LpGraph g, int layers, const float* params, const uint16_
     }
     const float* hl = H + (hstride ? layers * hstride : (layers & 1) * n * kH);
     hipLaunchKernelGGL(k_lp_output, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, hl, wq + lp_off_wout(layers),
-                       s_scale, z);
+                       sc, z);
 }
 
 int lp_partial_blocks(int64_t n) { return (int)blocks_for(n, kChunk); }
 
-void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double* v, double inv_s, double s_scale,
+void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double* v, const double* sc,
                         const float* H, const float* U, const double* dz, float* dH2, float* DU, float* dX,
                         float* partial, float* grad, hipStream_t st)
 {
@@ -580,7 +596,7 @@ void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double*
     float* dh = dH2;
     float* dh_next = dH2 + n * kH;
     hipLaunchKernelGGL(k_lp_output_bwd, dim3(nb), dim3(256), 0, st, n, H + layers * n * kH,
-                       wq + lp_off_wout(layers), s_scale, dz, dh, partial);
+                       wq + lp_off_wout(layers), sc, dz, dh, partial);
     hipLaunchKernelGGL(k_lp_reduce, dim3(1), dim3(256), 0, st, partial, nb, kH, grad + lp_off_wout(layers));
     for (int l = layers - 1; l >= 0; --l) {
         const float* hin = H + l * n * kH;
@@ -596,7 +612,7 @@ void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double*
         dh = dh_next;
         dh_next = tmp;
     }
-    hipLaunchKernelGGL(k_lp_input_bwd, dim3(nb), dim3(256), 0, st, n, g, v, inv_s, dh, partial);
+    hipLaunchKernelGGL(k_lp_input_bwd, dim3(nb), dim3(256), 0, st, n, g, v, sc, dh, partial);
     hipLaunchKernelGGL(k_lp_reduce, dim3(1), dim3(256), 0, st, partial, nb, 4 * kH, grad + lp_off_win());
 }
 

@@ -342,12 +342,13 @@ void launch_lp_round(int64_t P, const float* p, uint16_t* q, hipStream_t s);
 // hstride = 0: inference, H holds two ping-pong slots of N*M*64 floats and U is unused;
 // hstride = N*M*64: training, H holds layers+1 slots and U (may not be null) holds layers slots.
 void launch_lp_forward(LpGraph g, int layers, const float* params, const uint16_t* wq, const double* v,
-                       double inv_s, double s_scale, float* H, int64_t hstride, float* U, double* z,
-                       hipStream_t st);
+                       const double* sc, float* H, int64_t hstride, float* U, double* z, hipStream_t st);
+// sc[0] = sqrt(vv[0] / n), sc[1] = 1 / sc[0] (0 when vv = 0): the network's scale on the device.
+void launch_lp_scale(const double* vv, int64_t n, double* sc, hipStream_t st);
 int lp_partial_blocks(int64_t n);
 // Adds the gradient of <dz, z> to grad (layout of the parameter vector).  dH2: 2 N*M*64 floats,
 // DU: N*M*64, dX: 4 N*M*64, partial: lp_partial_blocks(N*M) * (64*256 + 64) floats.
-void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double* v, double inv_s, double s_scale,
+void launch_lp_backward(LpGraph g, int layers, const uint16_t* wq, const double* v, const double* sc,
                         const float* H, const float* U, const double* dz, float* dH2, float* DU, float* dX,
                         float* partial, float* grad, hipStream_t st);
 void launch_lp_adam(int64_t P, float* p, const float* grad, float* m, float* v2, float lr, int64_t step,

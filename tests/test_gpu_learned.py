@@ -144,6 +144,19 @@ def test_training_cuts_iterations(ctx, tb):
     assert torch.linalg.norm(r).item() <= 1e-8 * torch.linalg.norm(g).item()
     assert learned["converged"] and plain["converged"]
     assert learned["iterations"] < 0.5 * plain["iterations"], (learned["iterations"], plain["iterations"])
+    # the same solve with the iteration's z = P(v), w = A z replayed from a captured HIP graph: every
+    # replay must act like the eager launches, so the Givens estimates follow the same sequence
+    est_e, est_g = [], []
+    a_e, d_e = ctx.solve(g, tol=1e-8, restart=500, max_it=500, precond_kind=tb.PRECOND_LEARNED,
+                         progress=lambda it, e: est_e.append(e))
+    a_g, d_g = ctx.solve(g, tol=1e-8, restart=500, max_it=500, precond_kind=tb.PRECOND_LEARNED,
+                         use_graph=True, progress=lambda it, e: est_g.append(e))
+    assert d_g["converged"] and abs(d_g["iterations"] - d_e["iterations"]) <= 1
+    k = min(len(est_e), len(est_g))
+    assert np.allclose(est_g[:k], est_e[:k], rtol=1e-6, atol=0.0)
+    assert torch.linalg.norm(a_g - a_e).item() <= 1e-8 * torch.linalg.norm(a_e).item()
+    r = g - ctx.matvec(a_g)
+    assert torch.linalg.norm(r).item() <= 1e-8 * torch.linalg.norm(g).item()
     # the network for one cycle of 20 iterations, then Algorithm 1 (2, 10) from there
     alpha2, mixed = ctx.solve(g, tol=1e-8, restart=20, max_it=400, precond_inner=(2, 10),
                               precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
@@ -164,6 +177,9 @@ def test_learned_error_paths(tb):
     with pytest.raises(tb.TdbemError) as e:
         c.solve(v, precond_kind=tb.PRECOND_LEARNED)
     assert e.value.status == -6
+    with pytest.raises(tb.TdbemError) as e:
+        c.solve(v, use_graph=True)                       # the graph needs the learned network
+    assert e.value.status == -1
     c.lp_init(2, seed=0)
     with pytest.raises(tb.TdbemError) as e:
         c.lp_set_params(np.zeros(10, dtype=np.float32))
