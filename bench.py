@@ -233,6 +233,14 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
                     "solution_rel_diff_vs_alg1_fp64": float(torch.linalg.norm(a - alpha_ref) / nrm)}
         if solve_ref:
             res[tag]["speedup_vs_alg1_fp64_solve"] = solve_ref["ms"] / srep["ms"]
+    ctx.assemble(tb.FP64)
+    a, srep = ctx.solve(g, tol=args.tol, restart=args.lp_restart, max_it=args.lp_max_it,
+                        precond_kind=tb.PRECOND_LEARNED, use_graph=True)
+    print(f"# learned fp64, captured iteration: solve {srep['ms']:.1f} ms ({srep['iterations']} it)",
+          file=sys.stderr, flush=True)
+    res["fp64_graph"] = {"solve_ms": srep["ms"], "iterations": int(srep["iterations"]),
+                         "rel_residual": float(srep["rel_residual"]), "converged": bool(srep["converged"]),
+                         "solution_rel_diff_vs_alg1_fp64": float(torch.linalg.norm(a - alpha_ref) / nrm)}
     if args.batch_rhs > 0:
         res["batched"] = batched_leg(ctx, tb, args, res["fp64"]["solve_ms"])
     ctx.assemble(tb.FP64)
