@@ -20,14 +20,14 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "tdbem_oracle.c")
 
 CUTOFF = {"bump": 0, "erf": 1}
-MODE = {"psi": 0, "r": 1, "r3": 2, "one": 3, "curl": 4, "nn": 5}
+MODE = {"psi": 0, "r": 1, "r3": 2, "one": 3, "curl": 4, "nn": 5, "r_r3": 6}
 
 
 def build(force=False):
-    """Compile liboracle.so with gcc (-O2, OpenMP)."""
+    """Compile liboracle.so with gcc (-O3, OpenMP)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -46,28 +46,36 @@ def lib():
         L.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         L.orc_cutoff.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_mu.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
-        L.orc_basis.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
-        L.orc_support.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
-        L.orc_psi.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_basis.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_support.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.orc_psi.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_double, dp]
         L.orc_rule7.argtypes = [dp, dp]
         L.orc_ss_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp]
         L.orc_ss_rule.restype = ctypes.c_int
         L.orc_pair_local.argtypes = [dp, ip, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_int, dp]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        vp = ctypes.c_void_p
         L.orc_assemble_dense.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
-                                         ctypes.c_int, ctypes.c_int, dp]
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, dp]
         L.orc_assemble_dense.restype = ctypes.c_int
         L.orc_assemble_entries.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, dp]
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ip, ip, dp]
+        L.orc_tables_build.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.orc_tables_build.restype = vp
+        L.orc_tables_free.argtypes = [vp]
+        L.orc_psi_fast.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp]
         L.orc_rhs_plane_pulse.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
-                                          dp, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_count_quad_evals.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int]
+                                          ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_count_quad_evals.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int]
         L.orc_count_quad_evals.restype = ctypes.c_int64
-        L.orc_local_batch.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_local_batch.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, vp, dp]
         L.orc_local_batch.restype = ctypes.c_int64
         L.orc_num_threads.restype = ctypes.c_int
-        L.orc_potential_dl.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp,
-                                       ctypes.c_int, dp, ctypes.c_int, dp, dp]
+        L.orc_potential_dl.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int, dp, dp]
         L.orc_potential_dl.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -107,28 +115,61 @@ def mu(grid, j, t, kind="bump"):
     return out
 
 
-def basis(grid, j, t, kind="bump"):
-    """(b_j(t), b_j'(t), b_j''(t))."""
+def basis(grid, j, t, kind="bump", p=0):
+    """(b_j(t), b_j'(t), b_j''(t)) for basis j = n (p + 1) + m (node n, Legendre degree m)."""
     g, gp = _d(grid)
     out = np.zeros(3)
-    lib().orc_basis(gp, len(g), CUTOFF[kind], j, float(t), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    lib().orc_basis(gp, len(g), CUTOFF[kind], p, j, float(t), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
 
 
-def support(grid, k, i):
+def support(grid, k, i, p=0):
     """Open support (lo, hi) of psi_{k,i} in r >= 0 (Section 3.2)."""
     g, gp = _d(grid)
     lo = ctypes.c_double(); hi = ctypes.c_double()
-    lib().orc_support(gp, len(g), k, i, ctypes.byref(lo), ctypes.byref(hi))
+    lib().orc_support(gp, len(g), p, k, i, ctypes.byref(lo), ctypes.byref(hi))
     return lo.value, hi.value
 
 
-def psi(grid, k, i, r, kind="bump"):
+def psi(grid, k, i, r, kind="bump", p=0):
     """(psi_{k,i}(r), tilde psi_{k,i}(r)) by direct quadrature of eq. (psis)."""
     g, gp = _d(grid)
     out = np.zeros(2)
-    lib().orc_psi(gp, len(g), CUTOFF[kind], k, i, float(r), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    lib().orc_psi(gp, len(g), CUTOFF[kind], p, k, i, float(r), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
+
+
+class Tables:
+    """Fast mode: the oracle's own tabulation of psi_{k,i}, tpsi_{k,i} (uniform grid of n + 1
+    points over each support cut at rmax, degree-11 local interpolation), built by direct
+    quadrature of eq. (psis) at every grid point."""
+
+    def __init__(self, grid, kind="bump", rmax=2.0, n=2048, p=0):
+        g, gp = _d(grid)
+        self.N, self.p = len(g), p
+        self.h = lib().orc_tables_build(gp, len(g), CUTOFF[kind], int(p), float(rmax), int(n))
+        if not self.h:
+            raise MemoryError("oracle tables")
+
+    def psi(self, k, i, r):
+        out = np.zeros(2)
+        lib().orc_psi_fast(self.h, k, i, float(r), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_tables_free(self.h)
+            self.h = None
+
+
+def mesh_diameter(xyz):
+    """An upper bound of every distance on the mesh (diagonal of the bounding box)."""
+    xyz = np.asarray(xyz)
+    return float(np.linalg.norm(xyz.max(axis=0) - xyz.min(axis=0))) * (1 + 1e-9) + 1e-12
+
+
+def fast_tables(xyz, grid, kind="bump", n=2048, p=0):
+    return Tables(grid, kind, mesh_diameter(xyz), n, p)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -152,72 +193,79 @@ def ss_rule(kind, order):
 # ---------------------------------------------------------------------------------------------
 # assembly (eq. (MatrixEntries))
 # ---------------------------------------------------------------------------------------------
-def pair_local(xyz, tri, ex, ey, grid, kind="bump", mode="psi", ss_order=4):
+def pair_local(xyz, tri, ex, ey, grid, kind="bump", mode="psi", ss_order=4, p=0):
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
-    N = len(g)
-    nb = N if MODE[mode] in (0, 4, 5) else 1
+    L = len(g) * (p + 1)
+    nb = L if MODE[mode] in (0, 4, 5) else 1
     loc = np.zeros(nb * nb * 9)
-    lib().orc_pair_local(xp, tp, ex, ey, gp, N, CUTOFF[kind], MODE[mode], ss_order,
+    lib().orc_pair_local(xp, tp, ex, ey, gp, len(g), CUTOFF[kind], p, MODE[mode], ss_order,
                          loc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return loc.reshape(nb, nb, 3, 3)
 
 
-def assemble_dense(xyz, tri, grid, kind="bump", mode="psi", ss_order=4):
-    """All blocks: returns A[k, i, j, l] = A_{k,i}(j, l)."""
+def assemble_dense(xyz, tri, grid, kind="bump", mode="psi", ss_order=4, tables=None, p=0):
+    """All blocks: returns A[k, i, j, l] = A_{k,i}(j, l) for the L = N (p + 1) bases.  tables: a
+    Tables of the same grid, cutoff and p (fast mode), or None (direct quadrature of every
+    kernel value)."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
     M, E, N = len(x), len(t), len(g)
-    nb = N if MODE[mode] in (0, 4, 5) else 1
+    L = N * (p + 1)
+    nb = L if MODE[mode] in (0, 4, 5) else 1
     out = np.zeros(nb * nb * M * M)
-    rc = lib().orc_assemble_dense(xp, M, tp, E, gp, N, CUTOFF[kind], MODE[mode], ss_order,
+    rc = lib().orc_assemble_dense(xp, M, tp, E, gp, N, CUTOFF[kind], p, MODE[mode], ss_order,
+                                  tables.h if tables is not None else None,
                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc != 0:
         raise MemoryError("oracle dense assembly failed")
     return out.reshape(nb, nb, M, M)
 
 
-def assemble_entries(xyz, tri, grid, sel_j, sel_l, kind="bump", mode="psi", ss_order=4):
+def assemble_entries(xyz, tri, grid, sel_j, sel_l, kind="bump", mode="psi", ss_order=4, tables=None, p=0):
     """Selected entries: returns out[s, k, i] = A_{k,i}(sel_j[s], sel_l[s])."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
     sj, sjp = _i(sel_j); sl, slp = _i(sel_l)
     M, E, N = len(x), len(t), len(g)
-    nb = N if MODE[mode] in (0, 4, 5) else 1
+    L = N * (p + 1)
+    nb = L if MODE[mode] in (0, 4, 5) else 1
     out = np.zeros(len(sj) * nb * nb)
-    lib().orc_assemble_entries(xp, M, tp, E, gp, N, CUTOFF[kind], MODE[mode], ss_order, len(sj), sjp, slp,
+    lib().orc_assemble_entries(xp, M, tp, E, gp, N, CUTOFF[kind], p, MODE[mode], ss_order,
+                               tables.h if tables is not None else None, len(sj), sjp, slp,
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out.reshape(len(sj), nb, nb)
 
 
-def rhs_plane_pulse(xyz, tri, grid, direction, t0, width, kind="bump"):
+def rhs_plane_pulse(xyz, tri, grid, direction, t0, width, kind="bump", p=0):
     """g[k*M + l] for g = -d_n u_inc, u_inc = exp(-((t - t0 - d.x)/w)^2)."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid); d, dp = _d(direction)
     M, E, N = len(x), len(t), len(g)
-    out = np.zeros(N * M)
-    lib().orc_rhs_plane_pulse(xp, M, tp, E, gp, N, CUTOFF[kind], dp, float(t0), float(width),
+    out = np.zeros(N * (p + 1) * M)
+    lib().orc_rhs_plane_pulse(xp, M, tp, E, gp, N, CUTOFF[kind], p, dp, float(t0), float(width),
                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
 
 
-def count_quad_evals(xyz, tri, grid, ss_order=4):
+def count_quad_evals(xyz, tri, grid, ss_order=4, p=0):
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
-    return int(lib().orc_count_quad_evals(xp, len(x), tp, len(t), gp, len(g), ss_order))
+    return int(lib().orc_count_quad_evals(xp, len(x), tp, len(t), gp, len(g), p, ss_order))
 
 
-def local_batch(xyz, tri, taus, sigmas, grid, kind="bump", ss_order=4):
+def local_batch(xyz, tri, taus, sigmas, grid, kind="bump", ss_order=4, tables=None, p=0):
     """Local integrals of the ordered pairs (taus[s], sigmas[s]); returns (quad-evals, checksum)."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
     a, ap = _i(taus); b, bp = _i(sigmas)
     chk = ctypes.c_double()
-    n = lib().orc_local_batch(xp, tp, len(a), ap, bp, gp, len(g), CUTOFF[kind], ss_order, ctypes.byref(chk))
+    n = lib().orc_local_batch(xp, tp, len(a), ap, bp, gp, len(g), CUTOFF[kind], p, ss_order,
+                              tables.h if tables is not None else None, ctypes.byref(chk))
     return int(n), chk.value
 
 
-def potential_dl(xyz, tri, grid, alpha, pts, times, kind="bump"):
+def potential_dl(xyz, tri, grid, alpha, pts, times, kind="bump", p=0):
     """Retarded double layer potential u(x_p, t_s) of eq. (RetardedPotential) of the density
     sum alpha[i*M + j] b_i(t) phi_j(y); returns an array [len(times), len(pts)]."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
     a, ap = _d(np.ravel(alpha)); P, Pp = _d(np.reshape(pts, (-1, 3))); T, Tp = _d(np.ravel(times))
     out = np.zeros(len(T) * len(P))
-    lib().orc_potential_dl(xp, len(x), tp, len(t), gp, len(g), CUTOFF[kind], ap, len(P), Pp, len(T), Tp,
+    lib().orc_potential_dl(xp, len(x), tp, len(t), gp, len(g), CUTOFF[kind], p, ap, len(P), Pp, len(T), Tp,
                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out.reshape(len(T), len(P))
 

@@ -104,13 +104,17 @@ static void cutoff(int kind, double u, double F[3])
 void orc_cutoff(int kind, double u, double *out) { cutoff(kind, u, out); }
 
 /* ------------------------------------------------------------------------------------------
- * Partition of unity mu_j and temporal basis b_j with first and second derivatives
- * (Section 3, construction of f_i, rho_i, mu_i and eq. (BasisFunctions) with p = 0).
+ * Partition of unity mu_n and temporal basis b_{n,m} with first and second derivatives
+ * (Section 3, construction of f_i, rho_i, mu_i and eq. (BasisFunctions)).
  *   mu_0 = 1 - F((t - t_0)/h_1) on [t_0, t_1];
- *   mu_j = F((t - t_{j-1})/h_j) on [t_{j-1}, t_j], 1 - F((t - t_j)/h_{j+1}) on [t_j, t_{j+1}];
+ *   mu_n = F((t - t_{n-1})/h_n) on [t_{n-1}, t_n], 1 - F((t - t_n)/h_{n+1}) on [t_n, t_{n+1}];
  *   mu_{N-1} = F((t - t_{N-2})/h_{N-1}) on [t_{N-2}, t_{N-1}] and 1 beyond;
- *   every mu_j is 0 for t < 0 (causal extension).  h_j = t_j - t_{j-1}.
- *   b_0 = 8 (t/h_1)^2 mu_0 (the causal factor of the first basis), b_j = mu_j for j >= 1.
+ *   every mu_n is 0 for t < 0 (causal extension).  h_n = t_n - t_{n-1}.
+ *   b_{n,m} = mu_n P_m(s) with the Legendre polynomial P_m of the support mapped onto [-1, 1]:
+ *   s = 2t/h_1 - 1 and the causal factor 8 (t/h_1)^2 for n = 0, s = (t - t_n)/Delta t for the
+ *   inner nodes (on a graded grid the affine map of [t_{n-1}, t_{n+1}] onto [-1, 1]), and
+ *   s = 2 (t - t_{N-2})/h_{N-1} - 1 for n = N - 1.  m = 0..p; the basis index is j = n (p+1) + m,
+ *   L = N (p+1) in all (the numbering of Section 3 read with L = N (p+1)).
  * ---------------------------------------------------------------------------------------- */
 void orc_mu(const double *t, int N, int cut, int j, double x, double out[3])
 {
@@ -132,17 +136,44 @@ void orc_mu(const double *t, int N, int cut, int j, double x, double out[3])
     if (j == N - 1 && x > t[N - 1]) out[0] = 1.0;
 }
 
-void orc_basis(const double *t, int N, int cut, int j, double x, double out[3])
+/* Legendre polynomial P_m(s) with P_m' and P_m'' (three-term recurrence; the derivatives by
+ * P_m' = P_{m-2}' + (2m - 1) P_{m-1} and the same relation once more). */
+static void legendre(int m, double s, double P[3])
 {
-    double m[3];
-    orc_mu(t, N, cut, j, x, m);
-    if (j != 0) { out[0] = m[0]; out[1] = m[1]; out[2] = m[2]; return; }
-    if (x <= 0.0) { out[0] = out[1] = out[2] = 0.0; return; }
-    double h = t[1] - t[0], u = x / h;
-    double q = 8.0 * u * u, qd = 16.0 * u / h, qdd = 16.0 / (h * h);
-    out[0] = q * m[0];
-    out[1] = qd * m[0] + q * m[1];
-    out[2] = qdd * m[0] + 2.0 * qd * m[1] + q * m[2];
+    double p0[3] = {1.0, 0.0, 0.0}, p1[3] = {s, 1.0, 0.0};
+    if (m == 0) { P[0] = 1.0; P[1] = P[2] = 0.0; return; }
+    for (int q = 2; q <= m; ++q) {
+        double v = ((2.0 * q - 1.0) * s * p1[0] - (q - 1.0) * p0[0]) / q;
+        double d = p0[1] + (2.0 * q - 1.0) * p1[0];
+        double dd = p0[2] + (2.0 * q - 1.0) * p1[1];
+        p0[0] = p1[0]; p0[1] = p1[1]; p0[2] = p1[2];
+        p1[0] = v; p1[1] = d; p1[2] = dd;
+    }
+    P[0] = p1[0]; P[1] = p1[1]; P[2] = p1[2];
+}
+
+void orc_basis(const double *t, int N, int cut, int p, int j, double x, double out[3])
+{
+    int n = j / (p + 1), m = j % (p + 1);
+    double mu[3], b[3];
+    orc_mu(t, N, cut, n, x, mu);
+    if (n == 0) {
+        if (x <= 0.0) { out[0] = out[1] = out[2] = 0.0; return; }
+        double h = t[1] - t[0], u = x / h;
+        double q = 8.0 * u * u, qd = 16.0 * u / h, qdd = 16.0 / (h * h);
+        b[0] = q * mu[0];
+        b[1] = qd * mu[0] + q * mu[1];
+        b[2] = qdd * mu[0] + 2.0 * qd * mu[1] + q * mu[2];
+    } else {
+        b[0] = mu[0]; b[1] = mu[1]; b[2] = mu[2];
+    }
+    if (m == 0) { out[0] = b[0]; out[1] = b[1]; out[2] = b[2]; return; }
+    double lo = n == 0 ? 0.0 : t[n - 1], hi = n == N - 1 ? t[N - 1] : (n == 0 ? t[1] : t[n + 1]);
+    double a = 2.0 / (hi - lo), s = a * (x - lo) - 1.0, P[3];
+    legendre(m, s, P);
+    out[0] = b[0] * P[0];
+    out[1] = b[1] * P[0] + b[0] * P[1] * a;
+    out[2] = b[2] * P[0] + 2.0 * b[1] * P[1] * a + b[0] * P[2] * a * a;
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -181,16 +212,16 @@ static int cmp_dbl(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-/* [lo_k, hi_k] = support of b_k' inside [0, T] */
+/* [lo_k, hi_k] = support of b_k' inside [0, T], k the node */
 static void dsupp(const double *t, int N, int k, double *lo, double *hi)
 {
     *lo = t[k > 0 ? k - 1 : 0];
     *hi = t[k < N - 1 ? k + 1 : N - 1];
 }
 
-/* Open support of psi_{k,i} and tpsi_{k,i} in r >= 0 (Section 3.2):
- *   (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) with t_{-1} := 0 and t_N := T. */
-void orc_support(const double *t, int N, int k, int i, double *lo, double *hi)
+/* Open support of psi_{k,i} and tpsi_{k,i} in r >= 0 (Section 3.2), k, i the nodes of the two
+ * bases: (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) with t_{-1} := 0 and t_N := T. */
+static void node_support(const double *t, int N, int k, int i, double *lo, double *hi)
 {
     double tkm = t[k > 0 ? k - 1 : 0], tkp = t[k < N - 1 ? k + 1 : N - 1];
     double tim = t[i > 0 ? i - 1 : 0], tip = t[i < N - 1 ? i + 1 : N - 1];
@@ -199,13 +230,18 @@ void orc_support(const double *t, int N, int k, int i, double *lo, double *hi)
     *hi = tkp - tim;
 }
 
-void orc_psi(const double *t, int N, int cut, int k, int i, double r, double out[2])
+void orc_support(const double *t, int N, int p, int k, int i, double *lo, double *hi)
+{
+    node_support(t, N, k / (p + 1), i / (p + 1), lo, hi);
+}
+
+/* The two integrals of eq. (psis) at r, without the support test (at an end of the open
+ * support this is the kernel's one-sided limit). */
+static void psi_integral(const double *t, int N, int cut, int p, int kb, int ib, double r, double out[2])
 {
     tq_init();
     out[0] = out[1] = 0.0;
-    double slo, shi;
-    orc_support(t, N, k, i, &slo, &shi);
-    if (!(r > slo && r < shi)) return;
+    int k = kb / (p + 1), i = ib / (p + 1);     /* nodes of the two bases */
     double lo, hi;
     dsupp(t, N, k, &lo, &hi);
     double ilo = r + t[i > 0 ? i - 1 : 0];
@@ -236,8 +272,8 @@ void orc_psi(const double *t, int N, int cut, int k, int i, double r, double out
             for (int q = 0; q < ORC_TQ; ++q) {
                 double tt = mid + hw * g_tx[q], ww = hw * g_tw[q];
                 double bi[3], bk[3];
-                orc_basis(t, N, cut, i, tt - r, bi);
-                orc_basis(t, N, cut, k, tt, bk);
+                orc_basis(t, N, cut, p, ib, tt - r, bi);
+                orc_basis(t, N, cut, p, kb, tt, bk);
                 ps += ww * bi[2] * bk[1];
                 pt += ww * bi[0] * bk[1];
             }
@@ -246,6 +282,114 @@ void orc_psi(const double *t, int N, int cut, int k, int i, double r, double out
     out[0] = ps;
     out[1] = pt;
 }
+
+void orc_psi(const double *t, int N, int cut, int p, int k, int i, double r, double out[2])
+{
+    out[0] = out[1] = 0.0;
+    double slo, shi;
+    orc_support(t, N, p, k, i, &slo, &shi);
+    if (!(r > slo && r < shi)) return;
+    psi_integral(t, N, cut, p, k, i, r, out);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Fast mode: the oracle's own tabulation of psi_{k,i}, tpsi_{k,i} (a different scheme from the
+ * library's piecewise Chebyshev series).  Each kernel's support (lo, hi), cut at rmax (the
+ * longest distance on the mesh), carries a uniform grid r_m = lo + m h, m = -ORC_PAD .. n +
+ * ORC_PAD, holding the integrals of eq. (psis) without the support test (beyond an end of the
+ * support they are the integrals' smooth continuation: zero past a true end, the kernel at
+ * negative r below a support cut at r = 0); a value at r inside the open support is the
+ * degree-11 polynomial through the 12 grid points around r (barycentric form with the
+ * equispaced weights (-1)^j C(11, j)): centred stencils, except next to a support that starts
+ * at r = 0, where the stencil keeps to r >= 0; 0 outside.  Checked against the definition in
+ * the tests.
+ * ---------------------------------------------------------------------------------------- */
+#define ORC_LAG 12
+#define ORC_PAD 8
+typedef struct {
+    int N, n;              /* N: basis count L = nodes (p + 1) */
+    double *lo, *hi, *h;   /* per (k,i), index k*N + i */
+    int64_t *off;          /* first value of (k,i) in val, -1: not tabulated (outside rmax) */
+    double *val;           /* 2 (n + 1 + 2 ORC_PAD) per kernel: psi at r_{-ORC_PAD}.., then tpsi */
+} orc_tables;
+
+void orc_tables_free(orc_tables *T)
+{
+    if (!T) return;
+    free(T->lo); free(T->hi); free(T->h); free(T->off); free(T->val); free(T);
+}
+
+orc_tables *orc_tables_build(const double *t, int Nn, int cut, int p, double rmax, int n)
+{
+    tq_init();
+    if (n < ORC_LAG) n = ORC_LAG;
+    int N = Nn * (p + 1);
+    orc_tables *T = (orc_tables *)calloc(1, sizeof(orc_tables));
+    T->N = N; T->n = n;
+    T->lo = (double *)malloc(sizeof(double) * N * N);
+    T->hi = (double *)malloc(sizeof(double) * N * N);
+    T->h = (double *)malloc(sizeof(double) * N * N);
+    T->off = (int64_t *)malloc(sizeof(int64_t) * N * N);
+    int64_t tot = 0;
+    for (int k = 0; k < N; ++k)
+        for (int i = 0; i < N; ++i) {
+            int f = k * N + i;
+            orc_support(t, Nn, p, k, i, &T->lo[f], &T->hi[f]);
+            double end = T->hi[f] < rmax ? T->hi[f] : rmax;
+            T->off[f] = -1;
+            T->h[f] = 0.0;
+            if (T->hi[f] > T->lo[f] && end > T->lo[f]) {
+                T->h[f] = (end - T->lo[f]) / n;
+                T->off[f] = tot;
+                tot += 2 * (int64_t)(n + 1 + 2 * ORC_PAD);
+            }
+        }
+    T->val = (double *)malloc(sizeof(double) * (tot > 0 ? tot : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int f = 0; f < N * N; ++f) {
+        if (T->off[f] < 0) continue;
+        double *v = T->val + T->off[f];
+        int np = n + 1 + 2 * ORC_PAD;
+        for (int m = 0; m < np; ++m) {
+            double o[2];
+            psi_integral(t, Nn, cut, p, f / N, f % N, T->lo[f] + (m - ORC_PAD) * T->h[f], o);
+            v[m] = o[0];
+            v[np + m] = o[1];
+        }
+    }
+    return T;
+}
+
+/* psi, tpsi of (k,i) at r from the tables; returns 0 (and zeros) outside the open support. */
+static int table_psi(const orc_tables *T, int k, int i, double r, double out[2])
+{
+    int f = k * T->N + i;
+    out[0] = out[1] = 0.0;
+    if (!(r > T->lo[f] && r < T->hi[f]) || T->off[f] < 0) return 0;
+    const double *v = T->val + T->off[f];
+    int np = T->n + 1 + 2 * ORC_PAD;
+    double u = (r - T->lo[f]) / T->h[f] + ORC_PAD;     /* grid coordinate, node m at m */
+    int a = (int)u - ORC_LAG / 2 + 1;                  /* nodes a .. a + 11 around u */
+    if (a > np - ORC_LAG) a = np - ORC_LAG;            /* r at rmax (the mesh's longest distance) */
+    /* a support starting at r = 0: the kernels of the first bases are not smooth across r = 0
+     * (b_0'' jumps at 0), so the stencil stays on r >= 0 */
+    if (T->lo[f] == 0.0 && a < ORC_PAD) a = ORC_PAD;
+    double num0 = 0.0, num1 = 0.0, den = 0.0, c = 1.0;   /* c = C(11, j) with alternating sign */
+    for (int j = 0; j < ORC_LAG; ++j) {
+        double d = u - (a + j);
+        if (d == 0.0) { out[0] = v[a + j]; out[1] = v[np + a + j]; return 1; }
+        double q = c / d;
+        num0 += q * v[a + j];
+        num1 += q * v[np + a + j];
+        den += q;
+        c = -c * (double)(ORC_LAG - 1 - j) / (double)(j + 1);
+    }
+    out[0] = num0 / den;
+    out[1] = num1 / den;
+    return 1;
+}
+
+void orc_psi_fast(const orc_tables *T, int k, int i, double r, double out[2]) { table_psi(T, k, i, r, out); }
 
 /* ------------------------------------------------------------------------------------------
  * Spatial quadrature.
@@ -383,29 +527,56 @@ static void tri_build(const double *xyz, const int32_t *tri, int e, tri_t *T)
  * ---------------------------------------------------------------------------------------- */
 typedef struct {
     const double *t;
-    int N, cut, mode;
-    int64_t *count;   /* optional: number of (point pair, k, i) evaluated */
+    int N, cut, mode;        /* N: time nodes */
+    int64_t *count;          /* optional: number of (point pair, k, i) evaluated */
+    const orc_tables *tab;   /* fast mode: tabulated kernels (NULL: direct quadrature) */
+    int p, L;                /* temporal order, bases L = N (p + 1) */
 } tctx_t;
+
+/* Number of (k,i) blocks a kernel mode fills: every (k,i) for the paper's kernels, one for the
+ * closed-form test kernels. */
+static int mode_blocks(int mode, int N) { return (mode == 0 || mode == 4 || mode == 5) ? N : 1; }
+
+/* For fixed k both ends of the support (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) decrease with i,
+ * so {i : r in supp psi_{k,i}} is one range [ia, ib]; binary searches of the two ends. */
+static void support_range(const tctx_t *C, int k, double r, int *ia, int *ib)
+{
+    const orc_tables *T = C->tab;
+    int N = C->L, a = 0, b = N;                 /* first i with lo < r */
+    while (a < b) { int m = (a + b) / 2; if (T->lo[k * N + m] < r) b = m; else a = m + 1; }
+    *ia = a;
+    a = 0; b = N;                               /* first i with hi <= r */
+    while (a < b) { int m = (a + b) / 2; if (T->hi[k * N + m] <= r) b = m; else a = m + 1; }
+    *ib = a - 1;
+}
 
 static void accumulate_point(const tctx_t *C, const double *lx, const double *ly,
                              double r, double wgt, double *S1, double *S2)
 {
-    int nb = (C->mode == 0 || C->mode >= 4) ? C->N : 1;
-    if (C->mode >= 1 && C->mode <= 3) {
-        double v = C->mode == 1 ? r : C->mode == 2 ? r * r * r : 1.0;
-        double f = wgt * v / r;
+    int nb = mode_blocks(C->mode, C->L);
+    if ((C->mode >= 1 && C->mode <= 3) || C->mode == 6) {
+        /* closed-form kernels: (psi, tpsi) = (r, r), (r^3, r^3), (1, 1) or (r, r^3) */
+        double v1 = C->mode == 1 || C->mode == 6 ? r : C->mode == 2 ? r * r * r : 1.0;
+        double v2 = C->mode == 1 ? r : C->mode == 2 || C->mode == 6 ? r * r * r : 1.0;
+        double f1 = wgt * v1 / r, f2 = wgt * v2 / r;
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) S1[3 * a + b] += f * lx[a] * ly[b];
-        S2[0] += f;
+            for (int b = 0; b < 3; ++b) S1[3 * a + b] += f1 * lx[a] * ly[b];
+        S2[0] += f2;
         return;
     }
-    for (int k = 0; k < C->N; ++k)
-        for (int i = 0; i < C->N; ++i) {
-            double lo, hi;
-            orc_support(C->t, C->N, k, i, &lo, &hi);
-            if (!(r > lo && r < hi)) continue;
+    for (int k = 0; k < C->L; ++k) {
+        int ia = 0, ib = C->L - 1;
+        if (C->tab) support_range(C, k, r, &ia, &ib);
+        for (int i = ia; i <= ib; ++i) {
             double ps[2];
-            orc_psi(C->t, C->N, C->cut, k, i, r, ps);
+            if (C->tab) {
+                if (!table_psi(C->tab, k, i, r, ps)) continue;
+            } else {
+                double lo, hi;
+                orc_support(C->t, C->N, C->p, k, i, &lo, &hi);
+                if (!(r > lo && r < hi)) continue;
+                orc_psi(C->t, C->N, C->cut, C->p, k, i, r, ps);
+            }
             if (C->count) ++*C->count;
             double f1 = C->mode == 4 ? 0.0 : wgt * ps[0] / r;
             double f2 = C->mode == 5 ? 0.0 : wgt * ps[1] / r;
@@ -414,12 +585,13 @@ static void accumulate_point(const tctx_t *C, const double *lx, const double *ly
                 for (int b = 0; b < 3; ++b) s1[3 * a + b] += f1 * lx[a] * ly[b];
             S2[k * nb + i] += f2;
         }
+    }
 }
 
 static void finish_local(const tctx_t *C, const tri_t *X, const tri_t *Y, const double *S1,
                          const double *S2, double *loc)
 {
-    int nb = (C->mode == 0 || C->mode >= 4) ? C->N : 1;
+    int nb = mode_blocks(C->mode, C->L);
     double nn = X->n[0] * Y->n[0] + X->n[1] * Y->n[1] + X->n[2] * Y->n[2];
     for (int kb = 0; kb < nb * nb; ++kb)
         for (int a = 0; a < 3; ++a)
@@ -505,7 +677,7 @@ static int pair_relation(const tri_t *X, const tri_t *Y, int px[3], int py[3])
  * symmetrised in (a, b) so that the assembled blocks are exactly symmetric. */
 static void pair_local(const tctx_t *C, const tri_t *X, const tri_t *Y, int ss_order, double *loc)
 {
-    int nb = (C->mode == 0 || C->mode >= 4) ? C->N : 1;
+    int nb = mode_blocks(C->mode, C->L);
     double *S1 = (double *)calloc((size_t)9 * nb * nb, sizeof(double));
     double *S2 = (double *)calloc((size_t)nb * nb, sizeof(double));
     int px[3], py[3];
@@ -527,9 +699,9 @@ static void pair_local(const tctx_t *C, const tri_t *X, const tri_t *Y, int ss_o
 
 /* Public: local integrals of one ordered triangle pair (used by the closed-form tests). */
 void orc_pair_local(const double *xyz, const int32_t *tri, int ex, int ey, const double *t, int N,
-                    int cut, int mode, int ss_order, double *loc)
+                    int cut, int porder, int mode, int ss_order, double *loc)
 {
-    tctx_t C = {t, N, cut, mode, NULL};
+    tctx_t C = {t, N, cut, mode, NULL, NULL, porder, N * (porder + 1)};
     tri_t X, Y;
     tri_build(xyz, tri, ex, &X);
     tri_build(xyz, tri, ey, &Y);
@@ -546,9 +718,9 @@ void orc_pair_local(const double *xyz, const int32_t *tri, int ex, int ey, const
  * buffers reduced in thread order.
  * ---------------------------------------------------------------------------------------- */
 int orc_assemble_dense(const double *xyz, int M, const int32_t *tri, int E, const double *t,
-                       int N, int cut, int mode, int ss_order, double *out)
+                       int N, int cut, int porder, int mode, int ss_order, const orc_tables *tab, double *out)
 {
-    int nb = (mode == 0 || mode >= 4) ? N : 1;
+    int nb = mode_blocks(mode, N * (porder + 1));
     size_t total = (size_t)nb * nb * M * M;
     memset(out, 0, total * sizeof(double));
     int nthr = 1;
@@ -557,7 +729,7 @@ int orc_assemble_dense(const double *xyz, int M, const int32_t *tri, int E, cons
 #endif
     double *buf = (double *)calloc(total * (size_t)nthr, sizeof(double));
     if (!buf) return -1;
-    tctx_t C = {t, N, cut, mode, NULL};
+    tctx_t C = {t, N, cut, mode, NULL, nb > 1 ? tab : NULL, porder, N * (porder + 1)};
 #pragma omp parallel
     {
         int tid = 0;
@@ -596,13 +768,13 @@ int orc_assemble_dense(const double *xyz, int M, const int32_t *tri, int E, cons
  * ordered pairs (tau containing l, sigma containing j), each integrated in the canonical order
  * of the dense assembly.  out[(s*nb + k)*nb + i]. */
 int orc_assemble_entries(const double *xyz, int M, const int32_t *tri, int E, const double *t,
-                         int N, int cut, int mode, int ss_order, int nsel, const int32_t *sel_j,
-                         const int32_t *sel_l, double *out)
+                         int N, int cut, int porder, int mode, int ss_order, const orc_tables *tab, int nsel,
+                         const int32_t *sel_j, const int32_t *sel_l, double *out)
 {
-    int nb = (mode == 0 || mode >= 4) ? N : 1;
+    int nb = mode_blocks(mode, N * (porder + 1));
     (void)M;
     memset(out, 0, sizeof(double) * (size_t)nsel * nb * nb);
-    tctx_t C = {t, N, cut, mode, NULL};
+    tctx_t C = {t, N, cut, mode, NULL, nb > 1 ? tab : NULL, porder, N * (porder + 1)};
     /* vertex -> triangles */
     int *cnt = (int *)calloc(M, sizeof(int));
     for (int e = 0; e < 3 * E; ++e) cnt[tri[e]]++;
@@ -664,19 +836,21 @@ int orc_assemble_entries(const double *xyz, int M, const int32_t *tri, int E, co
  * Output g[k*M + l].
  * ---------------------------------------------------------------------------------------- */
 int orc_rhs_plane_pulse(const double *xyz, int M, const int32_t *tri, int E, const double *t,
-                        int N, int cut, const double d[3], double t0, double width, double *g)
+                        int N, int cut, int porder, const double d[3], double t0, double width, double *g)
 {
     tq_init();
-    memset(g, 0, sizeof(double) * (size_t)N * M);
+    int L = N * (porder + 1);
+    memset(g, 0, sizeof(double) * (size_t)L * M);
     double B[21], W[7];
     orc_rule7(B, W);
-    for (int k = 0; k < N; ++k) {
+    for (int k = 0; k < L; ++k) {
+        int kn = k / (porder + 1);
         double lo, hi;
-        dsupp(t, N, k, &lo, &hi);
+        dsupp(t, N, kn, &lo, &hi);
         double pts[3];
         int np = 0;
         pts[np++] = lo;
-        if (k > 0 && k < N - 1) pts[np++] = t[k];
+        if (kn > 0 && kn < N - 1) pts[np++] = t[kn];
         pts[np++] = hi;
         for (int e = 0; e < E; ++e) {
             tri_t X;
@@ -697,7 +871,7 @@ int orc_rhs_plane_pulse(const double *xyz, int M, const int32_t *tri, int E, con
                             double sarg = tt - t0 - dx;
                             double Gp = -2.0 * sarg / (width * width) * exp(-(sarg / width) * (sarg / width));
                             double bk[3];
-                            orc_basis(t, N, cut, k, tt, bk);
+                            orc_basis(t, N, cut, porder, k, tt, bk);
                             ti += hw * g_tw[m] * Gp * bk[1];
                         }
                     }
@@ -720,9 +894,10 @@ int orc_rhs_plane_pulse(const double *xyz, int M, const int32_t *tri, int E, con
  * Output out[s*npts + p] for point p (pts[3p..3p+2]) and time times[s].
  * ---------------------------------------------------------------------------------------- */
 int orc_potential_dl(const double *xyz, int M, const int32_t *tri, int E, const double *t, int N, int cut,
-                     const double *alpha, int npts, const double *pts, int ntimes, const double *times,
+                     int porder, const double *alpha, int npts, const double *pts, int ntimes, const double *times,
                      double *out)
 {
+    int L = N * (porder + 1);
     double B[21], W[7];
     orc_rule7(B, W);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -740,9 +915,9 @@ int orc_potential_dl(const double *xyz, int M, const int32_t *tri, int E, const 
                 const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
                 const double nd = X.n[0] * d[0] + X.n[1] * d[1] + X.n[2] * d[2];
                 double phi = 0.0, dphi = 0.0;
-                for (int i = 0; i < N; ++i) {
+                for (int i = 0; i < L; ++i) {
                     double bi[3];
-                    orc_basis(t, N, cut, i, times[s] - r, bi);
+                    orc_basis(t, N, cut, porder, i, times[s] - r, bi);
                     if (bi[0] == 0.0 && bi[1] == 0.0) continue;
                     double dens = 0.0;
                     for (int a = 0; a < 3; ++a) dens += B[3 * q + a] * alpha[(size_t)i * M + X.v[a]];
@@ -760,10 +935,11 @@ int orc_potential_dl(const double *xyz, int M, const int32_t *tri, int E, const 
 /* Quadrature-point count of the method (one unit = one (x_q, y_q', k, i) with r inside the open
  * support of psi_{k,i}), over unordered triangle pairs, computed by brute force. */
 int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E, const double *t,
-                             int N, int ss_order)
+                             int N, int porder, int ss_order)
 {
     (void)M;
     int64_t total = 0;
+    int L = N * (porder + 1);
     double B[21], W[7];
     orc_rule7(B, W);
     int npmax = 6 * ss_order * ss_order * ss_order * ss_order;
@@ -802,10 +978,10 @@ int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E
                     }
                     for (int c = 0; c < 3; ++c) d2 += (x[c] - y[c]) * (x[c] - y[c]);
                     double r = sqrt(d2);
-                    for (int k = 0; k < N; ++k)
-                        for (int i = 0; i < N; ++i) {
+                    for (int k = 0; k < L; ++k)
+                        for (int i = 0; i < L; ++i) {
                             double lo, hi;
-                            orc_support(t, N, k, i, &lo, &hi);
+                            orc_support(t, N, porder, k, i, &lo, &hi);
                             if (r > lo && r < hi) ++total;
                         }
                 }
@@ -820,15 +996,16 @@ int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E
  * workload): returns the number of (point pair, k, i) evaluations; *checksum receives the sum
  * of all local entries so that nothing is optimised away. */
 int64_t orc_local_batch(const double *xyz, const int32_t *tri, int npairs, const int32_t *taus,
-                        const int32_t *sigmas, const double *t, int N, int cut, int ss_order,
-                        double *checksum)
+                        const int32_t *sigmas, const double *t, int Nn, int cut, int porder, int ss_order,
+                        const orc_tables *tab, double *checksum)
 {
     int64_t total = 0;
     double sum = 0.0;
+    int N = Nn * (porder + 1);
 #pragma omp parallel reduction(+ : total, sum)
     {
         int64_t mine = 0;
-        tctx_t C = {t, N, cut, 0, &mine};
+        tctx_t C = {t, Nn, cut, 0, &mine, tab, porder, N};
         double *loc = (double *)malloc(sizeof(double) * 9 * N * N);
 #pragma omp for schedule(dynamic, 1)
         for (int s = 0; s < npairs; ++s) {

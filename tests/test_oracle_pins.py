@@ -385,6 +385,100 @@ def test_selected_entries_match_dense(oracle_mod, small_blocks):
         assert np.allclose(sel[s], ref, rtol=0, atol=1e-15 * np.abs(A).max())
 
 
+def _mesh_closed_form(xyz, tri, curl_kernel):
+    """Global blocks of eq. (MatrixEntries) with psi = r in the n.n term and tilde psi = r (curl_kernel
+    "one": the kernel tilde psi / r is 1) or r^3 ("r2": the kernel is |x - y|^2), written out from
+    the mesh: A(j, l) = sum over tau containing l and sigma containing j of
+      (n_tau . n_sigma) |tau||sigma| / (36 pi) + (e_a . e_b) / (4|tau||sigma|) I(tau, sigma) / (4 pi),
+    with e_a the edge of tau opposite l, e_b the edge of sigma opposite j, I = |tau||sigma| for the
+    constant kernel and I = |tau||sigma| (|m_tau - m_sigma|^2 + s_tau + s_sigma) for |x - y|^2
+    (m the centroid, s = (|e_0|^2 + |e_1|^2 + |e_2|^2) / 36 the triangle's second moment about
+    it)."""
+    M = len(xyz)
+    A = np.zeros((M, M))
+    G = [_geom(xyz, tri, e) for e in range(len(tri))]
+    cen = [g[0].mean(axis=0) for g in G]
+    mom = [sum(np.dot(v, v) for v in g[3]) / 36.0 for g in G]
+    for p in range(len(tri)):
+        _, n1, a1, e1 = G[p]
+        for q in range(len(tri)):
+            _, n2, a2, e2 = G[q]
+            if curl_kernel == "one":
+                I = a1 * a2
+            else:
+                d = cen[p] - cen[q]
+                I = a1 * a2 * (np.dot(d, d) + mom[p] + mom[q])
+            for a in range(3):
+                for b in range(3):
+                    A[tri[q][b], tri[p][a]] += (np.dot(n1, n2) * a1 * a2 / (36 * np.pi)
+                                                + np.dot(e1[a], e2[b]) / (4 * a1 * a2) * I / (4 * np.pi))
+    return A
+
+
+@pytest.mark.parametrize("mode", ["r", "r_r3"])
+def test_whole_mesh_closed_forms(oracle_mod, mode):
+    """P9: the assembled global block for polynomial kernels equals its closed form computed from
+    the mesh alone (geometry, surface curls, the P1 scatter with its local vertex numbering, the
+    mirroring of unordered pairs, every Sauter-Schwab kind); mode r_r3 sends psi = r to the n.n
+    term and tilde psi = r^3 to the curl-curl term, so exchanging the two kernels, or a vertex
+    permutation inside a triangle, changes the result."""
+    for xyz, tri in (icosphere(0), _torus_small()):
+        A = oracle_mod.assemble_dense(xyz, tri, np.array([0.0, 1.0]), mode=mode)[0, 0]
+        ref = _mesh_closed_form(xyz, np.asarray(tri), "one" if mode == "r" else "r2")
+        assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max(), np.abs(A - ref).max() / np.abs(ref).max()
+
+
+def _torus_small():
+    from workloads import torus
+    return torus(5, 4)
+
+
+def test_kernel_swap_is_visible(oracle_mod):
+    """The two closed forms of P9 differ (so the r_r3 pin is not blind to a psi <-> tilde psi swap)."""
+    xyz, tri = icosphere(0)
+    a = oracle_mod.assemble_dense(xyz, tri, np.array([0.0, 1.0]), mode="r_r3")[0, 0]
+    swapped = _mesh_closed_form(xyz, np.asarray(tri), "one")
+    assert np.abs(a - swapped).max() > 1e-3 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("name,p", [("eq10", 0), ("graded16", 0), ("eq8_erf", 1)])
+def test_fast_mode_tables_against_definition(oracle_mod, name, p):
+    """Fast mode (the oracle's own uniform-grid tabulation) against direct quadrature of eq.
+    (psis) at 10^4 seeded distances: within 1e-12 (psi) and 5e-13 (tilde psi) of each kernel's
+    maximum -- the definition's own quadrature error is of that size (a four times finer table
+    does not get closer), and exact zeros outside the open support."""
+    grid, kind = GRIDS[name] if name in GRIDS else (graded_grid(16, 4.0, seed=9), "bump")
+    rmax = 2.0
+    T = oracle_mod.Tables(grid, kind, rmax, 2048, p)
+    L = len(grid) * (p + 1)
+    rng = np.random.default_rng(11)
+    sup = {(k, i): oracle_mod.support(grid, k, i, p) for k in range(L) for i in range(L)}
+    kernels = [ki for ki, (lo, hi) in sup.items() if lo < rmax and hi > lo]
+    worst = np.zeros(2)
+    per = max(1, 10000 // len(kernels))
+    for (k, i) in kernels:
+        lo, hi = sup[(k, i)]
+        rs = rng.uniform(lo, min(hi, rmax), per)
+        ex = np.array([oracle_mod.psi(grid, k, i, r, kind, p) for r in rs])
+        fa = np.array([T.psi(k, i, r) for r in rs])
+        sc = np.maximum(np.abs(ex).max(axis=0), 1e-300)
+        worst = np.maximum(worst, np.abs(fa - ex).max(axis=0) / sc)
+        for r in (lo - 1e-9, hi + 1e-9, lo):
+            if r >= 0 and (r <= lo or r >= hi):
+                assert np.all(T.psi(k, i, r) == 0.0)
+    assert worst[0] <= 1e-12 and worst[1] <= 5e-13, worst
+
+
+def test_fast_mode_assembly_matches_definition(oracle_mod, small_blocks):
+    """The dense assembly in fast mode against the definition-mode assembly (every block)."""
+    c, A = small_blocks
+    xyz, tri = c["mesh"]
+    T = oracle_mod.fast_tables(xyz, c["grid"], c["cutoff"])
+    F = oracle_mod.assemble_dense(xyz, tri, c["grid"], kind=c["cutoff"], tables=T)
+    assert np.abs(F - A).max() <= 1e-12 * np.abs(A).max()
+    assert np.array_equal(F == 0.0, A == 0.0)
+
+
 def test_block_count_formula():
     """P16: the number of inner non-zero blocks on an equidistant grid is
     n_z = (N^2 - N - 4)/2 - (N - n~_z - 2)/2 max(N - n~_z - 1, 0) (Section 5.1), where n~_z is
