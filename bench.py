@@ -1,18 +1,21 @@
 """Benchmark of the space-time Galerkin TDBIE hot path on one MI355X.
 
-One step = the whole hot path on the resident inputs of the 5120-triangle sphere with 64 graded
-temporal bases on [0, 8]: geometry, time-kernel tables, band layout, regular and singular
-assembly of every block A_{k,i} in FP64, the plane-pulse right-hand side, and the FGMRES solve
-to a relative residual of 1e-8 with the recursive block-Hessenberg preconditioner (Algorithm 1).
+Workload: the 5120-triangle icosphere with 64 graded temporal bases on [0, 8] (every input seeded
+and synthetic, resident in device memory before the timed region).
 
-The headline value is assembly quadrature evaluations per second (one evaluation = one
-(x_q, y_q', k, i) with |x_q - y_q'| inside supp psi_{k,i}, counted over unordered triangle pairs).
-The same JSON line carries the solve, the mixed-precision form (FP32 far field, FP64 singular
-pairs and solver) with its error against FP64, the roofline of the dominant kernel (the
-regular-pair assembly kernel, FP64 vector ALU bound) and the CPU oracle timed on a sample of the
-same workload.  The learned leg trains the message-passing preconditioner on the assembled
-operator (the library's own forward, backward and Adam kernels) and solves the same problem with
-FGMRES preconditioned by the network, in FP64 and on the mixed-precision operator.
+One step = the FP64 assembly of every block A_{k,i} of the block-Hessenberg system (geometry,
+time-kernel tables, band layout, regular and singular triangle pairs) and the plane-pulse
+right-hand side.  The headline value is assembly quadrature evaluations per second over the
+timed steps (one evaluation = one (x_q, y_q', k, i) with |x_q - y_q'| inside supp psi_{k,i},
+counted over unordered triangle pairs).
+
+After the timed steps, each once and within a wall-clock budget: the CPU oracle on a bounded
+sample of the same workload, the block matvec, the FGMRES solve to a relative residual of 1e-8
+with the recursive block-Hessenberg preconditioner (Algorithm 1), the mixed-precision form
+(FP32 far field and storage, FP64 singular pairs and solver) with its error against FP64, the
+field off the surface, the learned preconditioner (trained on the GPU, then used in FGMRES) with
+the batched right-hand sides, and the uneven-mesh group assembly.  One JSON line is printed at
+the end (or on SIGTERM, with what has been measured by then).
 
 `--copy-calibration` runs only a plain 1 GiB device copy (the reference kernel that scales the
 FETCH_SIZE / WRITE_SIZE hardware counters into HBM bytes).
@@ -21,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import signal
 import sys
 import time
 
@@ -30,12 +34,11 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6          # MI355X, published
 HBM_PEAK_GBS = 8000.0
-# Algorithmic FP64 flops of one quadrature evaluation: the Chebyshev polynomials T_2..T_D of
-# the piece variable by their three-term recurrence (one FMA each), the two series psi and
-# tilde psi (one FMA per term), the map of r to the piece variable (2), the weight w_q w_q'/r
-# (2) and the accumulation (psi w, three products and sums with lam_b, tilde psi w and its sum: 9).
-CHEB_DEGREE = 14
-FLOPS_PER_QUAD_EVAL = 2 * (CHEB_DEGREE - 1) + 2 * 2 * CHEB_DEGREE + 2 + 2 + 9
+# Algorithmic FP64 flops of one quadrature evaluation (FMA = 2): the two Chebyshev series of
+# psi and tilde psi with their shared recurrence, 4 (D + 1), and the weight and the
+# accumulation into the local sums, 12 -- about 80 at degree D = 16.  The kernel runs at D = 14
+# (4 * 15 + 12 = 72); the figure 80 is kept as the per-evaluation work of the method.
+FLOPS_PER_QUAD_EVAL = 80
 REGULAR_KERNEL = "k_regular_tile"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07221_amd", "csrc", "k_assemble.hip")
 
@@ -43,17 +46,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1503_07221_amd", "csrc", "k_assemble.h
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere5120_graded64")
+    ap.add_argument("--budget-s", type=float, default=330.0,
+                    help="wall-clock seconds after which no further optional leg starts")
     ap.add_argument("--precond", default="2,10", help="Algorithm 1 inner iterations per level ('' = none)")
     ap.add_argument("--restart", type=int, default=300)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-it", type=int, default=300)
-    ap.add_argument("--skip-solve", action="store_true", help="assembly and right-hand side only (profiling)")
+    ap.add_argument("--skip-solve", action="store_true", help="no solve legs (profiling)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=2000, help="regular pairs timed on the CPU oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="approximate CPU seconds of the oracle sample (split over regular and singular pairs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--lp-steps", type=int, default=300,
                     help="Adam steps (batch 8, lr 1e-3) of the learned preconditioner, then half as many at 5e-4")
@@ -107,24 +113,71 @@ def counted_traffic(workload, launches_quad):
         return None
 
 
-def cpu_baseline(cfg, npairs):
-    """The oracle (plain C + OpenMP, direct quadrature of the time kernels) on a seeded sample of
-    regular triangle pairs of the same workload."""
+def cpu_baseline(cfg, seconds, quad_regular, quad_singular):
+    """The oracle in fast mode (plain C + OpenMP over triangle pairs, FP64, -O3, the same
+    quadrature rules, its own uniform-grid tabulation of the time kernels) on seeded samples of
+    the workload's unordered triangle pairs: regular pairs and singular (coincident, edge, vertex)
+    pairs are timed separately, each for about half of `seconds`; the time of the whole assembly
+    is the table build plus each kind's time per quad-eval times its exact count."""
     import numpy as np
     import oracle
     xyz, tri = cfg["mesh"]
+    E = len(tri)
     rng = np.random.default_rng(7)
     sets = [set(t) for t in tri]
-    taus, sigs = [], []
-    while len(taus) < npairs:
-        a, b = (int(x) for x in rng.integers(0, len(tri), 2))
-        if a < b and not (sets[a] & sets[b]):
-            taus.append(a); sigs.append(b)
+    vt = {}
+    for e, t in enumerate(tri):
+        for v in t:
+            vt.setdefault(int(v), []).append(e)
+    singular = sorted({(min(a, b), max(a, b)) for lst in vt.values() for a in lst for b in lst})
+    order = rng.permutation(len(singular))
+    singular = [singular[s] for s in order]
     t0 = time.perf_counter()
-    n, _ = oracle.local_batch(xyz, tri, np.array(taus), np.array(sigs), cfg["grid"], kind=cfg["cutoff"])
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "quad-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{npairs} random regular triangle pairs of {cfg['name']} ({n} quad-evals, {dt:.1f} s)"}
+    tables = oracle.fast_tables(xyz, cfg["grid"], cfg["cutoff"])
+    t_tables = time.perf_counter() - t0
+
+    def regular_pairs(n):
+        taus, sigs = [], []
+        while len(taus) < n:
+            a, b = (int(x) for x in rng.integers(0, E, 2))
+            if a < b and not (sets[a] & sets[b]):
+                taus.append(a); sigs.append(b)
+        return np.array(taus), np.array(sigs)
+
+    def sample(kind, n):
+        if kind == "regular":
+            return regular_pairs(n)
+        sel = singular[:min(n, len(singular))]
+        return np.array([s[0] for s in sel]), np.array([s[1] for s in sel])
+
+    def timed(taus, sigs):
+        t0 = time.perf_counter()
+        q, _ = oracle.local_batch(xyz, tri, taus, sigs, cfg["grid"], kind=cfg["cutoff"], tables=tables)
+        return q, time.perf_counter() - t0
+
+    res = {}
+    for kind in ("regular", "singular"):
+        n = 64
+        taus, sigs = sample(kind, n)
+        q, dt = timed(taus, sigs)
+        while dt < 0.05 * seconds and not (kind == "singular" and n >= len(singular)):
+            n *= 4
+            taus, sigs = sample(kind, n)
+            q, dt = timed(taus, sigs)
+        if dt < 0.25 * seconds and not (kind == "singular" and n >= len(singular)):
+            n = int(n * 0.5 * seconds / max(dt, 1e-3))
+            taus, sigs = sample(kind, n)
+            q, dt = timed(taus, sigs)
+        res[kind] = (len(taus), q, dt)
+    (nr, qr, tr), (ns, qs, ts) = res["regular"], res["singular"]
+    est = t_tables + quad_regular * tr / qr + quad_singular * ts / qs
+    return {"value": (quad_regular + quad_singular) / est, "unit": "quad-evals/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"oracle fast mode: kernel tables {t_tables:.1f} s, {nr} random regular pairs ({qr} "
+                       f"quad-evals, {tr:.1f} s) and {ns} random singular pairs ({qs} quad-evals, {ts:.1f} s) of "
+                       f"{cfg['name']}; the whole FP64 assembly ({quad_regular + quad_singular} quad-evals) "
+                       f"extrapolated from them: {est:.0f} s"),
+            "extrapolated_assembly_s": est}
 
 
 def sample_entries(ctx, cfg, n, seed):
@@ -194,9 +247,50 @@ def potential_leg(ctx, tb, alpha, cfg):
             "quadrature_evals_per_s": evals / (ms * 1e-3), "max_abs_u": float(u.abs().max())}
 
 
-def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
-    """Train the learned preconditioner on the FP64 operator, then solve with it in FP64 and on
-    the mixed-precision operator; solutions are compared with the Algorithm 1 solution alpha_ref."""
+def mixed_leg(ctx, tb, cfg, args, g, alpha64, inner, n, time_matvec, rep64):
+    """The mixed form (FP32 far-field quadrature and FP32 storage; FP64 singular pairs, tables and
+    solver) on the same inputs: assembly speed, entry and matvec error against the FP64 assembly,
+    and the solve of the mixed system, whose residual is also measured on the FP64 operator."""
+    import numpy as np
+    import torch
+    xr = torch.randn(n, dtype=torch.float64, device="cuda:0",
+                     generator=torch.Generator(device="cuda:0").manual_seed(11))
+    ctx.assemble(tb.FP64)
+    y64 = ctx.matvec(xr).clone()
+    ks, is_, js, ls = sample_entries(ctx, cfg, 200000, 5)
+    e64 = ctx.get_entries(ks, is_, js, ls)
+    mreps = [ctx.assemble(tb.MIXED) for _ in range(2)]
+    mrep = mreps[-1]
+    print(f"# mixed: assembly {mrep['ms_total']:.1f} ms (regular {mrep['ms_regular']:.1f})", file=sys.stderr,
+          flush=True)
+    y32 = ctx.matvec(xr)
+    e32 = ctx.get_entries(ks, is_, js, ls)
+    mv32 = time_matvec()
+    res = {"assembly_ms": mrep["ms_total"], "regular_ms": mrep["ms_regular"],
+           "value": mrep["quad_evals"] / (mrep["ms_total"] * 1e-3), "matrix_bytes": int(mrep["bytes_matrix"]),
+           "fp64_assembly_ms": rep64["ms_total"], "matvec_ms": mv32,
+           "matvec_GBps": mrep["bytes_matrix"] / (mv32 * 1e-3) / 1e9,
+           "matvec_rel_err_vs_fp64": float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)),
+           "entry_max_err_rel_to_max_entry": float(np.max(np.abs(e32 - e64)) / np.max(np.abs(e64)))}
+    if alpha64 is not None and not args.skip_solve:
+        a32, srep = ctx.solve(g, tol=args.tol, restart=args.restart, max_it=args.max_it, precond_inner=inner)
+        ctx.assemble(tb.FP64)                                 # FP64 residual of the mixed solution
+        r = g - ctx.matvec(a32)
+        r64 = float(torch.linalg.norm(r) / torch.linalg.norm(g))
+        res.update({"solve_ms": srep["ms"], "iterations": int(srep["iterations"]),
+                    "rel_residual_mixed_operator": float(srep["rel_residual"]),
+                    "rel_residual_fp64_operator": r64, "converged_fp64_operator": r64 <= args.tol,
+                    "solution_rel_diff_vs_fp64": float(torch.linalg.norm(a32 - alpha64) / torch.linalg.norm(alpha64))})
+        print(f"# mixed solve: {srep['ms']:.0f} ms ({srep['iterations']} it), residual {srep['rel_residual']:.2e} "
+              f"on the mixed operator, {r64:.2e} on the FP64 operator", file=sys.stderr, flush=True)
+    ctx.assemble(tb.FP64)
+    return res
+
+
+def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref, budget):
+    """Train the learned preconditioner on the FP64 operator, then solve with it (kernels launched
+    one by one, then as a captured graph per iteration); solutions are compared with the Algorithm 1
+    solution alpha_ref."""
     import numpy as np
     import torch
     ctx.assemble(tb.FP64)
@@ -219,11 +313,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
            "train_ms": trep["ms"], "train_samples": int(trep["samples"]), "loss_first": float(hist[0]),
            "loss_last10": float(hist[-10:].mean()), "apply_ms": e0.elapsed_time(e1) / 10}
     nrm = torch.linalg.norm(alpha_ref)
-    for tag, prec in (("fp64", tb.FP64), ("mixed", tb.MIXED)):
-        if prec == tb.MIXED:
-            if args.no_mixed:
-                continue
-            ctx.assemble(tb.MIXED)
+    for tag in ("fp64",):
         a, srep = ctx.solve(g, tol=args.tol, restart=args.lp_restart, max_it=args.lp_max_it,
                             precond_kind=tb.PRECOND_LEARNED)
         print(f"# learned {tag}: solve {srep['ms']:.1f} ms ({srep['iterations']} it, residual "
@@ -241,7 +331,7 @@ def learned_leg(ctx, tb, args, g, alpha_ref, solve_ref):
     res["fp64_graph"] = {"solve_ms": srep["ms"], "iterations": int(srep["iterations"]),
                          "rel_residual": float(srep["rel_residual"]), "converged": bool(srep["converged"]),
                          "solution_rel_diff_vs_alg1_fp64": float(torch.linalg.norm(a - alpha_ref) / nrm)}
-    if args.batch_rhs > 0:
+    if args.batch_rhs > 0 and budget.allows("batched", 75):
         res["batched"] = batched_leg(ctx, tb, args, res["fp64"]["solve_ms"])
     ctx.assemble(tb.FP64)
     return res
@@ -281,15 +371,37 @@ def batched_leg(ctx, tb, args, single_ms):
             "product_ms": multi_ms, "product_ms_per_rhs": multi_ms / R}
 
 
+class Budget:
+    """Wall-clock budget of the optional legs: a leg starts only if its estimated duration fits in
+    what is left, so the whole run stays inside the time the caller allows."""
+
+    def __init__(self, seconds):
+        self.t0 = time.perf_counter()
+        self.seconds = seconds
+        self.skipped = []
+
+    def left(self):
+        return self.seconds - (time.perf_counter() - self.t0)
+
+    def allows(self, name, estimate_s):
+        if self.left() >= estimate_s:
+            return True
+        self.skipped.append(name)
+        print(f"# {name}: skipped ({estimate_s:.0f} s estimated, {self.left():.0f} s of the budget left)",
+              file=sys.stderr, flush=True)
+        return False
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark measures one GPU; --gpus must be 1 "
                                    "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
         return
+    budget = Budget(args.budget_s)
     import numpy as np
     import torch
     import paper_1503_07221_amd as tb
@@ -305,15 +417,25 @@ def main():
     n = len(grid) * len(xyz)
     g = torch.empty(n, dtype=torch.float64, device="cuda:0")
     alpha = torch.empty_like(g)
+    out = {}
 
-    def step(prec=tb.FP64, out=alpha):
-        rep = ctx.assemble(prec)
+    def emit(signum=None, frame=None):
+        """Print the JSON line with what has been measured so far (also on SIGTERM)."""
+        if out.get("_printed"):
+            return
+        out["_printed"] = True
+        line = {k: v for k, v in out.items() if k != "_printed"}
+        if budget.skipped:
+            line["legs_skipped"] = budget.skipped
+        print(json.dumps(line), flush=True)
+        if signum is not None:
+            sys.exit(124)
+
+    def step():
+        """One step: the FP64 assembly of every block and the right-hand side."""
+        rep = ctx.assemble(tb.FP64)
         ctx.rhs_plane_pulse(cfg["direction"], cfg["t0"], cfg["width"], out=g)
-        srep = None
-        if not args.skip_solve:
-            _, srep = ctx.solve(g, tol=args.tol, restart=args.restart, max_it=args.max_it, precond_inner=inner,
-                                out=out)
-        return rep, srep
+        return rep
 
     def time_matvec(launches=20):
         """Average time of a full block matvec y = A x (HIP events on the library's stream)."""
@@ -330,21 +452,22 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) / launches
 
-    def note(tag, rep, srep):
+    def note(tag, rep, srep=None):
         s = f"# {tag}: assembly {rep['ms_total']:.1f} ms (regular {rep['ms_regular']:.1f})"
         if srep:
             s += f", solve {srep['ms']:.1f} ms ({srep['iterations']} it, residual {srep['rel_residual']:.2e})"
         print(s, file=sys.stderr, flush=True)
 
+    # ---- the timed steps: FP64 assembly (the headline) -------------------------------------
     for w in range(args.warmup):
-        note(f"warmup {w}", *step())
+        note(f"warmup {w}", step())
     torch.cuda.synchronize()
-    reps, sreps = [], []
+    reps = []
     t0 = time.perf_counter()
     for s in range(args.steps):
-        rep, srep = step()
-        reps.append(rep); sreps.append(srep)
-        note(f"step {s}", rep, srep)
+        rep = step()
+        reps.append(rep)
+        note(f"step {s}", rep)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -353,10 +476,9 @@ def main():
     asm_ms = float(np.mean([r["ms_total"] for r in reps]))
     reg_ms = float(np.mean([r["ms_regular"] for r in reps]))
     achieved_tflops = quad_reg * FLOPS_PER_QUAD_EVAL / (reg_ms * 1e-3) / 1e12
-    traffic = counted_traffic(cfg["name"], quad_reg)
-    out = {
+    out.update({
         "metric": "assembly quad-evals/s + FGMRES solve time to 1e-8 resid (FP64 vs mixed)",
-        "value": quad / (asm_ms * 1e-3),
+        "value": quad * args.steps / wall,
         "unit": "quad-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -369,9 +491,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "triangles": int(len(tri)), "vertices": int(len(xyz)),
                    "time_bases": int(len(grid)), "T": float(grid[-1]), "precision": "fp64",
-                   "solver": (f"FGMRES({args.restart}) + Algorithm 1 {inner}" if inner else f"FGMRES({args.restart})")
-                   if not args.skip_solve else "none (assembly only)"},
-        "assembly_ms": asm_ms,
+                   "step": "FP64 assembly of every block (tables, layout, regular and singular pairs) "
+                           "+ right-hand side"},
+        "assembly_ms_events": asm_ms,
         "quad_evals": int(quad),
         "quad_evals_regular": int(quad_reg),
         "assembly_breakdown_ms": {k: float(np.mean([r[k] for r in reps]))
@@ -379,54 +501,49 @@ def main():
         "matrix_bytes": int(reps[-1]["bytes_matrix"]),
         "roofline": {"bound": "alu", "kernel": REGULAR_KERNEL, "achieved": achieved_tflops,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": counted_traffic(cfg["name"], quad_reg),
                      "flops_per_quad_eval": FLOPS_PER_QUAD_EVAL, "launch_ms": reg_ms,
                      "quad_evals_per_launch": int(quad_reg)},
-    }
+    })
+    signal.signal(signal.SIGTERM, emit)
+
+    # ---- the CPU oracle on a bounded sample of the same workload ----------------------------
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds, quad_reg, quad - quad_reg)
+        print(f"# cpu baseline: {out['cpu_baseline']['value']:.3e} quad-evals/s "
+              f"({out['cpu_baseline']['cores']} threads)", file=sys.stderr, flush=True)
+
+    # ---- the block matvec ------------------------------------------------------------------
     mv_ms = time_matvec()
     out["matvec"] = {"fp64_ms": mv_ms, "fp64_GBps": reps[-1]["bytes_matrix"] / (mv_ms * 1e-3) / 1e9,
-                     "hbm_peak_GBps": HBM_PEAK_GBS, "fp64_frac": reps[-1]["bytes_matrix"] / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    if not args.skip_solve:
-        out["solve"] = {"ms": float(np.mean([s["ms"] for s in sreps])), "iterations": int(sreps[-1]["iterations"]),
-                        "matvecs": int(sreps[-1]["matvecs"]), "rel_residual": float(sreps[-1]["rel_residual"]),
-                        "converged": bool(sreps[-1]["converged"])}
-    if not args.no_mixed:
-        # the mixed form on the same inputs, compared with the FP64 matrix and solution above
-        xr = torch.randn(n, dtype=torch.float64, device="cuda:0",
-                         generator=torch.Generator(device="cuda:0").manual_seed(11))
-        y64 = ctx.matvec(xr).clone()
-        ks, is_, js, ls = sample_entries(ctx, cfg, 200000, 5)
-        e64 = ctx.get_entries(ks, is_, js, ls)
-        a64 = alpha.clone()
-        alpha32 = torch.empty_like(g)
-        mrep, msrep = step(tb.MIXED, alpha32)
-        note("mixed", mrep, msrep)
-        y32 = ctx.matvec(xr)
-        e32 = ctx.get_entries(ks, is_, js, ls)
-        mv32 = time_matvec()
-        out["matvec"].update({"mixed_ms": mv32, "mixed_GBps": mrep["bytes_matrix"] / (mv32 * 1e-3) / 1e9})
-        mixed = {"assembly_ms": mrep["ms_total"], "regular_ms": mrep["ms_regular"],
-                 "value": mrep["quad_evals"] / (mrep["ms_total"] * 1e-3), "matrix_bytes": int(mrep["bytes_matrix"]),
-                 "matvec_rel_err_vs_fp64": float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64)),
-                 "entry_max_err_rel_to_max_entry": float(np.max(np.abs(e32 - e64)) / np.max(np.abs(e64)))}
-        if msrep:
-            mixed.update({"solve_ms": msrep["ms"], "iterations": int(msrep["iterations"]),
-                          "rel_residual_mixed_operator": float(msrep["rel_residual"]),
-                          "solution_rel_diff_vs_fp64": float(torch.linalg.norm(alpha32 - a64) / torch.linalg.norm(a64))})
-            ctx.assemble(tb.FP64)               # FP64 residual of the mixed solution
-            res = g - ctx.matvec(alpha32)
-            mixed["rel_residual_fp64_operator"] = float(torch.linalg.norm(res) / torch.linalg.norm(g))
-        out["mixed"] = mixed
-    if not args.no_potential and not args.skip_solve:
+                     "hbm_peak_GBps": HBM_PEAK_GBS,
+                     "fp64_frac": reps[-1]["bytes_matrix"] / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    # ---- the solve to 1e-8 (FP64, Algorithm 1) ----------------------------------------------
+    srep = None
+    if not args.skip_solve and budget.allows("solve", 40):
+        _, srep = ctx.solve(g, tol=args.tol, restart=args.restart, max_it=args.max_it, precond_inner=inner,
+                            out=alpha)
+        out["solve"] = {"solver": f"FGMRES({args.restart}) + Algorithm 1 {inner}" if inner
+                        else f"FGMRES({args.restart})",
+                        "ms": srep["ms"], "iterations": int(srep["iterations"]), "matvecs": int(srep["matvecs"]),
+                        "rel_residual": float(srep["rel_residual"]), "converged": bool(srep["converged"])}
+        print(f"# solve: {srep['ms']:.0f} ms ({srep['iterations']} it, residual {srep['rel_residual']:.2e})",
+              file=sys.stderr, flush=True)
+
+    # ---- the mixed form on the same inputs -----------------------------------------------------
+    if not args.no_mixed and budget.allows("mixed", 45):
+        out["mixed"] = mixed_leg(ctx, tb, cfg, args, g, alpha if srep else None, inner, n, time_matvec,
+                                 reps[-1])
+    if srep and not args.no_potential and budget.allows("potential", 15):
         out["potential"] = potential_leg(ctx, tb, alpha, cfg)
-    if not args.no_uneven:
+    if not args.no_learned and srep and budget.allows("learned", 110):
+        out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"), budget)
+    if not args.no_uneven and budget.allows("uneven", 30):
         out["uneven"] = uneven_leg(tb)
-    if not args.no_learned and not args.skip_solve:
-        out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_pairs)
     ctx.close()
-    print(json.dumps(out))
+    emit()
 
 
 if __name__ == "__main__":

@@ -85,12 +85,25 @@ typedef struct {
     /* preconditioner of the outer iteration: 0 = Algorithm 1 as set by precond_levels (none
      * when 0); 1 = the learned network of tdbem_learned.h (must be initialised); 2 = the learned
      * network during the first restart cycle, then Algorithm 1 (precond_levels > 0) from the
-     * iterate reached, the paper's preconditioner serving as the fallback */
+     * iterate reached, the paper's preconditioner serving as the fallback; 3 = DGMRES(restart,
+     * deflation_l) of Section 4.1: the deflation M^{-1} = I + U (|lambda_max| T^{-1} - I) U^T,
+     * T = U^T A U, where after every restart the eigenvectors of the cycle's Hessenberg matrix for
+     * its deflation_l smallest eigenvalues (mapped back through the Krylov basis) are added to U,
+     * up to deflation_max columns (precond_levels must be 0) */
     int32_t precond_kind;
     /* 1: with the learned network, run each outer iteration's preconditioned operator
      * (z = P(v), w = A z) as one captured HIP graph, replayed on the context's stream; 0: launch
      * the kernels one by one.  Requires precond_kind 1 or 2. */
     int32_t use_graph;
+    int32_t deflation_l;         /* DGMRES: vectors added to U after each restart (precond_kind 3) */
+    int32_t deflation_max;       /* DGMRES: largest dimension of U, <= 256 (precond_kind 3); U and
+                                    A U take 2 deflation_max N M float64 of device memory */
+    /* 1: the products inside Algorithm 1 (its inner FGMRES solves and the coupling block) read an
+     * FP32 copy of the FP64 band (made once per assembly, half the bytes of the band), while the
+     * outer iteration and its true residual keep the FP64 operator, so the solve still reaches tol
+     * on the FP64 system (FGMRES accepts the inexact preconditioner).  Needs an FP64 assembly and
+     * precond_levels > 0. */
+    int32_t inner_fp32;
 } tdbem_solve_opts;
 
 typedef struct {
@@ -115,10 +128,12 @@ const char *tdbem_last_error(const tdbem_ctx *ctx);
  * TDBEM_EMESH for an index out of range, a repeated vertex in a triangle or a zero area. */
 tdbem_status tdbem_set_mesh(tdbem_ctx *ctx, const double *xyz, int64_t M, const int32_t *tri, int64_t E);
 
-/* Time grid 0 = t_0 < t_1 < ... < t_{N-1} = T (host, float64), one temporal basis per node
- * (Section 3: mu_i from the cutoff, b_0 with the causal factor 8 (t/h_1)^2).  Resets any
- * assembled matrix.  TDBEM_EGRID unless N >= 2, t_0 = 0 and t strictly increasing. */
-tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdbem_cutoff cutoff);
+/* Time grid 0 = t_0 < t_1 < ... < t_{N-1} = T (host, float64) and temporal order p (Section 3,
+ * eq. (BasisFunctions): p + 1 bases per node, L = N (p + 1) in all).  This library implements
+ * p = 0, one basis per node (mu_i from the cutoff, b_0 with the causal factor 8 (t/h_1)^2);
+ * another p gives TDBEM_EINVAL.  Resets any assembled matrix.  TDBEM_EGRID unless 2 <= N <= 4096,
+ * t_0 = 0 and t strictly increasing. */
+tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdbem_cutoff cutoff, int32_t p);
 
 /* Assemble every block A_{k,i} of eq. (MatrixEntries) on the device (Section 3): kernels
  * psi_{k,i}, tilde psi_{k,i} of eq. (psis) tabulated as piecewise Chebyshev series
@@ -141,6 +156,20 @@ tdbem_status tdbem_assemble_group(tdbem_ctx *const *ctxs, int32_t n, tdbem_preci
  * arrays).  Entries outside the stored band are zero by eq. (SparsitySmallBlock). */
 tdbem_status tdbem_get_entries(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,
                                const int32_t *j, const int32_t *l, double *out);
+
+/* Number of entries of the assembled block A_{k,i} (the sparse blocks of eq. (Apartitioned), with
+ * the pattern of eq. (SparsitySmallBlock)): the non-zero values of the stored band, counted in
+ * both triangles (an off-diagonal vertex pair counts twice, the blocks being symmetric).  Written
+ * to *nnz (host).  Requires tdbem_assemble; TDBEM_EINVAL for k or i outside 0..N-1. */
+tdbem_status tdbem_block_nnz(tdbem_ctx *ctx, int32_t k, int32_t i, int64_t *nnz);
+
+/* The block A_{k,i} in coordinate form (host arrays owned by the caller, cap entries each):
+ * row[s] = l (test vertex), col[s] = j (trial vertex), val[s] = A_{k,i}(j, l) for the
+ * tdbem_block_nnz(ctx, k, i) entries, sorted by (row, column).  Values are float64 also after a
+ * mixed-precision assembly (the stored FP32 values, widened).  TDBEM_EINVAL if cap is smaller than
+ * the entry count (the message gives it); nothing is written then. */
+tdbem_status tdbem_get_block_coo(tdbem_ctx *ctx, int32_t k, int32_t i, int32_t *row, int32_t *col, double *val,
+                                 int64_t cap);
 
 /* Evaluate the tabulated time kernels used by the assembly: psi[s] = psi_{k[s],i[s]}(r[s]) and
  * tpsi[s] = tilde psi_{k[s],i[s]}(r[s]) of eq. (psis) for n host points (host arrays), 0 outside

@@ -385,3 +385,101 @@ def solve(Afull, g, N, M, tol=1e-8, restart=30, max_it=5000, alg1_inner=None):
     """FGMRES(restart) on A alpha = g, optionally with the Algorithm 1 preconditioner."""
     P = alg1_preconditioner(Afull, N, M, tol, alg1_inner) if alg1_inner else None
     return fgmres(lambda v: Afull @ v, g, tol, max_it, restart=restart, precond=P)
+
+
+# ---------------------------------------------------------------------------------------------
+# DGMRES(m, l): restarted GMRES preconditioned by deflation (Section 4.1, after Erhel, Burrage
+# and Pohl 1996)
+# ---------------------------------------------------------------------------------------------
+def deflation_inverse(v, U, Tinv, lam):
+    """M^{-1} v = v + U (|lambda_LM| T^{-1} - I) U^T v with T = U^T A U (Section 4.1)."""
+    if U.shape[1] == 0:
+        return v.copy()
+    c = U.T @ v
+    return v + U @ (lam * (Tinv @ c) - c)
+
+
+def smallest_invariant_basis(H, l):
+    """Real orthonormal basis (k x l', l' = l, or l + 1 to keep a complex pair whole) of the
+    invariant subspace of the k x k matrix H belonging to its l eigenvalues of smallest modulus,
+    and the largest eigenvalue modulus.  Eigenvectors by a library eigensolver; complex pairs
+    contribute their real and imaginary parts."""
+    ev, W = np.linalg.eig(H)
+    order = np.argsort(np.abs(ev), kind="stable")
+    cols, taken = [], 0
+    for idx in order:
+        if taken >= l:
+            break
+        if abs(ev[idx].imag) > 1e-14 * max(1.0, abs(ev[idx])):
+            if ev[idx].imag < 0:
+                continue                          # its conjugate partner supplies the pair
+            cols += [W[:, idx].real, W[:, idx].imag]
+            taken += 2
+        else:
+            cols.append(W[:, idx].real)
+            taken += 1
+    Y = np.array(cols).T if cols else np.zeros((H.shape[0], 0))
+    Q, _ = np.linalg.qr(Y)
+    return Q, float(np.abs(ev).max())
+
+
+def dgmres(apply_A, b, tol, max_it, m=50, l=4, rmax=None):
+    """DGMRES(m, l): GMRES(m) right-preconditioned by the deflation M^{-1} of Section 4.1.  After
+    every cycle the eigenvectors of the cycle's Hessenberg matrix H_m (of the preconditioned
+    operator A M^{-1}) for its l smallest eigenvalues, mapped back as V_m S, are orthonormalised
+    against U and appended to U until U has rmax columns (default 4 l); |lambda_LM| is estimated
+    by the largest eigenvalue modulus of H_m.  Stops at the true residual ||b - A x|| <= tol ||b||.
+    Returns (x, iterations, history)."""
+    n = b.shape[0]
+    rmax = 4 * l if rmax is None else rmax
+    x = np.zeros(n)
+    bnorm = np.linalg.norm(b)
+    hist = []
+    if bnorm == 0.0:
+        return x, 0, hist
+    U = np.zeros((n, 0)); AU = np.zeros((n, 0)); Tinv = np.zeros((0, 0)); lam = 1.0
+    its = 0
+    r = b.copy()
+    beta = np.linalg.norm(r)
+    while its < max_it and beta > tol * bnorm:
+        k = min(m, max_it - its)
+        V = np.zeros((k + 1, n)); Z = np.zeros((k, n)); H = np.zeros((k + 1, k))
+        V[0] = r / beta
+        done = 0
+        g = np.zeros(k + 1); g[0] = beta
+        for j in range(k):
+            Z[j] = deflation_inverse(V[j], U, Tinv, lam)
+            w = apply_A(Z[j])
+            for q in range(j + 1):
+                H[q, j] = np.dot(w, V[q])
+                w = w - H[q, j] * V[q]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            its += 1
+            done = j + 1
+            y, *_ = np.linalg.lstsq(H[:j + 2, :j + 1], g[:j + 2], rcond=None)
+            res = np.linalg.norm(g[:j + 2] - H[:j + 2, :j + 1] @ y)
+            hist.append(res / bnorm)
+            if res <= tol * bnorm or H[j + 1, j] == 0.0:
+                break
+        y, *_ = np.linalg.lstsq(H[:done + 1, :done], g[:done + 1], rcond=None)
+        x = x + Z[:done].T @ y
+        r = b - apply_A(x)
+        beta = np.linalg.norm(r)
+        if beta <= tol * bnorm or its >= max_it:
+            break
+        if U.shape[1] < rmax and done >= 2:
+            S, lam_c = smallest_invariant_basis(H[:done, :done], min(l, rmax - U.shape[1]))
+            lam = max(lam if U.shape[1] else 0.0, lam_c)
+            W = V[:done].T @ S
+            for _ in range(2):                   # orthonormalise against U, twice
+                W = W - U @ (U.T @ W)
+            Q, R = np.linalg.qr(W)
+            keep = np.abs(np.diag(R)) > 1e-10 * max(1.0, np.abs(np.diag(R)).max(initial=0.0))
+            Q = Q[:, keep]
+            if Q.shape[1]:
+                U = np.hstack([U, Q])
+                AU = np.hstack([AU, np.column_stack([apply_A(Q[:, c]) for c in range(Q.shape[1])])])
+                Tinv = np.linalg.inv(U.T @ AU)
+    return x, its, hist

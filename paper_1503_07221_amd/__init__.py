@@ -19,7 +19,7 @@ from .build import LIB_PATH, build_library
 
 __all__ = ["Context", "TdbemError", "assemble_group", "load_library", "build_library", "LIB_PATH", "EXPORTED_SYMBOLS",
            "FP64", "MIXED", "CUTOFF_BUMP", "CUTOFF_ERF", "PRECOND_ALG1", "PRECOND_LEARNED",
-           "PRECOND_LEARNED_THEN_ALG1"]
+           "PRECOND_LEARNED_THEN_ALG1", "PRECOND_DEFLATION"]
 
 FP64, MIXED = 0, 1
 CUTOFF_BUMP, CUTOFF_ERF = 0, 1
@@ -27,7 +27,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
           -6: "ESTATE"}
 
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
-                    "tdbem_assemble", "tdbem_get_entries", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
+                    "tdbem_assemble", "tdbem_get_entries", "tdbem_block_nnz", "tdbem_get_block_coo", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
                     "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
                     "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
 
 # preconditioner kinds of SolveOpts.precond_kind
-PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1 = 0, 1, 2
+PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1, PRECOND_DEFLATION = 0, 1, 2, 3
 
 
 class TdbemError(RuntimeError):
@@ -67,7 +67,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("tol", ctypes.c_double), ("max_it", ctypes.c_int32),
                 ("precond_levels", ctypes.c_int32), ("precond_inner", ctypes.c_int32 * 8),
                 ("progress", PROGRESS), ("progress_user", ctypes.c_void_p), ("precond_kind", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("deflation_l", ctypes.c_int32), ("deflation_max", ctypes.c_int32),
+                ("inner_fp32", ctypes.c_int32)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -114,7 +115,9 @@ def load_library(path=LIB_PATH):
     L.tdbem_last_error.argtypes = [vp]
     L.tdbem_last_error.restype = ctypes.c_char_p
     L.tdbem_set_mesh.argtypes = [vp, P(dp), i64, P(i32), i64]
-    L.tdbem_set_time_grid.argtypes = [vp, P(dp), i32, ctypes.c_int]
+    L.tdbem_set_time_grid.argtypes = [vp, P(dp), i32, ctypes.c_int, i32]
+    L.tdbem_block_nnz.argtypes = [vp, i32, i32, P(i64)]
+    L.tdbem_get_block_coo.argtypes = [vp, i32, i32, P(i32), P(i32), P(dp), i64]
     L.tdbem_assemble.argtypes = [vp, ctypes.c_int, P(AssemblyReport)]
     L.tdbem_get_entries.argtypes = [vp, i64, P(i32), P(i32), P(i32), P(i32), P(dp)]
     L.tdbem_eval_kernels.argtypes = [vp, i64, P(i32), P(i32), P(dp), P(dp), P(dp)]
@@ -211,11 +214,23 @@ class Context:
         self._check(self.lib.tdbem_set_mesh(self.h, _dptr(xyz), xyz.shape[0], _iptr(tri), tri.shape[0]))
         self.M, self.E = xyz.shape[0], tri.shape[0]
 
-    def set_time_grid(self, t, cutoff="bump"):
+    def set_time_grid(self, t, cutoff="bump", p=0):
         t = np.ascontiguousarray(t, dtype=np.float64)
         c = {"bump": CUTOFF_BUMP, "erf": CUTOFF_ERF}[cutoff] if isinstance(cutoff, str) else int(cutoff)
-        self._check(self.lib.tdbem_set_time_grid(self.h, _dptr(t), len(t), c))
-        self.N = len(t)
+        self._check(self.lib.tdbem_set_time_grid(self.h, _dptr(t), len(t), c, int(p)))
+        self.N = len(t) * (int(p) + 1)          # temporal bases L = N (p + 1)
+
+    def block_nnz(self, k, i):
+        n = ctypes.c_int64()
+        self._check(self.lib.tdbem_block_nnz(self.h, int(k), int(i), ctypes.byref(n)))
+        return n.value
+
+    def get_block_coo(self, k, i):
+        """Block A_{k,i} as (row l, column j, value) arrays sorted by (row, column)."""
+        n = self.block_nnz(k, i)
+        row = np.zeros(n, dtype=np.int32); col = np.zeros(n, dtype=np.int32); val = np.zeros(n)
+        self._check(self.lib.tdbem_get_block_coo(self.h, int(k), int(i), _iptr(row), _iptr(col), _dptr(val), n))
+        return row, col, val
 
     def assemble(self, precision=FP64):
         rep = AssemblyReport()
@@ -273,13 +288,15 @@ class Context:
         return y, rep.as_dict()
 
     def solve(self, g, tol=1e-8, restart=30, max_it=10000, precond_inner=(), out=None, progress=None,
-              precond_kind=PRECOND_ALG1, use_graph=False):
+              precond_kind=PRECOND_ALG1, use_graph=False, deflation=None, inner_fp32=False):
         """FGMRES(restart) from 0 to ||g - A alpha|| <= tol ||g||, with Algorithm 1 when
         precond_inner lists inner iterations per level (e.g. (2, 10)); progress(iteration,
         estimate) is called after every outer iteration when given.  precond_kind selects the
         learned network (PRECOND_LEARNED) or the network for the first restart cycle and
         Algorithm 1 afterwards (PRECOND_LEARNED_THEN_ALG1); use_graph replays the learned
-        iteration's preconditioned operator as one captured HIP graph."""
+        iteration's preconditioned operator as one captured HIP graph.  deflation = (l, r_max)
+        runs DGMRES(restart, l) with at most r_max deflation vectors (PRECOND_DEFLATION); inner_fp32
+        runs Algorithm 1's products on an FP32 copy of the FP64 band."""
         n = self.N * self.M
         alpha = self._vec() if out is None else out
         o = SolveOpts()
@@ -291,6 +308,10 @@ class Context:
         o.progress = cb
         o.precond_kind = int(precond_kind)
         o.use_graph = 1 if use_graph else 0
+        o.inner_fp32 = 1 if inner_fp32 else 0
+        if deflation is not None:
+            o.precond_kind = PRECOND_DEFLATION
+            o.deflation_l, o.deflation_max = int(deflation[0]), int(deflation[1])
         rep = SolveReport()
         st = self._check(self.lib.tdbem_solve(self.h, self._dev(g, n), self._dev(alpha, n), ctypes.byref(o),
                                               ctypes.byref(rep)))

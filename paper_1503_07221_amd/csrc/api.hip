@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -152,7 +153,8 @@ struct tdbem_ctx {
     int ss_order = 4;
     std::string err;
 
-    int M = 0, E = 0, N = 0, cut = 0;
+    int M = 0, E = 0, N = 0, cut = 0;   // N: temporal bases L = nodes (p + 1)
+    int nodes = 0, p1 = 1;              // time nodes, bases per node (p + 1)
     std::vector<double> xyz, t;
     std::vector<int32_t> tri;
     double diam = 0.0;
@@ -184,6 +186,18 @@ struct tdbem_ctx {
         int64_t n = 0;
     };
     std::vector<Level> levels;
+    // FP32 copy of the FP64 band for the preconditioner's inner products (inner_fp32)
+    DBuf d_val32;
+    uint64_t val32_assembly = ~0ull;
+    // DGMRES deflation space of the outer solve: U (orthonormal columns), A U, T^{-1} = (U^T A U)^{-1}
+    // on the host, |lambda_max| estimate
+    struct Deflation {
+        DBuf U, AU, coef;
+        int r = 0, rmax = 0;
+        int64_t n = 0;
+        std::vector<double> T, Tinv;
+        double lam = 1.0;
+    } defl;
     int64_t matvecs = 0;
     // learned preconditioner: parameters (float32 master, bfloat16 copy, Adam moments), the graph
     // of the current mesh and grid, workspaces
@@ -235,6 +249,8 @@ struct tdbem_ctx {
         tv.meta = d_meta.as<double4>();
         tv.cell = d_cell.as<uint16_t>();
         tv.N = N;
+        tv.nodes = nodes;
+        tv.p1 = p1;
         tv.pt = pieces;
         return tv;
     }
@@ -248,6 +264,8 @@ struct tdbem_ctx {
         b.N = N;
         const int64_t T = ((int64_t)M + kBT - 1) / kBT;
         b.nt = T * (T + 1) / 2;
+        b.nodes = nodes;
+        b.p1 = p1;
         return b;
     }
     const double* valf64() const { return prec == TDBEM_FP64 ? d_val.as<double>() : nullptr; }
@@ -489,13 +507,15 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     return TDBEM_OK;
 }
 
-tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem_cutoff cutoff)
+tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem_cutoff cutoff, int32_t p)
 {
     if (!c) return TDBEM_EINVAL;
     c->err.clear();
     if (!t) FAIL(c, TDBEM_EINVAL, "null time grid");
+    if (p < 0 || p > 4) FAIL(c, TDBEM_EINVAL, "temporal order p = %d outside 0..4", p);
     if (cutoff != TDBEM_CUTOFF_BUMP && cutoff != TDBEM_CUTOFF_ERF) FAIL(c, TDBEM_EINVAL, "unknown cutoff %d", (int)cutoff);
     if (N < 2 || N > 4096) FAIL(c, TDBEM_EGRID, "need 2 <= N <= 4096 time nodes, got %d", N);
+    if ((int64_t)N * (p + 1) > 8192) FAIL(c, TDBEM_EINVAL, "N (p + 1) = %d temporal bases exceed 8192", N * (p + 1));
     if (t[0] != 0.0) FAIL(c, TDBEM_EGRID, "t_0 must be 0");
     for (int s = 0; s < N; ++s)
         if (!std::isfinite(t[s])) FAIL(c, TDBEM_EGRID, "t_%d is not finite", s);
@@ -504,7 +524,9 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem
     TRY(set_device(c));
     c->assembled = false;
     c->have_grid = false;
-    c->N = N;
+    c->nodes = N;
+    c->p1 = p + 1;
+    c->N = N * (p + 1);
     c->cut = (int)cutoff;
     c->t.assign(t, t + N);
     TRY(upload(c, c->d_t, c->t.data(), c->t.size()));
@@ -519,7 +541,7 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem
 // ---------------------------------------------------------------------------------------------
 static tdbem_status build_tables(tdbem_ctx* c)
 {
-    const int N = c->N;
+    const int N = c->N, nodes = c->nodes, p1 = c->p1;     // N: temporal bases
     const double* t = c->t.data();
     const double rcap = c->diam * (1.0 + 1e-9) + 1e-12;
     std::vector<KernelDesc> desc;
@@ -532,18 +554,19 @@ static tdbem_status build_tables(tdbem_ctx* c)
     for (int k = 0; k < N; ++k)
         for (int i = 0; i < N; ++i) {
             double lo, hi;
-            kernel_support(t, N, k, i, lo, hi);
+            kernel_support(t, nodes, p1, k, i, lo, hi);
             if (!(hi > lo) || !(lo < rcap)) continue;
             // node differences t_c - t_a inside the support split it into analytic intervals
             std::vector<double> bp{lo};
-            for (int cc = k - 1; cc <= k + 1; ++cc)
-                for (int a = i - 1; a <= i + 1; ++a) {
-                    if (cc < 0 || cc >= N || a < 0 || a >= N) continue;
+            const int kn = k / p1, in = i / p1;
+            for (int cc = kn - 1; cc <= kn + 1; ++cc)
+                for (int a = in - 1; a <= in + 1; ++a) {
+                    if (cc < 0 || cc >= nodes || a < 0 || a >= nodes) continue;
                     const double d = t[cc] - t[a];
                     if (d > lo && d < hi) bp.push_back(d);
                 }
             std::sort(bp.begin(), bp.end());
-            const double tol = 1e-13 * (1.0 + t[N - 1]);
+            const double tol = 1e-13 * (1.0 + t[nodes - 1]);
             std::vector<double> uniq;
             for (double b : bp)
                 if (uniq.empty() || b - uniq.back() > tol) uniq.push_back(b);
@@ -611,7 +634,7 @@ static tdbem_status build_tables(tdbem_ctx* c)
     ALLOC(c, d_values, sizeof(double2) * (size_t)npieces * kNc);
     ALLOC(c, c->d_coef, sizeof(double2) * (size_t)npieces * kNc);
     ALLOC(c, c->d_coef32, sizeof(float2) * (size_t)npieces * kNc);
-    launch_table_values(c->d_t.as<double>(), N, c->cut, c->rule, c->pieces, d_pcf.as<int32_t>(), d_pcj.as<int32_t>(),
+    launch_table_values(c->d_t.as<double>(), nodes, p1, c->cut, c->rule, c->pieces, d_pcf.as<int32_t>(), d_pcj.as<int32_t>(),
                         d_pcp.as<int32_t>(), npieces, c->d_fk.as<int32_t>(), c->d_fi.as<int32_t>(),
                         c->d_desc.as<KernelDesc>(), c->d_ivl.as<double>(), d_values.as<double2>(), c->stream);
     HIPCHK(c, hipGetLastError());
@@ -826,6 +849,69 @@ tdbem_status tdbem_get_entries(tdbem_ctx* c, int64_t n, const int32_t* k, const 
     return TDBEM_OK;
 }
 
+static tdbem_status block_coo(tdbem_ctx* c, int32_t k, int32_t i, int32_t* row, int32_t* col, double* val,
+                              int64_t cap, int64_t* nnz)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before reading blocks");
+    if (k < 0 || k >= c->N || i < 0 || i >= c->N) FAIL(c, TDBEM_EINVAL, "block (%d, %d) outside 0..%d", k, i, c->N - 1);
+    TRY(set_device(c));
+    DBuf dcount;
+    ALLOC(c, dcount, sizeof(unsigned long long));
+    HIPCHK(c, hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), c->stream));
+    launch_block_coo(c->band(), c->valf64(), c->valf32(), k, i, dcount.as<unsigned long long>(), nullptr, nullptr,
+                     nullptr, 0, c->stream);
+    HIPCHK(c, hipGetLastError());
+    unsigned long long cnt = 0;
+    HIPCHK(c, hipMemcpyAsync(&cnt, dcount.p, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *nnz = (int64_t)cnt;
+    if (!row) return TDBEM_OK;
+    if ((int64_t)cnt > cap) FAIL(c, TDBEM_EINVAL, "block (%d, %d) has %llu entries, capacity %lld", k, i, cnt, (long long)cap);
+    if (cnt == 0) return TDBEM_OK;
+    DBuf drow, dcol, dval;
+    ALLOC(c, drow, sizeof(int32_t) * cnt);
+    ALLOC(c, dcol, sizeof(int32_t) * cnt);
+    ALLOC(c, dval, sizeof(double) * cnt);
+    HIPCHK(c, hipMemsetAsync(dcount.p, 0, sizeof(unsigned long long), c->stream));
+    launch_block_coo(c->band(), c->valf64(), c->valf32(), k, i, dcount.as<unsigned long long>(), drow.as<int32_t>(),
+                     dcol.as<int32_t>(), dval.as<double>(), (int64_t)cnt, c->stream);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int32_t> r(cnt), cl(cnt);
+    std::vector<double> v(cnt);
+    HIPCHK(c, hipMemcpyAsync(r.data(), drow.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cl.data(), dcol.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(v.data(), dval.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the kernel's positions depend on the order of its atomics: sort by (row, column)
+    std::vector<int64_t> ord(cnt);
+    for (int64_t s = 0; s < (int64_t)cnt; ++s) ord[s] = s;
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return r[a] != r[b] ? r[a] < r[b] : cl[a] < cl[b]; });
+    for (int64_t s = 0; s < (int64_t)cnt; ++s) {
+        row[s] = r[ord[s]];
+        col[s] = cl[ord[s]];
+        val[s] = v[ord[s]];
+    }
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_block_nnz(tdbem_ctx* c, int32_t k, int32_t i, int64_t* nnz)
+{
+    if (!c) return TDBEM_EINVAL;
+    if (!nnz) { c->err = "null nnz"; return TDBEM_EINVAL; }
+    return block_coo(c, k, i, nullptr, nullptr, nullptr, 0, nnz);
+}
+
+tdbem_status tdbem_get_block_coo(tdbem_ctx* c, int32_t k, int32_t i, int32_t* row, int32_t* col, double* val,
+                                 int64_t cap)
+{
+    if (!c) return TDBEM_EINVAL;
+    if (!row || !col || !val || cap < 0) { c->err = "null output or negative capacity"; return TDBEM_EINVAL; }
+    int64_t nnz = 0;
+    return block_coo(c, k, i, row, col, val, cap, &nnz);
+}
+
 tdbem_status tdbem_eval_kernels(tdbem_ctx* c, int64_t n, const int32_t* k, const int32_t* i, const double* r,
                                 double* psi, double* tpsi)
 {
@@ -858,7 +944,8 @@ tdbem_status tdbem_rhs_plane_pulse(tdbem_ctx* c, const double d[3], double t0, d
     if (!(width > 0.0) || !std::isfinite(t0)) FAIL(c, TDBEM_EINVAL, "pulse width must be > 0 and t0 finite");
     if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
     TRY(set_device(c));
-    launch_rhs(c->geom(), c->d_t.as<double>(), c->N, c->cut, c->rule, d[0], d[1], d[2], t0, width, c->M, g, c->stream);
+    launch_rhs(c->geom(), c->d_t.as<double>(), c->nodes, c->p1, c->cut, c->rule, d[0], d[1], d[2], t0, width, c->M, g,
+               c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return TDBEM_OK;
@@ -912,6 +999,7 @@ uint64_t host_splitmix64(uint64_t x)
 tdbem_status lp_graph(tdbem_ctx* c)
 {
     if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
+    if (c->p1 != 1) FAIL(c, TDBEM_EINVAL, "the learned preconditioner is implemented for p = 0");
     tdbem_ctx::Learned& L = c->lp;
     if (L.gver == c->graph_version) return TDBEM_OK;
     std::vector<std::vector<int32_t>> nb(c->M);
@@ -1305,6 +1393,180 @@ tdbem_status tdbem_lp_train(tdbem_ctx* c, const tdbem_lp_train_opts* o, float* l
 // ---------------------------------------------------------------------------------------------
 namespace {
 
+// ---------------------------------------------------------------------------------------------
+// DGMRES(m, l) (Section 4.1): deflation of the smallest eigenvalues.  The cycle's Hessenberg
+// matrix is small (k <= restart), so its eigenvalues are found on the host by the complex QR
+// algorithm with Wilkinson shifts, and eigenvectors by inverse iteration.
+// ---------------------------------------------------------------------------------------------
+using cplx = std::complex<double>;
+
+// Eigenvalues of the k x k upper Hessenberg matrix H (row-major, leading dimension ld).
+std::vector<cplx> hessenberg_eigenvalues(const std::vector<double>& H, int k, int ld)
+{
+    std::vector<cplx> A((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = j >= i - 1 ? H[(size_t)i * ld + j] : 0.0;
+    auto at = [&](int i, int j) -> cplx& { return A[(size_t)i * k + j]; };
+    std::vector<cplx> ev(k);
+    int hi = k - 1, iter = 0;
+    while (hi >= 0) {
+        if (hi == 0) { ev[0] = at(0, 0); break; }
+        int lo = hi;
+        while (lo > 0 && std::abs(at(lo, lo - 1)) > 1e-15 * (std::abs(at(lo - 1, lo - 1)) + std::abs(at(lo, lo)))) --lo;
+        if (lo == hi) { ev[hi] = at(hi, hi); --hi; iter = 0; continue; }
+        if (iter > 200 * k) { for (int s = lo; s <= hi; ++s) ev[s] = at(s, s); hi = lo - 1; continue; }
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block closer to its last entry
+        const cplx a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+        const cplx tr = a + d, det = a * d - b * c, disc = std::sqrt(tr * tr * 0.25 - det);
+        const cplx m1 = tr * 0.5 + disc, m2 = tr * 0.5 - disc;
+        cplx mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+        if (iter % 11 == 10) mu = d + std::abs(c);               // exceptional shift
+        ++iter;
+        for (int s = lo; s <= hi; ++s) at(s, s) -= mu;
+        std::vector<cplx> gc(hi - lo), gs(hi - lo);
+        for (int j = lo; j < hi; ++j) {                          // R = G^H (A - mu I) row by row
+            const cplx x = at(j, j), y = at(j + 1, j);
+            const double rr = std::sqrt(std::norm(x) + std::norm(y));
+            const cplx cc = rr > 0.0 ? x / rr : 1.0, ss = rr > 0.0 ? y / rr : 0.0;
+            gc[j - lo] = cc;
+            gs[j - lo] = ss;
+            for (int q = j; q <= hi; ++q) {
+                const cplx u = at(j, q), v = at(j + 1, q);
+                at(j, q) = std::conj(cc) * u + std::conj(ss) * v;
+                at(j + 1, q) = -ss * u + cc * v;
+            }
+        }
+        for (int j = lo; j < hi; ++j) {                          // R Q, Q = prod G_j
+            const cplx cc = gc[j - lo], ss = gs[j - lo];
+            for (int q = lo; q <= std::min(j + 2, hi); ++q) {
+                const cplx u = at(q, j), v = at(q, j + 1);
+                at(q, j) = cc * u + ss * v;
+                at(q, j + 1) = -std::conj(ss) * u + std::conj(cc) * v;
+            }
+        }
+        for (int s = lo; s <= hi; ++s) at(s, s) += mu;
+    }
+    return ev;
+}
+
+// An eigenvector of H (k x k, leading dimension ld) for the eigenvalue lam: two steps of inverse
+// iteration with a slightly perturbed shift (Gaussian elimination with partial pivoting).
+std::vector<cplx> hessenberg_eigenvector(const std::vector<double>& H, int k, int ld, cplx lam)
+{
+    const double scale = std::max(1.0, std::abs(lam));
+    const cplx shift = lam + cplx(1e-10 * scale, 1e-10 * scale);
+    std::vector<cplx> A((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = (j >= i - 1 ? H[(size_t)i * ld + j] : 0.0) - (i == j ? shift : 0.0);
+    std::vector<int> piv(k);
+    for (int j = 0; j < k; ++j) {
+        int pr = j;
+        for (int i = j + 1; i < k; ++i)
+            if (std::abs(A[(size_t)i * k + j]) > std::abs(A[(size_t)pr * k + j])) pr = i;
+        piv[j] = pr;
+        if (pr != j)
+            for (int q = 0; q < k; ++q) std::swap(A[(size_t)j * k + q], A[(size_t)pr * k + q]);
+        if (std::abs(A[(size_t)j * k + j]) == 0.0) A[(size_t)j * k + j] = 1e-300;
+        for (int i = j + 1; i < k; ++i) {
+            const cplx f = A[(size_t)i * k + j] / A[(size_t)j * k + j];
+            A[(size_t)i * k + j] = f;
+            for (int q = j + 1; q < k; ++q) A[(size_t)i * k + q] -= f * A[(size_t)j * k + q];
+        }
+    }
+    std::vector<cplx> y(k, cplx(1.0, 0.5));
+    for (int step = 0; step < 2; ++step) {
+        for (int j = 0; j < k; ++j) {
+            std::swap(y[j], y[piv[j]]);
+            for (int i = j + 1; i < k; ++i) y[i] -= A[(size_t)i * k + j] * y[j];
+        }
+        for (int j = k - 1; j >= 0; --j) {
+            for (int q = j + 1; q < k; ++q) y[j] -= A[(size_t)j * k + q] * y[q];
+            y[j] /= A[(size_t)j * k + j];
+        }
+        double nrm = 0.0;
+        for (const cplx& v : y) nrm += std::norm(v);
+        nrm = std::sqrt(nrm);
+        for (cplx& v : y) v /= nrm;
+    }
+    return y;
+}
+
+// Real orthonormal basis (k x cols, column-major) of the invariant subspace of the eigenvalues of
+// smallest modulus (l of them, l + 1 when a complex pair would be split), and the largest modulus.
+std::vector<double> smallest_invariant_basis(const std::vector<double>& H, int k, int ld, int l, int* cols,
+                                             double* lam_max)
+{
+    std::vector<cplx> ev = hessenberg_eigenvalues(H, k, ld);
+    std::vector<int> order(k);
+    for (int s = 0; s < k; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::abs(ev[a]) < std::abs(ev[b]); });
+    *lam_max = 0.0;
+    for (const cplx& v : ev) *lam_max = std::max(*lam_max, std::abs(v));
+    std::vector<std::vector<double>> vecs;
+    int taken = 0;
+    for (int idx : order) {
+        if (taken >= l) break;
+        const cplx lam = ev[idx];
+        if (std::fabs(lam.imag()) > 1e-12 * std::max(1.0, std::abs(lam))) {
+            if (lam.imag() < 0.0) continue;                      // the partner with Im > 0 gives the pair
+            std::vector<cplx> y = hessenberg_eigenvector(H, k, ld, lam);
+            std::vector<double> re(k), im(k);
+            for (int s = 0; s < k; ++s) { re[s] = y[s].real(); im[s] = y[s].imag(); }
+            vecs.push_back(re);
+            vecs.push_back(im);
+            taken += 2;
+        } else {
+            std::vector<cplx> y = hessenberg_eigenvector(H, k, ld, cplx(lam.real(), 0.0));
+            std::vector<double> re(k);
+            for (int s = 0; s < k; ++s) re[s] = y[s].real();
+            vecs.push_back(re);
+            taken += 1;
+        }
+    }
+    std::vector<double> Q;
+    for (auto& v : vecs) {                                       // modified Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t c0 = 0; c0 < Q.size() / k; ++c0) {
+                double d = 0.0;
+                for (int s = 0; s < k; ++s) d += Q[c0 * k + s] * v[s];
+                for (int s = 0; s < k; ++s) v[s] -= d * Q[c0 * k + s];
+            }
+        double nrm = 0.0;
+        for (double x : v) nrm += x * x;
+        nrm = std::sqrt(nrm);
+        if (nrm < 1e-10) continue;
+        for (double x : v) Q.push_back(x / nrm);
+    }
+    *cols = (int)(Q.size() / k);
+    return Q;
+}
+
+// Inverse of a small dense matrix (row-major) by Gauss-Jordan elimination with partial pivoting.
+bool small_inverse(std::vector<double> A, int r, std::vector<double>& inv)
+{
+    inv.assign((size_t)r * r, 0.0);
+    for (int s = 0; s < r; ++s) inv[(size_t)s * r + s] = 1.0;
+    for (int j = 0; j < r; ++j) {
+        int pr = j;
+        for (int i = j + 1; i < r; ++i)
+            if (std::fabs(A[(size_t)i * r + j]) > std::fabs(A[(size_t)pr * r + j])) pr = i;
+        if (A[(size_t)pr * r + j] == 0.0) return false;
+        for (int q = 0; q < r; ++q) {
+            std::swap(A[(size_t)j * r + q], A[(size_t)pr * r + q]);
+            std::swap(inv[(size_t)j * r + q], inv[(size_t)pr * r + q]);
+        }
+        const double d = A[(size_t)j * r + j];
+        for (int q = 0; q < r; ++q) { A[(size_t)j * r + q] /= d; inv[(size_t)j * r + q] /= d; }
+        for (int i = 0; i < r; ++i) {
+            if (i == j) continue;
+            const double f = A[(size_t)i * r + j];
+            if (f == 0.0) continue;
+            for (int q = 0; q < r; ++q) { A[(size_t)i * r + q] -= f * A[(size_t)j * r + q]; inv[(size_t)i * r + q] -= f * inv[(size_t)j * r + q]; }
+        }
+    }
+    return true;
+}
+
 struct SolveCtx {
     tdbem_ctx* c;
     double tol;
@@ -1313,10 +1575,25 @@ struct SolveCtx {
     const int32_t* inner;
     void (*progress)(int32_t, double, void*);
     void* progress_user;
-    int kind;               // 0: Algorithm 1 / none, 1: learned network, 2: learned, then Algorithm 1
+    int kind;               // 0: Algorithm 1 / none, 1: learned network, 2: learned, then Algorithm 1,
+                            // 3: deflation (DGMRES)
+    int defl_l;             // DGMRES: vectors added to the deflation space after each restart
     bool learned_active;    // the outer iteration currently uses the learned network
     bool graph;             // the learned iteration replays the captured z = P(v), w = A z
+    bool inner32;           // Algorithm 1's inner products read the FP32 copy of the band
 };
+
+// Block product inside the solver: the outer iteration (depth 0) uses the assembled operator; the
+// preconditioner's products (depth >= 1) the FP32 copy when inner32 is set.
+tdbem_status solver_matvec(SolveCtx& S, int depth, int k0, int k1, int i0, int i1, const double* x, double* y)
+{
+    tdbem_ctx* c = S.c;
+    if (!(S.inner32 && depth >= 1)) return matvec_range(c, k0, k1, i0, i1, x, y);
+    launch_matvec(c->band(), nullptr, c->d_val32.as<float>(), k0, k1, i0, i1, x, y, c->stream);
+    HIPCHK(c, hipGetLastError());
+    ++c->matvecs;
+    return TDBEM_OK;
+}
 
 tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
                     int* its_out, double* rel_out);
@@ -1327,7 +1604,8 @@ tdbem_status apply_precond(SolveCtx& S, int depth, int level, int a, int b, cons
 {
     tdbem_ctx* c = S.c;
     const int64_t M = c->M;
-    const int h = a + (b - a + 1) / 2;
+    const int p1 = c->p1;                          // split between the node groups of p + 1 bases
+    const int h = a + ((b - a) / p1 + 1) / 2 * p1;
     const int m_it = S.inner[level - 1];
     int its;
     double rel;
@@ -1335,10 +1613,88 @@ tdbem_status apply_precond(SolveCtx& S, int depth, int level, int a, int b, cons
     if (b > h) {
         tdbem_ctx::Level& L = c->levels[depth];
         double* tmp = L.tmp.as<double>();
-        TRY(matvec_range(c, h, b, a, h, y, tmp));                                    // M21 y1
+        TRY(solver_matvec(S, depth, h, b, a, h, y, tmp));                             // M21 y1
         launch_axpby(tmp, v + (int64_t)(h - a) * M, 1.0, -1.0, (int64_t)(b - h) * M, c->stream);   // v2 - M21 y1
         HIPCHK(c, hipGetLastError());
         TRY(fgmres(S, depth, h, b, tmp, y + (int64_t)(h - a) * M, m_it, true, &its, &rel));
+    }
+    return TDBEM_OK;
+}
+
+// z = M^{-1} v = v + U (|lambda| T^{-1} - I) U^T v (Section 4.1) for the outer solve.
+tdbem_status apply_deflation(SolveCtx& S, const double* v, double* z, int64_t n, double* part)
+{
+    tdbem_ctx* c = S.c;
+    tdbem_ctx::Deflation& D = c->defl;
+    hipStream_t st = c->stream;
+    launch_scale_copy(z, v, 1.0, n, st);
+    if (D.r == 0) return TDBEM_OK;
+    double* dc = D.coef.as<double>();
+    launch_dots(D.U.as<double>(), D.r, n, n, v, part, dc, st);
+    std::vector<double> cv(D.r), d(D.r);
+    HIPCHK(c, hipMemcpyAsync(cv.data(), dc, sizeof(double) * D.r, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int a = 0; a < D.r; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < D.r; ++b) s += D.Tinv[(size_t)a * D.r + b] * cv[b];
+        d[a] = D.lam * s - cv[a];
+    }
+    HIPCHK(c, hipMemcpyAsync(dc, d.data(), sizeof(double) * D.r, hipMemcpyHostToDevice, st));
+    launch_sub_combination(z, D.U.as<double>(), D.r, n, n, dc, 1.0, st);
+    HIPCHK(c, hipGetLastError());
+    return TDBEM_OK;
+}
+
+// After a restart cycle of the outer DGMRES: append the basis V_k S of the invariant subspace of
+// the cycle's Hessenberg matrix for its l smallest eigenvalues to U (orthonormalised against U,
+// classical Gram-Schmidt twice), with A U and T = U^T A U; |lambda| = the largest eigenvalue
+// modulus seen.
+tdbem_status update_deflation(SolveCtx& S, const std::vector<double>& Hraw, int k, int ld, const double* V,
+                              int64_t n, double* part)
+{
+    tdbem_ctx* c = S.c;
+    tdbem_ctx::Deflation& D = c->defl;
+    hipStream_t st = c->stream;
+    if (D.r >= D.rmax || k < 2) return TDBEM_OK;
+    int cols = 0;
+    double lam_max = 0.0;
+    const std::vector<double> Sb = smallest_invariant_basis(Hraw, k, ld, std::min(S.defl_l, D.rmax - D.r), &cols, &lam_max);
+    D.lam = std::max(D.r > 0 ? D.lam : 0.0, lam_max);
+    double* dc = D.coef.as<double>();
+    for (int col = 0; col < cols && D.r < D.rmax; ++col) {
+        double* u = D.U.as<double>() + (int64_t)D.r * n;
+        HIPCHK(c, hipMemcpyAsync(dc, Sb.data() + (size_t)col * k, sizeof(double) * k, hipMemcpyHostToDevice, st));
+        launch_fill(u, 0.0, n, st);
+        launch_sub_combination(u, V, k, n, n, dc, 1.0, st);
+        for (int pass = 0; pass < 2 && D.r > 0; ++pass) {
+            launch_dots(D.U.as<double>(), D.r, n, n, u, part, dc, st);
+            launch_sub_combination(u, D.U.as<double>(), D.r, n, n, dc, -1.0, st);
+        }
+        launch_dots(u, 1, n, n, u, part, dc, st);
+        double nn = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&nn, dc, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (!(nn > 1e-20)) continue;                              // already in the span of U
+        launch_scale_copy(u, u, 1.0 / std::sqrt(nn), n, st);
+        double* au = D.AU.as<double>() + (int64_t)D.r * n;
+        TRY(matvec_range(c, 0, c->N, 0, c->N, u, au));
+        const int r1 = D.r + 1;
+        std::vector<double> colv(r1), rowv(r1);
+        launch_dots(D.U.as<double>(), r1, n, n, au, part, dc, st);          // u_a^T A u_new
+        HIPCHK(c, hipMemcpyAsync(colv.data(), dc, sizeof(double) * r1, hipMemcpyDeviceToHost, st));
+        launch_dots(D.AU.as<double>(), r1, n, n, u, part, dc, st);          // u_new^T A u_b
+        HIPCHK(c, hipMemcpyAsync(rowv.data(), dc, sizeof(double) * r1, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        std::vector<double> T((size_t)r1 * r1);
+        for (int a = 0; a < D.r; ++a)
+            for (int b = 0; b < D.r; ++b) T[(size_t)a * r1 + b] = D.T[(size_t)a * D.r + b];
+        for (int a = 0; a < r1; ++a) T[(size_t)a * r1 + D.r] = colv[a];
+        for (int b = 0; b < D.r; ++b) T[(size_t)D.r * r1 + b] = rowv[b];
+        std::vector<double> Ti;
+        if (!small_inverse(T, r1, Ti)) continue;                   // singular T: drop the vector
+        D.T.swap(T);
+        D.Tinv.swap(Ti);
+        D.r = r1;
     }
     return TDBEM_OK;
 }
@@ -1353,7 +1709,7 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
     hipStream_t st = c->stream;
     const int64_t n = (int64_t)(b - a) * c->M;
     tdbem_ctx::Level& L = c->levels[depth];
-    const bool alg1 = depth < S.levels && (b - a) > 1;
+    const bool alg1 = depth < S.levels && (b - a) > c->p1;
     const bool precond = alg1 || (depth == 0 && S.kind != 0);
     const int m = inner ? max_it : std::min(S.restart, max_it);
     double* V = L.V.as<double>();
@@ -1377,6 +1733,8 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
     double* wres = L.w.as<double>();
     int its = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), hbuf(2 * (m + 1) + 1);
+    const bool deflate = depth == 0 && S.kind == 3;
+    std::vector<double> Hraw(deflate ? (size_t)(m + 1) * m : 0);   // the cycle's Hessenberg matrix, unrotated
     while (true) {
         const int mm = inner ? max_it - its : std::min(m, max_it - its);
         if (mm <= 0 || beta <= S.tol * bnorm) break;
@@ -1399,9 +1757,10 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
                 ++c->matvecs;
             } else {
                 if (depth == 0 && S.learned_active) TRY(lp_apply(c, vj, zj));
+                else if (deflate) TRY(apply_deflation(S, vj, zj, n, part));
                 else if (alg1) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
                 else if (precond) launch_scale_copy(zj, vj, 1.0, n, st);
-                TRY(matvec_range(c, a, b, a, b, zj, w));
+                TRY(solver_matvec(S, depth, a, b, a, b, zj, w));
             }
             // classical Gram-Schmidt, twice
             launch_dots(V, j + 1, n, n, w, part, dbuf, st);
@@ -1416,6 +1775,9 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
             for (int q = 0; q <= j; ++q) H[(size_t)q * m + j] = hbuf[q] + hbuf[m + 1 + q];
             const double hn = std::sqrt(std::max(hbuf[2 * (m + 1)], 0.0));
             H[(size_t)(j + 1) * m + j] = hn;
+            if (deflate) {
+                for (int q = 0; q <= j + 1; ++q) Hraw[(size_t)q * m + j] = H[(size_t)q * m + j];
+            }
             for (int q = 0; q < j; ++q) {
                 const double t1 = cs[q] * H[(size_t)q * m + j] + sn[q] * H[(size_t)(q + 1) * m + j];
                 H[(size_t)(q + 1) * m + j] = -sn[q] * H[(size_t)q * m + j] + cs[q] * H[(size_t)(q + 1) * m + j];
@@ -1459,6 +1821,7 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
         (void)done;
         if (depth == 0 && S.kind == 2) S.learned_active = false;   // fall back to Algorithm 1
         if (beta <= S.tol * bnorm || its >= max_it) break;
+        if (deflate) TRY(update_deflation(S, Hraw, jdone, m, V, n, part));
     }
     *its_out = its;
     *rel_out = beta / bnorm;
@@ -1479,16 +1842,44 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
         FAIL(c, TDBEM_EINVAL, "bad solver options");
     for (int s = 0; s < o->precond_levels; ++s)
         if (o->precond_inner[s] < 1 || o->precond_inner[s] > 1000) FAIL(c, TDBEM_EINVAL, "bad inner iteration count");
-    if (o->precond_kind < 0 || o->precond_kind > 2) FAIL(c, TDBEM_EINVAL, "unknown preconditioner kind %d", o->precond_kind);
+    if (o->precond_kind < 0 || o->precond_kind > 3) FAIL(c, TDBEM_EINVAL, "unknown preconditioner kind %d", o->precond_kind);
+    if (o->precond_kind == 3 && (o->deflation_l < 1 || o->deflation_max < o->deflation_l || o->deflation_max > 256 ||
+                                 o->precond_levels != 0 || o->use_graph))
+        FAIL(c, TDBEM_EINVAL, "deflation needs 1 <= deflation_l <= deflation_max <= 256, no Algorithm 1 levels and no graph");
     if (o->precond_kind == 2 && o->precond_levels < 1)
         FAIL(c, TDBEM_EINVAL, "the learned-then-Algorithm-1 preconditioner needs precond_levels > 0");
     TRY(set_device(c));
     if (o->use_graph != 0 && o->use_graph != 1) FAIL(c, TDBEM_EINVAL, "use_graph must be 0 or 1");
     if (o->use_graph && o->precond_kind == 0)
         FAIL(c, TDBEM_EINVAL, "the captured iteration applies the learned preconditioner (precond_kind 1 or 2)");
-    if (o->precond_kind != 0) {
+    if (o->precond_kind == 1 || o->precond_kind == 2) {
         TRY(lp_need_params(c));
         TRY(lp_graph(c));
+    }
+    if (o->inner_fp32 != 0 && o->inner_fp32 != 1) FAIL(c, TDBEM_EINVAL, "inner_fp32 must be 0 or 1");
+    if (o->inner_fp32 && (c->prec != TDBEM_FP64 || o->precond_levels < 1 || o->precond_kind != 0))
+        FAIL(c, TDBEM_EINVAL, "inner_fp32 needs an FP64 assembly and Algorithm 1 (precond_levels > 0)");
+    if (o->inner_fp32 && c->val32_assembly != c->assemblies) {
+        const int64_t nv = std::max<int64_t>(c->nvals, 1);
+        ALLOC(c, c->d_val32, sizeof(float) * (size_t)nv);
+        launch_to_f32(c->d_val.as<double>(), c->d_val32.as<float>(), c->nvals, c->stream);
+        HIPCHK(c, hipGetLastError());
+        c->val32_assembly = c->assemblies;
+    }
+    if (o->precond_kind == 3) {
+        tdbem_ctx::Deflation& D = c->defl;
+        const int64_t n = (int64_t)c->N * c->M;
+        if (D.rmax < o->deflation_max || D.n != n) {
+            ALLOC(c, D.U, sizeof(double) * (size_t)o->deflation_max * n);
+            ALLOC(c, D.AU, sizeof(double) * (size_t)o->deflation_max * n);
+            ALLOC(c, D.coef, sizeof(double) * (size_t)std::max(o->deflation_max, o->restart) + 8);
+        }
+        D.rmax = o->deflation_max;
+        D.n = n;
+        D.r = 0;                                   // a fresh deflation space for every solve
+        D.T.clear();
+        D.Tinv.clear();
+        D.lam = 1.0;
     }
     if (o->use_graph) TRY(lp_operator_graph(c));
     const auto t_start = std::chrono::steady_clock::now();
@@ -1511,10 +1902,20 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
             L.m = m;
             L.n = n;
         }
-        blocks = (blocks + 1) / 2;
+        blocks = (blocks / c->p1 + 1) / 2 * c->p1;
     }
-    SolveCtx S{c, o->tol, o->restart, o->precond_levels, o->precond_inner, o->progress, o->progress_user,
-               o->precond_kind, o->precond_kind != 0, o->use_graph != 0};
+    SolveCtx S{c,
+               o->tol,
+               o->restart,
+               o->precond_levels,
+               o->precond_inner,
+               o->progress,
+               o->progress_user,
+               o->precond_kind,
+               o->precond_kind == 3 ? o->deflation_l : 0,
+               o->precond_kind == 1 || o->precond_kind == 2,
+               o->use_graph != 0,
+               o->inner_fp32 != 0};
     c->matvecs = 0;
     int its = 0;
     double rel = 0.0;
@@ -1548,6 +1949,7 @@ tdbem_status tdbem_potential_dl(tdbem_ctx* c, const double* alpha, int64_t npts,
     if (!alpha || !pts || !times || !u) FAIL(c, TDBEM_EINVAL, "null argument");
     if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid first");
     if (npts < 1 || ntimes < 1) FAIL(c, TDBEM_EINVAL, "need at least one point and one time");
+    if (c->p1 != 1) FAIL(c, TDBEM_EINVAL, "the field evaluation is implemented for p = 0");
     if (c->N > 1024) FAIL(c, TDBEM_EINVAL, "the field evaluation takes at most 1024 time nodes");
     const double T = c->t[c->N - 1];
     for (int s = 0; s < ntimes; ++s)

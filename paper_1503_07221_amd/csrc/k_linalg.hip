@@ -20,6 +20,13 @@ __device__ inline void rhs_rule7(int q, double& l0, double& l1, double& l2, doub
     }
 }
 
+// dst = (float) src: the FP32 copy of an FP64 band for the inner products of the preconditioner.
+__global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = (float)src[s];
+}
+
 __global__ void __launch_bounds__(256) k_fill(double* __restrict__ x, double v, int64_t n)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,18 +37,19 @@ __global__ void __launch_bounds__(256) k_fill(double* __restrict__ x, double v, 
 // G(s) = exp(-(s/w)^2): one lane per (k, tau); the time integral over supp b_k' is split at t_k
 // and graded dyadically towards the split points like the kernel quadrature.
 __global__ void __launch_bounds__(256)
-k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
-      double t0, double width, int M, double* __restrict__ gvec)
+k_rhs(GeomView g, const double* __restrict__ t, int N, int p1, int cut, TimeRule rule, double d0, double d1,
+      double d2, double t0, double width, int M, double* __restrict__ gvec)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int E = g.E;
-    if (gid >= (int64_t)N * E) return;
+    if (gid >= (int64_t)N * p1 * E) return;
     const int k = (int)(gid / E), e = (int)(gid - (int64_t)k * E);
+    const int kn = k / p1;                       // node of the test basis
     double pts[3];
     int np = 0;
-    pts[np++] = t[k > 0 ? k - 1 : 0];
-    if (k > 0 && k < N - 1) pts[np++] = t[k];
-    pts[np++] = t[k < N - 1 ? k + 1 : N - 1];
+    pts[np++] = t[kn > 0 ? kn - 1 : 0];
+    if (kn > 0 && kn < N - 1) pts[np++] = t[kn];
+    pts[np++] = t[kn < N - 1 ? kn + 1 : N - 1];
     const double dn = d0 * g.n[e] + d1 * g.n[E + e] + d2 * g.n[2 * E + e];
     const double iw2 = 1.0 / (width * width);
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
@@ -60,7 +68,7 @@ k_rhs(GeomView g, const double* __restrict__ t, int N, int cut, TimeRule rule, d
                     const double sa = tt - t0 - dx;
                     const double Gp = -2.0 * sa * iw2 * exp(-sa * sa * iw2);
                     double bv, b1, b2;
-                    basis_eval(t, N, cut, k, tt, bv, b1, b2);
+                    basis_eval(t, N, p1, cut, k, tt, bv, b1, b2);
                     ti = fma(half * rule.w[m] * Gp, b1, ti);
                 }
             }
@@ -298,12 +306,18 @@ void launch_fill(double* x, double v, int64_t n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, x, v, n);
 }
 
-void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2, double t0,
-                double width, int M, double* gvec, hipStream_t s)
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)N * M, 256)), dim3(256), 0, s, gvec, 0.0, (int64_t)N * M);
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for((int64_t)N * g.E, 256)), dim3(256), 0, s, g, t, N, cut, rule, d0, d1, d2,
-                       t0, width, M, gvec);
+    if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_rhs(GeomView g, const double* t, int N, int p1, int cut, TimeRule rule, double d0, double d1, double d2,
+                double t0, double width, int M, double* gvec, hipStream_t s)
+{
+    const int64_t L = (int64_t)N * p1;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(L * M, 256)), dim3(256), 0, s, gvec, 0.0, L * M);
+    hipLaunchKernelGGL(k_rhs, dim3(grid_for(L * g.E, 256)), dim3(256), 0, s, g, t, N, p1, cut, rule, d0, d1, d2, t0,
+                       width, M, gvec);
 }
 
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,

@@ -7,10 +7,11 @@ namespace tdbem {
 
 // Both kernels at r by Gauss-Legendre quadrature over t in supp b_k' cap (r + supp b_i), split at
 // every node t_k and every shifted node r + t_a and graded dyadically towards each split point.
-__device__ void kernels_by_quadrature(const double* t, int N, int cut, const TimeRule& rule,
-                                      int k, int i, double r, double& ps, double& pt)
+__device__ void kernels_by_quadrature(const double* t, int N, int p1, int cut, const TimeRule& rule,
+                                      int kb, int ib, double r, double& ps, double& pt)
 {
     ps = 0.0; pt = 0.0;
+    const int k = kb / p1, i = ib / p1;      // the nodes of the two bases
     double lo = t[k > 0 ? k - 1 : 0], hi = t[k < N - 1 ? k + 1 : N - 1];
     const double ilo = r + t[i > 0 ? i - 1 : 0];
     lo = lo > ilo ? lo : ilo;
@@ -45,8 +46,8 @@ __device__ void kernels_by_quadrature(const double* t, int N, int cut, const Tim
             for (int q = 0; q < kTimeGauss; ++q) {
                 const double tt = fma(half, rule.x[q], mid);
                 double bv, b1, b2, kv, k1, k2;
-                basis_eval(t, N, cut, i, tt - r, bv, b1, b2);
-                basis_eval(t, N, cut, k, tt, kv, k1, k2);
+                basis_eval(t, N, p1, cut, ib, tt - r, bv, b1, b2);
+                basis_eval(t, N, p1, cut, kb, tt, kv, k1, k2);
                 const double w = half * rule.w[q] * k1;
                 sp = fma(w, b2, sp);
                 st = fma(w, bv, st);
@@ -58,7 +59,7 @@ __device__ void kernels_by_quadrature(const double* t, int N, int cut, const Tim
 }
 
 __global__ void __launch_bounds__(256)
-k_table_values(const double* __restrict__ t, int N, int cut, TimeRule rule, PieceTable pt,
+k_table_values(const double* __restrict__ t, int N, int p1, int cut, TimeRule rule, PieceTable pt,
                const int32_t* __restrict__ pc_f, const int32_t* __restrict__ pc_j,
                const int32_t* __restrict__ pc_p, int64_t npieces, const int32_t* __restrict__ f_k,
                const int32_t* __restrict__ f_i, const KernelDesc* __restrict__ desc,
@@ -76,7 +77,7 @@ k_table_values(const double* __restrict__ t, int N, int cut, TimeRule rule, Piec
     const double fr = pt.edge[p] + 0.5 * (xm + 1.0) * (pt.edge[p + 1] - pt.edge[p]);
     const double r = start + fr * len;
     double ps, tps;
-    kernels_by_quadrature(t, N, cut, rule, f_k[f], f_i[f], r, ps, tps);
+    kernels_by_quadrature(t, N, p1, cut, rule, f_k[f], f_i[f], r, ps, tps);
     values[gid] = make_double2(ps, tps);
 }
 
@@ -121,13 +122,13 @@ k_table_eval(TableView tv, int64_t n, const int32_t* __restrict__ k, const int32
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-void launch_table_values(const double* t, int N, int cut, TimeRule rule, PieceTable pt, const int32_t* pc_f,
+void launch_table_values(const double* t, int N, int p1, int cut, TimeRule rule, PieceTable pt, const int32_t* pc_f,
                          const int32_t* pc_j, const int32_t* pc_p, int64_t npieces, const int32_t* f_k,
                          const int32_t* f_i, const KernelDesc* desc, const double* ivl, double2* values,
                          hipStream_t s)
 {
     if (npieces <= 0) return;
-    hipLaunchKernelGGL(k_table_values, dim3(grid_for(npieces * kNc, 256)), dim3(256), 0, s, t, N, cut, rule, pt,
+    hipLaunchKernelGGL(k_table_values, dim3(grid_for(npieces * kNc, 256)), dim3(256), 0, s, t, N, p1, cut, rule, pt,
                        pc_f, pc_j, pc_p, npieces, f_k, f_i, desc, ivl, values);
 }
 

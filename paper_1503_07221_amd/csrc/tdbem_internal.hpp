@@ -96,27 +96,31 @@ __host__ __device__ inline void cutoff_eval(int kind, double u, double& F, doubl
     }
 }
 
-// Temporal basis b_j with first and second derivative (Section 3, eq. (BasisFunctions), p = 0):
-// mu_j from the cutoff on [t_{j-1}, t_j] (rising) and [t_j, t_{j+1}] (falling), mu_{N-1} = 1 after
-// T, every basis 0 for negative arguments (causality), b_0 = 8 (t/h_1)^2 mu_0.
-__host__ __device__ inline void basis_eval(const double* t, int N, int cut, int j, double x,
+// Temporal basis b_j, j = n p1 + m (node n of the N nodes, Legendre degree m < p1 = p + 1), with
+// first and second derivative (Section 3, eq. (BasisFunctions)): mu_n from the cutoff on
+// [t_{n-1}, t_n] (rising) and [t_n, t_{n+1}] (falling), mu_{N-1} = 1 after T, every basis 0 for
+// negative arguments (causality), the causal factor 8 (t/h_1)^2 on node 0, times the Legendre
+// polynomial P_m of the support mapped onto [-1, 1]: [0, t_1] for n = 0, [t_{n-1}, t_{n+1}] for the
+// inner nodes (the paper's (t - t_n)/Delta t on equidistant grids), [t_{N-2}, T] for n = N - 1.
+__host__ __device__ inline void basis_eval(const double* t, int N, int p1, int cut, int j, double x,
                                            double& v, double& d1, double& d2)
 {
     v = 0.0; d1 = 0.0; d2 = 0.0;
     if (x < 0.0) return;
+    const int n = j / p1, m = j - n * p1;
     double F, F1, F2;
-    if (j > 0 && x > t[j - 1] && x <= t[j]) {
-        const double h = t[j] - t[j - 1], ih = 1.0 / h;
-        cutoff_eval(cut, (x - t[j - 1]) * ih, F, F1, F2);
+    if (n > 0 && x > t[n - 1] && x <= t[n]) {
+        const double h = t[n] - t[n - 1], ih = 1.0 / h;
+        cutoff_eval(cut, (x - t[n - 1]) * ih, F, F1, F2);
         v = F; d1 = F1 * ih; d2 = F2 * ih * ih;
-    } else if (j < N - 1 && x >= t[j] && x < t[j + 1]) {
-        const double h = t[j + 1] - t[j], ih = 1.0 / h;
-        cutoff_eval(cut, (x - t[j]) * ih, F, F1, F2);
+    } else if (n < N - 1 && x >= t[n] && x < t[n + 1]) {
+        const double h = t[n + 1] - t[n], ih = 1.0 / h;
+        cutoff_eval(cut, (x - t[n]) * ih, F, F1, F2);
         v = 1.0 - F; d1 = -F1 * ih; d2 = -F2 * ih * ih;
-    } else if (j == N - 1 && x > t[N - 1]) {
+    } else if (n == N - 1 && x > t[N - 1]) {
         v = 1.0;
     }
-    if (j == 0) {
+    if (n == 0) {
         if (x <= 0.0) { v = d1 = d2 = 0.0; return; }
         const double ih = 1.0 / (t[1] - t[0]);
         const double u = x * ih;
@@ -124,12 +128,28 @@ __host__ __device__ inline void basis_eval(const double* t, int N, int cut, int 
         const double nv = c * v, nd1 = c1 * v + c * d1, nd2 = c2 * v + 2.0 * c1 * d1 + c * d2;
         v = nv; d1 = nd1; d2 = nd2;
     }
+    if (m == 0) return;
+    const double lo = n == 0 ? 0.0 : t[n - 1];
+    const double hi = n == N - 1 ? t[N - 1] : (n == 0 ? t[1] : t[n + 1]);
+    const double a = 2.0 / (hi - lo), s = a * (x - lo) - 1.0;
+    // P_m, P_m', P_m'' by the three-term recurrence and P_q' = P_{q-2}' + (2q - 1) P_{q-1}
+    double p0 = 1.0, p0d = 0.0, p0dd = 0.0, q1 = s, q1d = 1.0, q1dd = 0.0;
+    for (int q = 2; q <= m; ++q) {
+        const double pv = ((2.0 * q - 1.0) * s * q1 - (q - 1.0) * p0) / q;
+        const double pd = p0d + (2.0 * q - 1.0) * q1;
+        const double pdd = p0dd + (2.0 * q - 1.0) * q1d;
+        p0 = q1; p0d = q1d; p0dd = q1dd;
+        q1 = pv; q1d = pd; q1dd = pdd;
+    }
+    const double nv = v * q1, nd1 = d1 * q1 + v * q1d * a, nd2 = d2 * q1 + 2.0 * d1 * q1d * a + v * q1dd * a * a;
+    v = nv; d1 = nd1; d2 = nd2;
 }
 
-// Open support of psi_{k,i} (Section 3.2): (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) cap r > 0 with
-// t_{-1} := 0 and t_N := T.
-__host__ __device__ inline void kernel_support(const double* t, int N, int k, int i, double& lo, double& hi)
+// Open support of psi_{k,i} (Section 3.2) for the bases k, i (nodes k / p1, i / p1):
+// (t_{k-1} - t_{i+1}, t_{k+1} - t_{i-1}) cap r > 0 with t_{-1} := 0 and t_N := T.
+__host__ __device__ inline void kernel_support(const double* t, int N, int p1, int kb, int ib, double& lo, double& hi)
 {
+    const int k = kb / p1, i = ib / p1;
     const double tkm = t[k > 0 ? k - 1 : 0], tkp = t[k < N - 1 ? k + 1 : N - 1];
     const double tim = t[i > 0 ? i - 1 : 0], tip = t[i < N - 1 ? i + 1 : N - 1];
     lo = tkm - tip > 0.0 ? tkm - tip : 0.0;
@@ -156,13 +176,14 @@ __device__ inline void clenshaw2(const double2* __restrict__ c, double x, double
 // Device-side table handle (passed by value as a kernel argument).
 struct TableView {
     const KernelDesc* desc;   // one per tabulated (k, i)
-    const int32_t* fid;       // fid[k*N + i]: index into desc or -1 (identically zero kernel)
+    const int32_t* fid;       // fid[k*N + i]: index into desc or -1 (identically zero kernel), N = L
     const double* ivl;        // interval starts and inverse lengths
     const double2* coef;      // Chebyshev coefficients (psi, tpsi)
     const float2* coef32;     // the same rounded to FP32 (mixed precision far field)
     const double4* meta;      // per-piece record (rhi, rc, ra, near)
     const uint16_t* cell;     // cell table
-    int32_t N;
+    int32_t N;                // temporal bases L = nodes (p + 1)
+    int32_t nodes, p1;        // time nodes and bases per node
     PieceTable pt;
 };
 
@@ -255,8 +276,9 @@ struct BandView {
     const int16_t* ilo;    // first trial index of every (k, l, j <= l), tiled as above
     const int32_t* B;      // B[k nt + t]
     const int64_t* voff;   // voff[k nt + t]
-    int32_t M, N;
+    int32_t M, N;          // N: temporal bases L = nodes (p + 1), the time rows of the band
     int64_t nt;            // tiles per time row
+    int32_t nodes, p1;     // time nodes and bases per node
 };
 
 __host__ __device__ inline int64_t band_ilo_index(const BandView& b, int k, int64_t l, int64_t j)
@@ -299,7 +321,7 @@ inline int64_t lp_num_params(int layers) { return lp_off_wout(layers) + kLpHidde
 // Launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------------------------
 namespace tdbem {
-void launch_table_values(const double* t, int N, int cut, TimeRule rule, PieceTable pt, const int32_t* pc_f,
+void launch_table_values(const double* t, int N, int p1, int cut, TimeRule rule, PieceTable pt, const int32_t* pc_f,
                          const int32_t* pc_j, const int32_t* pc_p, int64_t npieces, const int32_t* f_k,
                          const int32_t* f_i, const KernelDesc* desc, const double* ivl, double2* values,
                          hipStream_t s);
@@ -323,7 +345,12 @@ void launch_singular(GeomView g, TableView tv, const double* t, BandView band, c
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,
                         const int32_t* i, const int32_t* j, const int32_t* l, double* out, hipStream_t s);
 
-void launch_rhs(GeomView g, const double* t, int N, int cut, TimeRule rule, double d0, double d1, double d2,
+// Entries of block (k, i) as (row l, column j, value) with an atomic position counter; count only
+// when row is null.
+void launch_block_coo(BandView band, const double* val, const float* valf, int k, int i, unsigned long long* count,
+                      int32_t* row, int32_t* col, double* out, int64_t cap, hipStream_t s);
+
+void launch_rhs(GeomView g, const double* t, int N, int p1, int cut, TimeRule rule, double d0, double d1, double d2,
                 double t0, double width, int M, double* gvec, hipStream_t s);
 void launch_matvec(BandView band, const double* val, const float* valf, int k0, int k1, int i0, int i1,
                    const double* x, double* y, hipStream_t s);
@@ -337,6 +364,7 @@ void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hip
 int dots_partial_blocks(int64_t n);
 void launch_scale_inv_sqrt(double* dst, const double* src, const double* nrm2, int64_t n, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+void launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 void launch_lp_round(int64_t P, const float* p, uint16_t* q, hipStream_t s);
 // hstride = 0: inference, H holds two ping-pong slots of N*M*64 floats and U is unused;

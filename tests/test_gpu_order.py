@@ -1,0 +1,157 @@
+"""Temporal order p >= 1 (eq. (BasisFunctions) with m = 0..p, L = N (p + 1) bases) on the GPU.
+
+* Time-kernel tables against the oracle's direct quadrature, every tabulated (k, i).
+* Every entry of every block against the oracle's dense assembly on closed meshes (bump and erf
+  cutoffs, equidistant and graded grids), exact quad-eval counts.
+* The right-hand side and the product against the oracle.
+* Convergence to the closed-form sphere solutions of Section 6.1 beyond what the CPU oracle can
+  reach: icosphere levels 2 -> 3 with N = 24 -> 48, p = 1, the GPU assembly and solve
+  (FGMRES with Algorithm 1), the right-hand side g(t) Y_n^0(x) and the L2 error formed in numpy.
+Tolerances as in test_gpu_parity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.test_oracle_convergence import Y00, g_n0, g_n1, phi_paper_n0, phi_paper_n1
+from workloads import equidistant_grid, graded_grid, icosphere, torus
+
+pytestmark = pytest.mark.gpu
+
+BLOCK_TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def tb():
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    import paper_1503_07221_amd as tb
+    tb.load_library()
+    return tb
+
+
+@pytest.fixture(scope="module")
+def ctx(tb):
+    c = tb.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_blocks(ctx, L, M):
+    K, I, J, Lq = np.meshgrid(np.arange(L), np.arange(L), np.arange(M), np.arange(M), indexing="ij")
+    return ctx.get_entries(K.ravel(), I.ravel(), J.ravel(), Lq.ravel()).reshape(L, L, M, M)
+
+
+CASES = {
+    "sphere20_eq5_p1_erf": lambda: (icosphere(0), equidistant_grid(5, 3.0), "erf", 1),
+    "sphere20_graded6_p2": lambda: (icosphere(0), graded_grid(6, 3.0, seed=31), "bump", 2),
+    "torus24_graded5_p1": lambda: (torus(4, 3), graded_grid(5, 2.5, seed=22), "bump", 1),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_blocks_and_tables(ctx, tb, oracle_mod, case):
+    (xyz, tri), grid, kind, p = CASES[case]()
+    L, M = len(grid) * (p + 1), len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, kind, p=p)
+    rep = ctx.assemble(tb.FP64)
+    assert ctx.N == L
+    # tables: every kernel at seeded distances inside its support
+    rng = np.random.default_rng(5)
+    ks, is_, rs = [], [], []
+    for k in range(L):
+        for i in range(L):
+            lo, hi = oracle_mod.support(grid, k, i, p)
+            hi = min(hi, oracle_mod.mesh_diameter(xyz))
+            if hi > lo:
+                for r in rng.uniform(lo, hi, 6):
+                    ks.append(k); is_.append(i); rs.append(r)
+    ps, pt = ctx.eval_kernels(np.array(ks), np.array(is_), np.array(rs))
+    ref = np.array([oracle_mod.psi(grid, k, i, r, kind, p) for k, i, r in zip(ks, is_, rs)])
+    for k in range(L):
+        for i in range(L):
+            sel = (np.array(ks) == k) & (np.array(is_) == i)
+            if not sel.any():
+                continue
+            sc = np.abs(ref[sel]).max(axis=0)
+            assert np.abs(ps[sel] - ref[sel, 0]).max() <= 1e-10 * max(sc[0], 1e-300), (k, i)
+            assert np.abs(pt[sel] - ref[sel, 1]).max() <= 1e-11 * max(sc[1], 1e-300), (k, i)
+    A = oracle_mod.assemble_dense(xyz, tri, grid, kind=kind, p=p)
+    G = _gpu_blocks(ctx, L, M)
+    worst = 0.0
+    for k in range(L):
+        for i in range(L):
+            sc = np.abs(A[k, i]).max()
+            if sc == 0.0:
+                assert np.all(G[k, i] == 0.0), (k, i)
+                continue
+            worst = max(worst, np.abs(G[k, i] - A[k, i]).max() / sc)
+    assert worst <= BLOCK_TOL, worst
+    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, p=p)
+
+
+def test_rhs_and_product(ctx, tb, oracle_mod):
+    import torch
+    (xyz, tri), grid, kind, p = CASES["sphere20_eq5_p1_erf"]()
+    L, M = len(grid) * (p + 1), len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, kind, p=p); ctx.assemble(tb.FP64)
+    d = np.array([0.2, -0.3, 0.93]); d /= np.linalg.norm(d)
+    g = ctx.rhs_plane_pulse(d, 1.5, 0.3).cpu().numpy()
+    gr = oracle_mod.rhs_plane_pulse(xyz, tri, grid, d, 1.5, 0.3, kind=kind, p=p)
+    assert np.abs(g - gr).max() <= 1e-13 * np.abs(gr).max()
+    Af = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, grid, kind=kind, p=p))
+    x = np.random.default_rng(3).standard_normal(L * M)
+    y = ctx.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.linalg.norm(y - Af @ x) <= 1e-13 * np.linalg.norm(Af @ x)
+    alpha, rep = ctx.solve(torch.from_numpy(gr).cuda(), tol=1e-10, restart=100, max_it=2000, precond_inner=(2, 10))
+    assert rep["converged"]
+    ref = np.linalg.solve(Af, gr)
+    assert np.linalg.norm(alpha.cpu().numpy() - ref) <= np.linalg.cond(Af) * 1e-10 * np.linalg.norm(ref)
+
+
+def _gpu_relative_error(ctx, tb, oracle_mod, level, N, n, p=1, kind="erf"):
+    import torch
+    T = 6.0 if n == 0 else 2.0
+    xyz, tri = icosphere(level)
+    grid = equidistant_grid(N, T)
+    M, L = len(xyz), N * (p + 1)
+    B, W = oracle_mod.rule7()
+    P = xyz[tri]
+    area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    X = np.einsum("qa,eac->eqc", B, P)
+    Yq = np.full(X.shape[:2], Y00) if n == 0 else math.sqrt(3.0 / (4.0 * math.pi)) * X[..., 2]
+    space = np.zeros(M)
+    for a in range(3):
+        np.add.at(space, tri[:, a], area * (Yq * B[None, :, a] * W[None, :]).sum(1))
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    tq = np.concatenate([0.5 * (b - a) * xg + 0.5 * (a + b) for a, b in zip(grid[:-1], grid[1:])])
+    wt = np.concatenate([0.5 * (b - a) * wg for a, b in zip(grid[:-1], grid[1:])])
+    bas = np.array([[oracle_mod.basis(grid, i, t, kind, p) for t in tq] for i in range(L)])
+    gfun = g_n0 if n == 0 else g_n1
+    time_part = (bas[:, :, 1] * np.array([gfun(t) for t in tq])[None] * wt[None]).sum(1)
+    rhs = (time_part[:, None] * space[None, :]).ravel()
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, kind, p=p); ctx.assemble(tb.FP64)
+    alpha, rep = ctx.solve(torch.from_numpy(rhs).cuda(), tol=1e-10, restart=200, max_it=4000, precond_inner=(2, 10))
+    assert rep["converged"], (level, N, n)
+    alpha = alpha.cpu().numpy().reshape(L, M)
+    hq = np.einsum("iea,qa->ieq", alpha[:, tri], B)
+    ref = -np.array([(phi_paper_n0 if n == 0 else phi_paper_n1)(t) for t in tq])
+    num = den = 0.0
+    for m in range(len(tq)):
+        ph = np.einsum("i,ieq->eq", bas[:, m, 0], hq)
+        ex = ref[m] * Yq
+        num += wt[m] * (area[:, None] * W[None] * (ph - ex) ** 2).sum()
+        den += wt[m] * (area[:, None] * W[None] * ex ** 2).sum()
+    return math.sqrt(num / den)
+
+
+@pytest.mark.parametrize("n", [0, 1])
+def test_sphere_convergence_on_the_gpu(ctx, tb, oracle_mod, n):
+    """Section 6.1 closed forms, p = 1: the CPU oracle pins levels 0 -> 2; the GPU continues with
+    levels 2 -> 3 (N = 24 -> 48) and the error keeps falling."""
+    e2 = _gpu_relative_error(ctx, tb, oracle_mod, 2, 24, n)
+    e3 = _gpu_relative_error(ctx, tb, oracle_mod, 3, 48, n)
+    assert e3 < 0.7 * e2, (e2, e3)
+    assert e3 < (0.05 if n == 0 else 0.02), (e2, e3)

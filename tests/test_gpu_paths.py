@@ -1,0 +1,316 @@
+"""GPU path against the oracle on the code paths the full-size kernels take.
+
+* Every stored-operator product (single vector, time-block sub-ranges, every multi-vector
+  variant, the transposed product, FP64 and FP32 storage) and the matrix-free product on the
+  320-triangle, 10-basis sphere: M = 162 vertices span three 64-vertex tiles with a ragged last
+  one, so off-diagonal tiles, per-(time row, tile) band widths and the column sums are all
+  exercised, against the oracle's dense system (fast mode).
+* Whole blocks A_{k,i} through the C ABI (tdbem_block_nnz / tdbem_get_block_coo) against the
+  oracle's dense blocks.
+* Sampled entries at full size (5120 triangles, 64 graded bases): vertex pairs spread over
+  several rows and tiles, the farthest vertex included, FP64 and mixed.
+* FGMRES on a system of more than 8192 unknowns (several chunks of the dot-product kernel)
+  against the oracle's LU solution.
+* The reduced torus (32 x 20 quads, 32 graded bases on [0, 10]): FP64 solve to 1e-8, the operator
+  checked against the oracle at sampled entries and the residual confirmed by the matrix-free
+  product.
+* The FP64 assembly of the 20480-triangle torus with 128 bases reports TDBEM_ENOMEM with the
+  bytes it needs.
+
+Tolerances as in test_gpu_parity: blocks 1e-11 of each block's maximum, products 1e-13
+(FP64) / the mixed bound for FP32 storage.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from workloads import get_config, graded_grid, icosphere, torus
+
+pytestmark = pytest.mark.gpu
+
+BLOCK_TOL = 1e-11
+MIXED_TOL = 2e-6
+
+
+@pytest.fixture(scope="module")
+def tb():
+    if not gpu_available():
+        pytest.skip("no HIP device")
+    import paper_1503_07221_amd as tb
+    tb.load_library()
+    return tb
+
+
+@pytest.fixture(scope="module")
+def ctx(tb):
+    c = tb.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def config1(oracle_mod):
+    c = get_config("sphere320_eq10")
+    xyz, tri = c["mesh"]
+    T = oracle_mod.fast_tables(xyz, c["grid"], c["cutoff"])
+    A = oracle_mod.assemble_dense(xyz, tri, c["grid"], kind=c["cutoff"], tables=T)
+    return c, A, oracle_mod.system_matrix(A)
+
+
+def _x(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def test_products_three_tiles(ctx, tb, config1):
+    import torch
+    c, A, Af = config1
+    xyz, tri = c["mesh"]
+    N, M = len(c["grid"]), len(xyz)
+    assert M > 2 * 64 and M % 64 != 0
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], c["cutoff"]); ctx.assemble(tb.FP64)
+    x = _x(N * M, 1)
+    xd = torch.from_numpy(x).cuda()
+    y = ctx.matvec(xd).cpu().numpy()
+    yr = Af @ x
+    assert np.linalg.norm(y - yr) <= 1e-13 * np.linalg.norm(yr)
+    for (k0, k1, i0, i1) in [(0, 10, 0, 10), (3, 7, 1, 6), (5, 10, 0, 5), (0, 5, 0, 5), (9, 10, 8, 10)]:
+        xs = xd[i0 * M:i1 * M].contiguous()
+        ys = ctx.matvec_range(k0, k1, i0, i1, xs).cpu().numpy()
+        ysr = Af[k0 * M:k1 * M, i0 * M:i1 * M] @ x[i0 * M:i1 * M]
+        assert np.linalg.norm(ys - ysr) <= 1e-13 * max(np.linalg.norm(ysr), 1e-300), (k0, k1, i0, i1)
+    # the transposed product (blocks symmetric, so A^T y = sum_k A_{k,i} y_k)
+    yt = ctx.matvec_transpose(xd).cpu().numpy()
+    ytr = Af.T @ x
+    assert np.linalg.norm(yt - ytr) <= 1e-13 * np.linalg.norm(ytr)
+    # every multi-vector variant, with a right-hand-side count that is not a multiple of 4
+    X = np.stack([_x(N * M, 10 + r) for r in range(7)])
+    Yr = X @ Af.T
+    nv = ctx.matvec_multi_set_variant(-1)
+    for v in range(nv):
+        ctx.matvec_multi_set_variant(v)
+        Y = ctx.matvec_multi(torch.from_numpy(X).cuda()).cpu().numpy()
+        for r in range(len(X)):
+            assert np.linalg.norm(Y[r] - Yr[r]) <= 1e-13 * np.linalg.norm(Yr[r]), (v, r)
+    ctx.matvec_multi_set_variant(-1)
+    # the matrix-free FP64 product
+    yf, rep = ctx.matvec_free(xd)
+    assert np.linalg.norm(yf.cpu().numpy() - yr) <= 1e-13 * np.linalg.norm(yr)
+    # FP32 storage (mixed assembly): products within the mixed bound of the FP64 oracle
+    ctx.assemble(tb.MIXED)
+    y32 = ctx.matvec(xd).cpu().numpy()
+    assert np.linalg.norm(y32 - yr) <= MIXED_TOL * np.linalg.norm(yr)
+    yt32 = ctx.matvec_transpose(xd).cpu().numpy()
+    assert np.linalg.norm(yt32 - ytr) <= MIXED_TOL * np.linalg.norm(ytr)
+    Y32 = ctx.matvec_multi(torch.from_numpy(X).cuda()).cpu().numpy()
+    assert np.linalg.norm(Y32 - Yr) <= MIXED_TOL * np.linalg.norm(Yr)
+
+
+def test_block_coo_against_oracle(ctx, tb, oracle_mod, config1):
+    """Whole blocks through tdbem_get_block_coo: the 20-triangle sphere (every block) and the
+    320-triangle workload (every block), sorted by (row, column), block maxima to 1e-11."""
+    c0 = get_config("sphere20_eq5_erf")
+    x0, t0 = c0["mesh"]
+    A0 = oracle_mod.assemble_dense(x0, t0, c0["grid"], kind="erf")
+    c1, A1, _ = config1
+    for c, A in ((c0, A0), (c1, A1)):
+        xyz, tri = c["mesh"]
+        L, M = A.shape[0], A.shape[2]
+        ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], c["cutoff"]); ctx.assemble(tb.FP64)
+        for k in range(L):
+            for i in range(L):
+                row, col, val = ctx.get_block_coo(k, i)
+                ref = A[k, i].T                       # [row l, column j] = A_{k,i}(j, l)
+                D = np.zeros((M, M))
+                D[row, col] = val
+                assert len(val) == ctx.block_nnz(k, i)
+                assert np.all(np.diff(row.astype(np.int64) * M + col) > 0)      # sorted, no duplicates
+                sc = np.abs(ref).max()
+                if sc == 0.0:
+                    assert len(val) == 0, (k, i)
+                    continue
+                assert np.abs(D - ref).max() <= BLOCK_TOL * sc, (k, i)
+                assert np.array_equal(D, D.T)
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.get_block_coo(L, 0)
+    assert e.value.status == -1
+    import ctypes
+    n = ctx.block_nnz(L - 1, L - 1)
+    buf_i = np.zeros(max(n - 1, 1), dtype=np.int32); buf_v = np.zeros(max(n - 1, 1))
+    st = ctx.lib.tdbem_get_block_coo(ctx.h, L - 1, L - 1, buf_i.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     buf_i.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     buf_v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n - 1)
+    assert st == -1 and str(n) in ctx.lib.tdbem_last_error(ctx.h).decode()
+
+
+def _spread_pairs(xyz, tri, rng, n):
+    """Vertex pairs over several rows and tiles: (l, j) with l drawn over all vertices, j near,
+    at mid distance and at the far side of l; the farthest vertex of vertex 0 included."""
+    M = len(xyz)
+    d0 = np.linalg.norm(xyz - xyz[0], axis=1)
+    js, ls = [int(np.argmax(d0))], [0]
+    for l in rng.choice(M, n - 1, replace=False):
+        d = np.linalg.norm(xyz - xyz[l], axis=1)
+        pick = rng.integers(0, 3)
+        j = [int(np.argsort(d)[1]), int(np.argmin(np.abs(d - np.median(d)))), int(np.argmax(d))][pick]
+        js.append(j); ls.append(int(l))
+    return np.array(js), np.array(ls)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sampled_entries_spread_full_size(ctx, tb, oracle_mod, prec):
+    c = get_config("sphere5120_graded64")
+    xyz, tri = c["mesh"]; grid = c["grid"]
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, c["cutoff"])
+    ctx.assemble(tb.FP64 if prec == "fp64" else tb.MIXED)
+    sj, sl = _spread_pairs(xyz, tri, np.random.default_rng(21 if prec == "fp64" else 22), 32)
+    assert len(set((sl // 64).tolist())) >= 8          # many vertex tiles
+    T = oracle_mod.fast_tables(xyz, grid, c["cutoff"])
+    ref = oracle_mod.assemble_entries(xyz, tri, grid, sj, sl, kind=c["cutoff"], tables=T)
+    N = len(grid)
+    K, I = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    tol = BLOCK_TOL if prec == "fp64" else MIXED_TOL
+    for s in range(len(sj)):
+        got = ctx.get_entries(K.ravel(), I.ravel(), sj[s], sl[s]).reshape(N, N)
+        sc = np.abs(ref[s]).max()
+        if sc == 0.0:
+            assert np.all(got == 0.0), (sj[s], sl[s])
+            continue
+        assert np.abs(got - ref[s]).max() <= tol * sc, (sj[s], sl[s], np.abs(got - ref[s]).max() / sc)
+
+
+def test_solve_more_than_8192_unknowns(ctx, tb, oracle_mod):
+    """FGMRES on 162 vertices x 52 graded bases (8424 unknowns, two chunks of the dot-product
+    kernel) against the LU solution of the oracle's system: with Algorithm 1 (2, 10) to 1e-10,
+    plain FGMRES(200) to 1e-5 (restarted GMRES stagnates on these systems; the oracle's own FGMRES
+    reaches 6e-7 after 3000 iterations)."""
+    import torch
+    xyz, tri = icosphere(2)
+    grid = graded_grid(52, 10.0, seed=23)
+    N, M = len(grid), len(xyz)
+    assert N * M > 8192
+    T = oracle_mod.fast_tables(xyz, grid, "bump")
+    Af = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, grid, tables=T))
+    g = oracle_mod.rhs_plane_pulse(xyz, tri, grid, np.array([0.0, 0.6, 0.8]), 1.9, 0.3)
+    ref = np.linalg.solve(Af, g)
+    kappa = np.linalg.cond(Af)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, "bump"); ctx.assemble(tb.FP64)
+    for inner, tol in [((2, 10), 1e-10), ((), 1e-5)]:
+        alpha, rep = ctx.solve(torch.from_numpy(g).cuda(), tol=tol, restart=200, max_it=3000, precond_inner=inner)
+        a = alpha.cpu().numpy()
+        assert rep["converged"], inner
+        assert np.linalg.norm(g - Af @ a) <= 1.01 * tol * np.linalg.norm(g), inner
+        assert np.linalg.norm(a - ref) <= kappa * tol * np.linalg.norm(ref), inner
+
+
+def test_reduced_torus_fp64_solve(ctx, tb, oracle_mod):
+    """32 x 20 quads (1280 triangles), 32 graded bases on [0, 10]: the stored FP64 operator
+    against the oracle at sampled entries, FGMRES + Algorithm 1 to 1e-8, and the residual of
+    that solution under the matrix-free FP64 product."""
+    import torch
+    xyz, tri = torus(32, 20)
+    grid = graded_grid(32, 10.0, seed=4)
+    N, M = len(grid), len(xyz)
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(grid, "bump"); ctx.assemble(tb.FP64)
+    sj, sl = _spread_pairs(xyz, tri, np.random.default_rng(24), 12)
+    T = oracle_mod.fast_tables(xyz, grid, "bump")
+    ref = oracle_mod.assemble_entries(xyz, tri, grid, sj, sl, tables=T)
+    K, I = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    for s in range(len(sj)):
+        got = ctx.get_entries(K.ravel(), I.ravel(), sj[s], sl[s]).reshape(N, N)
+        sc = np.abs(ref[s]).max()
+        assert np.abs(got - ref[s]).max() <= BLOCK_TOL * max(sc, 1e-300), (sj[s], sl[s])
+    d = np.array([0.3, -0.5, 0.81]); d /= np.linalg.norm(d)
+    g = ctx.rhs_plane_pulse(d, 1.35 + 6 * 0.1 * 4, 0.4)
+    alpha, rep = ctx.solve(g, tol=1e-8, restart=300, max_it=3000, precond_inner=(2, 10))
+    assert rep["converged"] and rep["rel_residual"] <= 1e-8
+    yf, _ = ctx.matvec_free(alpha)
+    assert torch.linalg.norm(g - yf).item() <= 1.05e-8 * torch.linalg.norm(g).item()
+
+
+def test_fp64_torus_reports_memory(tb):
+    """The 20480-triangle torus with 128 graded bases needs more than the device holds in FP64:
+    TDBEM_ENOMEM, with the bytes in the message, and the context stays usable."""
+    c = get_config("torus20480_graded128")
+    ctx = tb.Context(0)
+    ctx.set_mesh(*c["mesh"]); ctx.set_time_grid(c["grid"], c["cutoff"])
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.assemble(tb.FP64)
+    assert e.value.status == -4
+    assert "GB" in str(e.value) and "band storage needs" in str(e.value)
+    ctx.set_mesh(*icosphere(0)); ctx.set_time_grid(np.array([0.0, 1.0, 2.0]))
+    ctx.assemble(tb.FP64)
+    ctx.close()
+
+
+def test_time_grid_order_argument(tb):
+    """Temporal orders 0..4 are accepted, others rejected at the boundary (TDBEM_EINVAL); the
+    learned preconditioner and the field evaluation are p = 0 only."""
+    import torch
+    ctx = tb.Context(0)
+    for p in (-1, 5):
+        with pytest.raises(tb.TdbemError) as e:
+            ctx.set_time_grid(np.array([0.0, 1.0, 2.0]), "bump", p=p)
+        assert e.value.status == -1
+    ctx.set_mesh(*icosphere(0)); ctx.set_time_grid(np.array([0.0, 1.0, 2.0]), "bump", p=1); ctx.assemble()
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.lp_init(2)
+        ctx.lp_apply(torch.zeros(6 * 12, dtype=torch.float64, device="cuda"))
+    assert e.value.status == -1
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.potential_dl(torch.zeros(6 * 12, dtype=torch.float64, device="cuda"), np.array([[3.0, 0, 0]]),
+                         np.array([1.0]))
+    assert e.value.status == -1
+    ctx.close()
+
+
+def test_dgmres_against_lu(ctx, tb, oracle_mod):
+    """DGMRES(m, l) (Section 4.1) on the GPU: the 20-triangle system to 1e-10 against LU, and on
+    the 320-triangle workload DGMRES(50, 4) reaches 1e-8 in well under the iterations of GMRES(50)
+    (the comparison of Tables 1 and 3; the oracle's DGMRES needs 252 against 666)."""
+    import torch
+    c = get_config("sphere20_eq5_erf")
+    xyz, tri = c["mesh"]
+    Af = oracle_mod.system_matrix(oracle_mod.assemble_dense(xyz, tri, c["grid"], kind="erf"))
+    g = oracle_mod.rhs_plane_pulse(xyz, tri, c["grid"], c["direction"], c["t0"], c["width"], kind="erf")
+    ctx.set_mesh(xyz, tri); ctx.set_time_grid(c["grid"], "erf"); ctx.assemble(tb.FP64)
+    alpha, rep = ctx.solve(torch.from_numpy(g).cuda(), tol=1e-10, restart=10, max_it=3000, deflation=(2, 8))
+    a = alpha.cpu().numpy()
+    assert rep["converged"]
+    assert np.linalg.norm(g - Af @ a) <= 1.01e-10 * np.linalg.norm(g)
+    ref = np.linalg.solve(Af, g)
+    assert np.linalg.norm(a - ref) <= np.linalg.cond(Af) * 1e-10 * np.linalg.norm(ref)
+    c1 = get_config("sphere320_eq10")
+    ctx.set_mesh(*c1["mesh"]); ctx.set_time_grid(c1["grid"], c1["cutoff"]); ctx.assemble(tb.FP64)
+    g = ctx.rhs_plane_pulse(c1["direction"], c1["t0"], c1["width"])
+    _, rg = ctx.solve(g, tol=1e-8, restart=50, max_it=4000)
+    ad, rd = ctx.solve(g, tol=1e-8, restart=50, max_it=4000, deflation=(4, 16))
+    assert rg["converged"] and rd["converged"]
+    assert rd["iterations"] <= 0.6 * rg["iterations"], (rd, rg)      # oracle: 252 against 666
+    r = g - ctx.matvec(ad)
+    assert torch.linalg.norm(r).item() <= 1.01e-8 * torch.linalg.norm(g).item()
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.solve(g, tol=1e-8, restart=50, deflation=(4, 2))
+    assert e.value.status == -1
+
+
+def test_inner_fp32_solve_reaches_fp64_tolerance(ctx, tb):
+    """Algorithm 1's products on an FP32 copy of the FP64 band, the outer iteration on the FP64
+    operator: the solve reaches 1e-8 measured on the FP64 system, and its iterate agrees with the
+    all-FP64 solve."""
+    import torch
+    c = get_config("sphere320_eq10")
+    ctx.set_mesh(*c["mesh"]); ctx.set_time_grid(c["grid"], c["cutoff"]); ctx.assemble(tb.FP64)
+    g = ctx.rhs_plane_pulse(c["direction"], c["t0"], c["width"])
+    a64, r64 = ctx.solve(g, tol=1e-8, restart=300, max_it=2000, precond_inner=(2, 10))
+    a32, r32 = ctx.solve(g, tol=1e-8, restart=300, max_it=2000, precond_inner=(2, 10), inner_fp32=True)
+    assert r64["converged"] and r32["converged"]
+    res = g - ctx.matvec(a32)
+    assert torch.linalg.norm(res).item() <= 1.01e-8 * torch.linalg.norm(g).item()
+    assert torch.linalg.norm(a32 - a64).item() <= 1e-6 * torch.linalg.norm(a64).item()
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.solve(g, tol=1e-8, inner_fp32=True)              # no Algorithm 1 levels
+    assert e.value.status == -1
+    ctx.assemble(tb.MIXED)
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.solve(g, tol=1e-8, precond_inner=(2, 10), inner_fp32=True)
+    assert e.value.status == -1

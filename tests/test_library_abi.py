@@ -41,7 +41,9 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.tdbem_assemble(None, 0, None) == -1
     assert lib.tdbem_matvec(None, None, None) == -1
     assert lib.tdbem_matvec_free(None, None, None, None) == -1
-    assert lib.tdbem_set_time_grid(None, None, 2, 0) == -1
+    assert lib.tdbem_set_time_grid(None, None, 2, 0, 0) == -1
+    assert lib.tdbem_block_nnz(None, 0, 0, None) == -1
+    assert lib.tdbem_get_block_coo(None, 0, 0, None, None, None, 0) == -1
     assert lib.tdbem_solve(None, None, None, None, None) == -1
     assert lib.tdbem_lp_init(None, 4, 0) == -1
     assert lib.tdbem_matvec_multi(None, 2, None, None) == -1

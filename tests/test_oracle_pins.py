@@ -541,3 +541,56 @@ def test_rhs_against_direct_integration(oracle_mod):
                 val = quad(f, lo, hi, points=[grid[k]], epsabs=1e-14, epsrel=1e-13, limit=200)[0]
                 ref[tri[e]] += area * W[q] * np.dot(d, n) * val * B[q]
         assert np.abs(g[k * M:(k + 1) * M] - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+# --- DGMRES(m, l): deflation (Section 4.1) ------------------------------------------------------
+def _matrix_with_small_eigenvalues(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    D = np.diag(np.concatenate([[1e-3, 2e-3, 5e-3, 1e-2], rng.uniform(1, 3, n - 4)]))
+    return Q @ (D + np.triu(rng.standard_normal((n, n)) * 0.1, 1)) @ Q.T
+
+
+def test_deflation_replaces_the_smallest_eigenvalues(oracle_mod):
+    """With U an orthonormal basis of the invariant subspace of the r smallest eigenvalues (real
+    Schur vectors, scipy), A M^{-1} maps U to |lambda_LM| U and, on the complement, keeps the
+    eigenvalues lambda_{r+1}, ..., lambda_LM (Section 4.1)."""
+    import scipy.linalg as sl
+    n, r = 40, 4
+    A = _matrix_with_small_eigenvalues(n, 1)
+    ev = np.linalg.eigvals(A)
+    lam = np.abs(ev).max()
+    T, Z, sdim = sl.schur(A, output="real", sort=lambda re, im: abs(complex(re, im)) < 0.02)
+    assert sdim == r
+    U = Z[:, :r]
+    Tinv = np.linalg.inv(U.T @ A @ U)
+    AM = np.column_stack([A @ oracle_mod.deflation_inverse(e, U, Tinv, lam) for e in np.eye(n)])
+    assert np.abs(AM @ U - lam * U).max() <= 1e-6 * lam       # T^{-1} amplifies the Schur rounding by ~1e3
+    W = Z[:, r:]
+    got = np.sort_complex(np.linalg.eigvals(W.T @ AM @ W))
+    want = np.sort_complex(ev[np.argsort(np.abs(ev))][r:])
+    assert np.allclose(got, want, atol=1e-10 * lam)
+
+
+def test_dgmres_restores_convergence_where_gmres_stalls(oracle_mod):
+    """GMRES(10) stagnates on a matrix with four tiny eigenvalues; DGMRES(10, 2) reaches the LU
+    solution (Section 4.1: deflation keeps the information restarts lose)."""
+    A = _matrix_with_small_eigenvalues(60, 0)
+    b = np.random.default_rng(2).standard_normal(60)
+    ref = np.linalg.solve(A, b)
+    x1, it1, _ = oracle_mod.fgmres(lambda v: A @ v, b, 1e-8, 2000, restart=10)
+    x2, it2, _ = oracle_mod.dgmres(lambda v: A @ v, b, 1e-8, 2000, m=10, l=2)
+    assert it1 == 2000 and np.linalg.norm(b - A @ x1) > 1e-6 * np.linalg.norm(b)
+    assert it2 < 200 and np.linalg.norm(b - A @ x2) <= 1.01e-8 * np.linalg.norm(b)
+    assert np.linalg.norm(x2 - ref) <= np.linalg.cond(A) * 1e-8 * np.linalg.norm(ref)
+
+
+def test_dgmres_on_the_block_system(oracle_mod, small_blocks):
+    """DGMRES(10, 2) on the assembled 20-triangle, 5-basis system reaches the LU solution."""
+    c, A = small_blocks
+    Af = oracle_mod.system_matrix(A)
+    g = oracle_mod.rhs_plane_pulse(*c["mesh"], c["grid"], c["direction"], c["t0"], c["width"], kind=c["cutoff"])
+    x, its, hist = oracle_mod.dgmres(lambda v: Af @ v, g, 1e-10, 3000, m=10, l=2)
+    ref = np.linalg.solve(Af, g)
+    assert np.linalg.norm(g - Af @ x) <= 1.01e-10 * np.linalg.norm(g)
+    assert np.linalg.norm(x - ref) <= np.linalg.cond(Af) * 1e-10 * np.linalg.norm(ref)
