@@ -157,6 +157,15 @@ tdbem_status tdbem_assemble_group(tdbem_ctx *const *ctxs, int32_t n, tdbem_preci
 tdbem_status tdbem_get_entries(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,
                                const int32_t *j, const int32_t *l, double *out);
 
+/* tdbem_get_entries for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same entries, staged through a
+ * statically allocated device array instead of allocations made per call.  At most 65536 entries
+ * per call (TDBEM_EINVAL beyond); no hipMalloc or hipFree.  Every context on one device shares
+ * that device's array, so calls that overlap on one device (several host threads or streams)
+ * race; the array keeps the last call's contents.  Host arrays as in tdbem_get_entries. */
+tdbem_status tdbem_get_entries_noalloc(tdbem_ctx *ctx, int64_t n, const int32_t *k, const int32_t *i,
+                                       const int32_t *j, const int32_t *l, double *out);
+
 /* Number of entries of the assembled block A_{k,i} (the sparse blocks of eq. (Apartitioned), with
  * the pattern of eq. (SparsitySmallBlock)): the non-zero values of the stored band, counted in
  * both triangles (an off-diagonal vertex pair counts twice, the blocks being symmetric).  Written

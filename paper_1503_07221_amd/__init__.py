@@ -27,7 +27,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "EGRID", -
           -6: "ESTATE"}
 
 EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_set_mesh", "tdbem_set_time_grid",
-                    "tdbem_assemble", "tdbem_get_entries", "tdbem_block_nnz", "tdbem_get_block_coo", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
+                    "tdbem_assemble", "tdbem_get_entries", "tdbem_get_entries_noalloc", "tdbem_block_nnz", "tdbem_get_block_coo", "tdbem_eval_kernels", "tdbem_rhs_plane_pulse",
                     "tdbem_matvec", "tdbem_matvec_range", "tdbem_matvec_free", "tdbem_solve",
                     "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
                     "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
@@ -120,6 +120,7 @@ def load_library(path=LIB_PATH):
     L.tdbem_get_block_coo.argtypes = [vp, i32, i32, P(i32), P(i32), P(dp), i64]
     L.tdbem_assemble.argtypes = [vp, ctypes.c_int, P(AssemblyReport)]
     L.tdbem_get_entries.argtypes = [vp, i64, P(i32), P(i32), P(i32), P(i32), P(dp)]
+    L.tdbem_get_entries_noalloc.argtypes = [vp, i64, P(i32), P(i32), P(i32), P(i32), P(dp)]
     L.tdbem_eval_kernels.argtypes = [vp, i64, P(i32), P(i32), P(dp), P(dp), P(dp)]
     L.tdbem_rhs_plane_pulse.argtypes = [vp, P(dp), dp, dp, vp]
     L.tdbem_matvec.argtypes = [vp, vp, vp]

@@ -148,6 +148,7 @@ void ss_point(int kind, int reg, double xi, double e1, double e2, double e3, dou
 
 struct tdbem_ctx {
     int device = 0;
+    void* scratch = nullptr;      // device address of the allocation-free staging array
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int ss_order = 4;
@@ -341,6 +342,11 @@ tdbem_status tdbem_create(tdbem_ctx** out, const tdbem_options* opt)
         return TDBEM_EHIP;
     }
     if (hipSetDevice(c->device) != hipSuccess) { delete c; return TDBEM_EHIP; }
+    // the allocation-free entry point's staging array: its address on this device, once per device
+    if (noalloc_scratch(c->device, &c->scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        c->scratch = nullptr;   // tdbem_get_entries_noalloc then reports TDBEM_EHIP
+    }
     if (opt && opt->stream) {
         c->stream = static_cast<hipStream_t>(opt->stream);
     } else {
@@ -845,6 +851,37 @@ tdbem_status tdbem_get_entries(tdbem_ctx* c, int64_t n, const int32_t* k, const 
                        dl.as<int32_t>(), dout.as<double>(), c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(out, dout.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_get_entries_noalloc(tdbem_ctx* c, int64_t n, const int32_t* k, const int32_t* i, const int32_t* j,
+                                       const int32_t* l, double* out)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!k || !i || !j || !l || !out))) FAIL(c, TDBEM_EINVAL, "bad entry query");
+    if (n > kNoAllocEntries)
+        FAIL(c, TDBEM_EINVAL, "at most %lld entries per allocation-free query, got %lld", (long long)kNoAllocEntries,
+             (long long)n);
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before reading entries");
+    if (!c->scratch) FAIL(c, TDBEM_EHIP, "the staging array has no device address on device %d", c->device);
+    if (n == 0) return TDBEM_OK;
+    TRY(set_device(c));
+    char* base = static_cast<char*>(c->scratch);
+    int32_t* sk = reinterpret_cast<int32_t*>(base);
+    int32_t* si = sk + kNoAllocEntries;
+    int32_t* sj = si + kNoAllocEntries;
+    int32_t* sl = sj + kNoAllocEntries;
+    double* so = reinterpret_cast<double*>(sl + kNoAllocEntries);
+    const size_t b4 = sizeof(int32_t) * (size_t)n;
+    HIPCHK(c, hipMemcpyAsync(sk, k, b4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(si, i, b4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sj, j, b4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(sl, l, b4, hipMemcpyHostToDevice, c->stream));
+    launch_get_entries(c->band(), c->valf64(), c->valf32(), n, sk, si, sj, sl, so, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(out, so, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return TDBEM_OK;
 }

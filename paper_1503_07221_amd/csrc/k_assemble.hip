@@ -12,6 +12,8 @@
 // the lower-triangle storage forms on the fly (scatter_half).
 #include "tdbem_internal.hpp"
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace tdbem {
@@ -802,6 +804,30 @@ k_block_coo(BandView band, const double* __restrict__ val, const float* __restri
     if (!row) return;
     if ((int64_t)pos < cap) { row[pos] = l; col[pos] = j; out[pos] = v; }
     if (j < l && (int64_t)pos + 1 < cap) { row[pos + 1] = j; col[pos + 1] = l; out[pos + 1] = v; }
+}
+
+// Staging of the allocation-free entry query (tdbem_get_entries_noalloc): the four index arrays and
+// the results of up to kNoAllocEntries entries, in one statically allocated device array.  Host
+// code never passes the array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device (each device holds its own copy).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void** ptr)
+{
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the caller made `device` current
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+    *ptr = p;
+    return hipSuccess;
 }
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -342,6 +342,12 @@ void launch_singular(GeomView g, TableView tv, const double* t, BandView band, c
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      int max_points, double* val, float* valf, const double* px, double* py,
                      unsigned long long* counter, hipStream_t s);
+// Allocation-free entry query: static device staging of kNoAllocEntries queries (4 int32 index
+// arrays and the float64 results); noalloc_scratch returns its address on `device` (current).
+constexpr int64_t kNoAllocEntries = 65536;
+constexpr size_t kNoAllocScratchBytes = (size_t)kNoAllocEntries * (4 * sizeof(int32_t) + sizeof(double));
+hipError_t noalloc_scratch(int device, void** ptr);
+
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,
                         const int32_t* i, const int32_t* j, const int32_t* l, double* out, hipStream_t s);
 
