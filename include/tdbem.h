@@ -51,8 +51,8 @@ typedef enum {
 
 typedef enum {
     TDBEM_FP64 = 0,              /* FP64 quadrature and FP64 matrix storage */
-    TDBEM_MIXED = 1              /* FP32 regular far-field quadrature, FP32 matrix storage;
-                                    FP64 singular pairs, tables, solver vectors and sums */
+    TDBEM_MIXED = 1              /* FP32 matrix storage (every sum formed in FP64, rounded once);
+                                    FP64 tables and solver vectors */
 } tdbem_precision;
 
 typedef struct {

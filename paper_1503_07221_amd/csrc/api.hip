@@ -170,8 +170,7 @@ struct tdbem_ctx {
     TimeRule rule{};
     PieceTable pieces{};
     // tables
-    DBuf d_desc, d_fid, d_ivl, d_coef, d_coef32, d_fk, d_fi, d_meta, d_cell;
-    double hmax = 0.0;   // longest triangle edge
+    DBuf d_desc, d_fid, d_ivl, d_coef, d_fk, d_fi, d_meta, d_cell;
     int64_t nfunc = 0;
     // band storage
     DBuf d_ilo, d_B, d_voff, d_val, d_counter;
@@ -246,7 +245,6 @@ struct tdbem_ctx {
         tv.fid = d_fid.as<int32_t>();
         tv.ivl = d_ivl.as<double>();
         tv.coef = d_coef.as<double2>();
-        tv.coef32 = d_coef32.as<float2>();
         tv.meta = d_meta.as<double4>();
         tv.cell = d_cell.as<uint16_t>();
         tv.N = N;
@@ -404,7 +402,6 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     c->M = (int)M;
     c->E = (int)E;
     c->xyz.assign(xyz, xyz + 3 * M);
-    c->hmax = 0.0;
     c->tri.assign(tri, tri + 3 * E);
     // diameter bound: bounding box diagonal
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -427,7 +424,6 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
                 const double dx = xyz[3 * v] - xyz[3 * u], dy = xyz[3 * v + 1] - xyz[3 * u + 1],
                              dz = xyz[3 * v + 2] - xyz[3 * u + 2];
                 rho[v] = std::max(rho[v], std::sqrt(dx * dx + dy * dy + dz * dz));
-                c->hmax = std::max(c->hmax, rho[v]);
             }
         }
     // singular pairs {tau <= sigma} sharing at least one vertex, grouped by kind
@@ -639,12 +635,11 @@ static tdbem_status build_tables(tdbem_ctx* c)
     TRY(upload(c, d_pcp, pc_p.data(), pc_p.size()));
     ALLOC(c, d_values, sizeof(double2) * (size_t)npieces * kNc);
     ALLOC(c, c->d_coef, sizeof(double2) * (size_t)npieces * kNc);
-    ALLOC(c, c->d_coef32, sizeof(float2) * (size_t)npieces * kNc);
     launch_table_values(c->d_t.as<double>(), nodes, p1, c->cut, c->rule, c->pieces, d_pcf.as<int32_t>(), d_pcj.as<int32_t>(),
                         d_pcp.as<int32_t>(), npieces, c->d_fk.as<int32_t>(), c->d_fi.as<int32_t>(),
                         c->d_desc.as<KernelDesc>(), c->d_ivl.as<double>(), d_values.as<double2>(), c->stream);
     HIPCHK(c, hipGetLastError());
-    launch_table_coefs(d_values.as<double2>(), npieces, c->d_coef.as<double2>(), c->d_coef32.as<float2>(), c->stream);
+    launch_table_coefs(d_values.as<double2>(), npieces, c->d_coef.as<double2>(), c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));   // the temporaries are released on return
     return TDBEM_OK;
@@ -713,10 +708,9 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
     float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
     unsigned long long* cnt = c->d_counter.as<unsigned long long>();
-    // mixed precision: point pairs farther apart than three of the longest triangle edges are the
-    // far field; FP64 everywhere in FP64 mode
-    const double r_far = prec == TDBEM_MIXED ? 3.0 * c->hmax : INFINITY;
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, r_far,
+    // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
+    // storage
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr,
                    c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
@@ -798,7 +792,7 @@ tdbem_status tdbem_matvec_free(tdbem_ctx* c, const double* x, double* y, tdbem_a
     HIPCHK(c, hipMemsetAsync(counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
     HIPCHK(c, hipEventRecord(ev[2], c->stream));
     unsigned long long* cnt = counter.as<unsigned long long>();
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), nullptr, nullptr, x, y, INFINITY,
+    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), nullptr, nullptr, x, y,
                    c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));

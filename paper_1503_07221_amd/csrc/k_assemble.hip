@@ -222,25 +222,6 @@ __device__ inline void cheb_sums(const double2 (&c)[kNc], double x, double& ps, 
     }
 }
 
-// The same in FP32, the coefficient pair m stored as two floats in the bits of c[m].x.
-__device__ inline void cheb_sums_f32(const double2 (&c)[kNc], float x, float& ps, float& pt)
-{
-    const float x2 = 2.0f * x;
-    float tm1 = 1.0f, tm = x;
-    auto lo = [&](int m) { return __uint_as_float((uint32_t)__double_as_longlong(c[m].x)); };
-    auto hi = [&](int m) { return __uint_as_float((uint32_t)((uint64_t)__double_as_longlong(c[m].x) >> 32)); };
-    ps = fmaf(lo(1), x, lo(0));
-    pt = fmaf(hi(1), x, hi(0));
-#pragma unroll
-    for (int m = 2; m < kNc; ++m) {
-        const float tn = fmaf(x2, tm, -tm1);
-        ps = fmaf(lo(m), tn, ps);
-        pt = fmaf(hi(m), tn, pt);
-        tm1 = tm;
-        tm = tn;
-    }
-}
-
 // 1/r to about one ulp: hardware reciprocal refined by two Newton steps.
 __device__ inline double recip(double r)
 {
@@ -255,13 +236,24 @@ __device__ inline double recip(double r)
 // Regular pairs, tiled.  One workgroup (256 lanes) owns a tile of kTileT consecutive test
 // triangles tau and kTileS consecutive trial triangles sigma (the unordered pairs sigma > tau
 // without a common vertex: 32 x 49 point pairs).  It sorts the point-pair distances once; for
-// every (k, i) the distances inside supp psi_{k,i} form one range of the sorted list, which the
-// lanes split into contiguous chunks.  A lane keeps the Chebyshev coefficients of its current
-// piece in registers and reloads them only when the piece changes (sorted neighbours share
-// pieces), adds psi w/r lam_b(q') and tpsi w/r into per-(pair, test point) sums in LDS, and the
-// 8 lanes of each pair then contract those sums into the pair's 3 x 3 block.  Blocks of pairs
-// that share vertices are merged in an LDS tile over the two vertex sets before one atomic add
-// per (vertex, vertex) entry goes to the band storage.  Two barriers per (k, i).
+// every (k, i) the distances inside supp psi_{k,i} form one range of the sorted list.
+//
+//   plan     one wave takes up to kPlan candidates (k, i) at once (one per lane): the range
+//            [s0, s1) of sorted distances inside the support, and the Chebyshev pieces that
+//            range meets.  A round whose range meets more than kStage pieces is cut, at a piece
+//            boundary, into segments of at most kStage pieces.  The records go to LDS.
+//   stage    the pieces of a record (coefficients and piece records), the interval starts and
+//            the support are copied to LDS; the copy for the next record is loaded into
+//            registers while the current one is evaluated, so the inner loop reads LDS only.
+//   phase 1  the lanes split the record's range into contiguous chunks; a lane keeps the
+//            coefficients of its current piece in registers and moves to the next piece when r
+//            passes its end (sorted neighbours share pieces); psi w/r and tpsi w/r of every
+//            point pair go to V (one plain store per point pair, each written by one lane).
+//   phase 2  after the last segment of a round, the 8 lanes of a triangle pair contract V:
+//            lane q sums over q' with lam_b(q') (R_b(q)), the group sums lam_a(q) R_b(q) with
+//            DPP moves, and the 3 x 3 block is merged in an LDS tile over the two vertex sets
+//            before one atomic add per (vertex, vertex) entry goes to the band storage.
+// Two barriers per record.
 // ---------------------------------------------------------------------------------------------
 constexpr int kTileT = 4, kTileS = 8;
 constexpr int kTilePairs = kTileT * kTileS;          // 32
@@ -269,29 +261,126 @@ constexpr int kTileEl = kTilePairs * 49;             // 1568
 constexpr int kTileSort = 2048;
 constexpr int kTileThreads = 256;
 constexpr int kTileVt = 3 * kTileT, kTileVs = 3 * kTileS;
-constexpr int kTileR = kTilePairs * (7 * 3 + 1);     // R_b per (q, b, pair), then T per pair
+constexpr int kStage = 64;                           // pieces of one record held in LDS
+constexpr int kStageSlots = kStage * (kNc + 2) + kMaxIntervals + 1;   // double2 slots
+constexpr int kStageRegs = (kStageSlots + kTileThreads - 1) / kTileThreads;
+constexpr int kPlan = 64;                            // candidates planned at once (one wave)
+constexpr int kSegMax = 3;                           // segments of one round (kMaxIntervals * kPieces pieces)
+constexpr int kMaxRec = kSegMax * kPlan;
+constexpr int kChunkMax = (kTileEl + kTileThreads - 1) / kTileThreads;   // sorted points of one lane
+static_assert((kStage - 1) * (kSegMax - 1) + kStage >= kMaxIntervals * kPieces, "segments cover a kernel");
+static_assert(kSegMax == 3, "the record compaction counts three slots");
+
+// One record: the sorted range [s0, s1) of a round (k, i) = kernel f, whose pieces
+// g0 .. g0 + np - 1 (kernel-local g0l; absolute g0) cover it; last = 1 on a round's last segment.
+struct TileRec {
+    int32_t f;
+    int32_t g0;
+    uint32_t s;      // s0 | s1 << 11 | (np - 1) << 22 | nint << 28
+    uint32_t ki;     // k | i << 13 | last << 26
+    int32_t g0l;
+    int32_t bpo;     // the kernel's first interval start in ivl
+};
 
 struct TileLds {
     double key[kTileSort];
-    double R[2][kTileR];             // R_b(q, pair) = sum_q' lam_b(q') psi w/r; T(pair) = sum tpsi w/r
+    double2 V[kTileEl];              // (psi w/r, tpsi w/r) of every point pair; zero off the support
+    double2 stage[kStageSlots];      // 15 np coefficients, 2 np piece records, intervals, (lo, hi)
     double acc[kTileVt * kTileVs];
     double alpha[kTilePairs];        // (n_tau . n_sigma) |tau||sigma| / (4 pi)
     double beta[kTilePairs * 9];     // C_ab |tau||sigma| / (4 pi), entry e = 3a + b
-    uint16_t aoff[kTilePairs * 9];   // entry (v_a(tau), v_b(sigma)) of the merged vertex tile
     double wqq[49];                  // w_q w_q'
     double lam[7 * 3];               // lam_b(q')
     double pmin[kTilePairs], pmax[kTilePairs];
-    uint16_t idx[kTileSort];
+    TileRec rec[kMaxRec];
+    int32_t bcum[kTileThreads + 1];  // candidates of the k-block: exclusive prefix over k
+    int32_t bia[kTileThreads];       // first trial index of each k's band
+    uint16_t idx[kTileSort];         // point pair p * 49 + 7 q + q' of each sorted distance
+    uint16_t aoff[kTilePairs * 9];   // entry (v_a(tau), v_b(sigma)) of the merged vertex tile
     int32_t vt[kTileVt], vs[kTileVs];
     int32_t pok[kTilePairs];
-    int32_t nvt, nvs;
+    int32_t nvt, nvs, nrec;
+    int32_t wtot[kTileThreads / 64];
 };
 
-template <bool MIXED>
-__global__ void __launch_bounds__(kTileThreads, 4)
+// Number of keys <= v (le) or < v among the ascending key[0..n), one lane.
+__device__ inline int lane_count_below(const double* key, int n, double v, bool le)
+{
+    int a = 0, b = n;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (le ? key[m] <= v : key[m] < v) a = m + 1;
+        else b = m;
+    }
+    return a;
+}
+
+// Kernel-local piece j * kPieces + p holding r: the interval from its starts, the piece from the
+// graded partition (lookup table, one correction).  Rounding can put r one piece early at a
+// boundary; callers move on through the piece records.
+__device__ inline int piece_local(double r, const double2* iv, int nint, const PieceTable& pt)
+{
+    int j = 0;
+    for (int m = 1; m < nint; ++m) j += r >= iv[m].x ? 1 : 0;
+    double fr = (r - iv[j].x) * iv[j].y;
+    fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+    int cell = (int)(fr * kLutCells);
+    cell = cell < kLutCells ? cell : kLutCells - 1;
+    int p = pt.lut[cell];
+    if (p + 1 < kPieces && fr >= pt.edge[p + 1]) ++p;
+    return j * kPieces + p;
+}
+
+// DPP moves inside groups of 8 lanes: xor 1, xor 2 (quad permutations), mirror within 8.
+template <int CTRL>
+__device__ inline double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo));
+}
+__device__ inline double group8_sum_dpp(double v)
+{
+    v += dpp_move<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);    // row_half_mirror
+    return v;
+}
+
+// Loads the LDS stage of record R into registers (slot e = tid + kTileThreads m).
+__device__ inline void stage_fetch(const TileRec& R, const TableView& tv, double2 (&st)[kStageRegs])
+{
+    const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+    const int nc = kNc * np, nm = nc + 2 * np, ni = nm + nint;
+    const double2* meta2 = reinterpret_cast<const double2*>(tv.meta);
+    const double2* ivl2 = reinterpret_cast<const double2*>(tv.ivl);
+#pragma unroll
+    for (int m = 0; m < kStageRegs; ++m) {
+        const int e = threadIdx.x + kTileThreads * m;
+        double2 v = make_double2(0.0, 0.0);
+        if (e < nc) v = tv.coef[(int64_t)R.g0 * kNc + e];
+        else if (e < nm) v = meta2[2 * (int64_t)R.g0 + (e - nc)];
+        else if (e < ni) v = ivl2[(R.bpo >> 1) + (e - nm)];
+        else if (e == ni) v = reinterpret_cast<const double2*>(tv.desc + R.f)[0];
+        st[m] = v;
+    }
+}
+
+__device__ inline void stage_store(const TileRec& R, double2* stage, const double2 (&st)[kStageRegs])
+{
+    const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+    const int used = (kNc + 2) * np + nint + 1;
+#pragma unroll
+    for (int m = 0; m < kStageRegs; ++m) {
+        const int e = threadIdx.x + kTileThreads * m;
+        if (e < used) stage[e] = st[m];
+    }
+}
+
+__global__ void __launch_bounds__(kTileThreads, 2)
 k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
-               ProductView pv, double r_far, const int2* __restrict__ tiles, int64_t ntiles,
-               unsigned long long* counter)
+               ProductView pv, const int2* __restrict__ tiles, int64_t ntiles, unsigned long long* counter)
 {
     // consecutive workgroups go to the 8 XCDs in turn: give each XCD one contiguous range of the
     // tile list (same test rows, shared L2 lines for the output)
@@ -301,7 +390,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
     const int2 tl = tiles[tix];
     const int E = g.E;
     const int tau0 = tl.x * kTileT, sig0 = tl.y * kTileS;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     __shared__ PieceTable spt;
     __shared__ TileLds L;
@@ -350,7 +439,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
         }
         L.pok[p] = ok ? 1 : 0;
     }
-    for (int z = tid; z < 2 * kTileR; z += kTileThreads) (&L.R[0][0])[z] = 0.0;
+    for (int z = tid; z < kTileEl; z += kTileThreads) L.V[z] = make_double2(0.0, 0.0);
     for (int z = tid; z < kTileVt * kTileVs; z += kTileThreads) L.acc[z] = 0.0;
     __syncthreads();
     for (int e = tid; e < kTileSort; e += kTileThreads) {
@@ -366,10 +455,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
             }
         }
         L.key[e] = r;
-        {
-            const int p = e / 49, qq = e - 49 * p;
-            L.idx[e] = (uint16_t)((p << 6) | ((qq / 7) << 3) | (qq % 7));
-        }
+        L.idx[e] = (uint16_t)(e < kTileEl ? e : 0);
     }
     __syncthreads();
     // distance range of every pair (8 lanes per pair, lane m < 7 scans the row q = m)
@@ -437,137 +523,323 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
             L.aoff[9 * gp + e] = (uint16_t)off;
         }
     }
-    __syncthreads();
 
     const int N = tv.N;
-    double2 cc[kNc];            // coefficients of the lane's current piece
-    double rhi = -1.0, rc = 0.0, ra = 0.0;
-    int64_t pcur = -1;
-    bool c32 = false;
     unsigned long long nq = 0;
-    int buf = 0;
-    int ia = 0, ib = -1;
-    for (int k = 0; k < N; ++k) {
-        while (ia < N) {
-            double lo, hi;
-            kernel_support(t, tv.nodes, tv.p1, k, ia, lo, hi);
-            if (lo < wmax) break;
-            ++ia;
-        }
-        while (ib + 1 < N) {
-            double lo, hi;
-            kernel_support(t, tv.nodes, tv.p1, k, ib + 1, lo, hi);
-            if (!(hi > wmin)) break;
-            ++ib;
-        }
-        for (int i = ia; i <= ib; ++i) {
-            const int f = __builtin_amdgcn_readfirstlane(tv.fid[k * N + i]);
-            if (f < 0) continue;
-            const KernelDesc kd = tv.desc[f];
-            const int s0 = __builtin_amdgcn_readfirstlane(wave_count_below(L.key, nvalid, kd.lo, true));
-            const int s1 = __builtin_amdgcn_readfirstlane(wave_count_below(L.key, nvalid, kd.hi, false));
-            if (s1 <= s0) continue;
-            const int n = s1 - s0;
-            const int C = (n + kTileThreads - 1) / kTileThreads;
-            const int u1 = min(n, (tid + 1) * C);
-            double* __restrict__ Rb = L.R[buf];
-            rhi = -1.0;                                  // new kernel: no cached piece
-            pcur = -1;
-            if (MIXED) {
-                // mixed precision, decided for the whole wave: FP32 series when every distance
-                // of the wave's stretch is in the far field and away from the two flat ends of
-                // the support (the first half of the first interval, the second half of the
-                // last), FP64 otherwise
-                const int wa = (tid & ~63) * C, wb = min(n, ((tid & ~63) + 64) * C);
-                const double* iv = tv.ivl + kd.bp_off;
-                const double lo_end = iv[0] + 0.5 / iv[1];
-                const double hi_start = iv[2 * (kd.nint - 1)] + 0.5 / iv[2 * kd.nint - 1];
-                c32 = wa < wb && L.key[s0 + wa] >= r_far && L.key[s0 + wa] >= lo_end && L.key[s0 + wb - 1] < hi_start;
-            }
-            for (int u = tid * C; u < u1; ++u) {
-                const int s = s0 + u;
-                const double r = L.key[s];
-                const int code = L.idx[s];
-                if (r >= rhi) {
-                    // the lane's next piece: the first one from the cell table (new kernel), else
-                    // the one after the current piece; advance while r lies beyond its end
-                    int64_t g;
-                    if (pcur < 0) {
-                        int cl = (int)((r - kd.lo) * kd.cell_scale);
-                        cl = cl < 0 ? 0 : (cl < kCells ? cl : kCells - 1);
-                        g = kd.coef_off / kNc + tv.cell[kd.cell_off + cl];
-                    } else {
-                        g = pcur + 1;
-                    }
-                    double4 mt = tv.meta[g];
-                    while (r >= mt.x) mt = tv.meta[++g];
-                    pcur = g;
-                    rhi = mt.x;
-                    rc = mt.y;
-                    ra = mt.z;
-                    const int64_t off = g * kNc;
-                    // mixed precision: far-field pieces away from the two ends of the support
-                    // evaluate the FP32 copy of the series
-                    if (MIXED && c32) {
+    // lam_a(q) of the lane's phase-2 entry (a, b) = (gm / 3, gm % 3)
+    double la[7];
 #pragma unroll
-                        for (int m = 0; m < kNc; ++m) {
-                            const float2 v = tv.coef32[off + m];
-                            cc[m].x = __longlong_as_double((long long)(((uint64_t)__float_as_uint(v.y) << 32) |
-                                                                       (uint64_t)__float_as_uint(v.x)));
+    for (int q = 0; q < 7; ++q) {
+        double l0, l1, l2, w;
+        rule7_point(q, l0, l1, l2, w);
+        la[q] = gm < 3 ? l0 : (gm < 6 ? l1 : l2);
+    }
+    // band addresses of the lane's entries z = tid, tid + 256 of the merged vertex tile (time row kcur)
+    int kcur = -1;
+    int dz_ilo[2] = {0, 0}, dz_B[2] = {0, 0}, dz_lj[2] = {0, 0};
+    int64_t dz_vo[2] = {0, 0};
+    for (int kb = 0; kb < N; kb += kTileThreads) {
+        // band [ia, ib] of every k of the block: supp psi_{k,i} meets (wmin, wmax); both ends of the
+        // support are non-increasing in i, so both ends of the band are binary searches
+        {
+            const int k = kb + tid;
+            int ia = 0, cnt = 0;
+            if (k < N) {
+                int a = 0, b = N;
+                while (a < b) {
+                    const int m = (a + b) >> 1;
+                    double lo, hi;
+                    kernel_support(t, tv.nodes, tv.p1, k, m, lo, hi);
+                    if (lo < wmax) b = m;
+                    else a = m + 1;
+                }
+                ia = a;
+                a = 0;
+                b = N;
+                while (a < b) {
+                    const int m = (a + b) >> 1;
+                    double lo, hi;
+                    kernel_support(t, tv.nodes, tv.p1, k, m, lo, hi);
+                    if (hi > wmin) a = m + 1;
+                    else b = m;
+                }
+                cnt = a - 1 >= ia ? a - ia : 0;
+            }
+            // exclusive prefix over the block
+            int inc = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += v;
+            }
+            if (lane == 63) L.wtot[wave] = inc;
+            __syncthreads();
+            int off = 0;
+            for (int w = 0; w < wave; ++w) off += L.wtot[w];
+            L.bcum[tid] = off + inc - cnt;
+            L.bia[tid] = ia;
+            if (tid == kTileThreads - 1) L.bcum[kTileThreads] = off + inc;
+            __syncthreads();
+        }
+        const int total = L.bcum[kTileThreads];
+        for (int c0 = 0; c0 < total; c0 += kPlan) {
+            if (wave == 0) {
+                // plan: lane = candidate c0 + lane
+                TileRec out[kSegMax];
+                bool ok[kSegMax];
+#pragma unroll
+                for (int m = 0; m < kSegMax; ++m) ok[m] = false;
+                const int c = c0 + lane;
+                if (c < total) {
+                    int a = 0, b = kTileThreads;       // last block slot with bcum <= c
+                    while (b - a > 1) {
+                        const int m = (a + b) >> 1;
+                        if (L.bcum[m] <= c) a = m;
+                        else b = m;
+                    }
+                    const int k = kb + a, i = L.bia[a] + (c - L.bcum[a]);
+                    const int f = tv.fid[(int64_t)k * N + i];
+                    if (f >= 0) {
+                        const KernelDesc kd = tv.desc[f];
+                        const int s0 = lane_count_below(L.key, nvalid, kd.lo, true);
+                        const int s1 = lane_count_below(L.key, nvalid, kd.hi, false);
+                        if (s1 > s0) {
+                            const double2* iv = reinterpret_cast<const double2*>(tv.ivl + kd.bp_off);
+                            const int base = (int)(kd.coef_off / kNc), npc = kd.nint * kPieces;
+                            int ga = piece_local(L.key[s0], iv, kd.nint, spt);
+                            int gl = piece_local(L.key[s1 - 1], iv, kd.nint, spt) + 1;
+                            gl = gl < npc ? gl : npc - 1;
+                            int sa = s0;
+                            bool done = false;
+#pragma unroll
+                            for (int sg = 0; sg < kSegMax; ++sg) {
+                                if (done) continue;
+                                int sb = s1, np = gl - ga + 1, last = 1;
+                                if (np > kStage && sg + 1 < kSegMax) {
+                                    np = kStage;
+                                    const double rs = tv.meta[base + ga + kStage - 1].x;
+                                    sb = lane_count_below(L.key, nvalid, rs, false);
+                                    if (sb < s1) last = 0;
+                                    else sb = s1;
+                                }
+                                np = np < kStage ? np : kStage;
+                                if (sb > sa) {
+                                    TileRec& R = out[sg];
+                                    R.f = f;
+                                    R.g0 = base + ga;
+                                    R.s = (uint32_t)sa | ((uint32_t)sb << 11) | ((uint32_t)(np - 1) << 22) |
+                                          ((uint32_t)kd.nint << 28);
+                                    R.ki = (uint32_t)k | ((uint32_t)i << 13) | ((uint32_t)last << 26);
+                                    R.g0l = ga;
+                                    R.bpo = kd.bp_off;
+                                    ok[sg] = true;
+                                }
+                                if (last) {
+                                    done = true;
+                                } else {
+                                    sa = sb;
+                                    ga = piece_local(L.key[sa], iv, kd.nint, spt);
+                                }
+                            }
                         }
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < kNc; ++m) cc[m] = tv.coef[off + m];
                     }
                 }
-                const double x = (r - rc) * ra;
-                double ps, pt;
-                if (MIXED && c32) {
-                    float fps, fpt;
-                    cheb_sums_f32(cc, (float)x, fps, fpt);
-                    ps = fps;
-                    pt = fpt;
-                } else {
-                    cheb_sums(cc, x, ps, pt);
-                }
-                const int pr = code >> 6, q = (code >> 3) & 7, qp = code & 7;
-                const double w = L.wqq[7 * q + qp] * recip(r);
-                const double P = ps * w;
-                double* Rq = Rb + q * 3 * kTilePairs + pr;
-                atomicAdd(Rq, P * L.lam[3 * qp]);
-                atomicAdd(Rq + kTilePairs, P * L.lam[3 * qp + 1]);
-                atomicAdd(Rq + 2 * kTilePairs, P * L.lam[3 * qp + 2]);
-                atomicAdd(Rb + 21 * kTilePairs + pr, pt * w);
-            }
-            if (u1 > tid * C) nq += (unsigned long long)(u1 - tid * C);
-            __syncthreads();
-            // the other buffer was read by the previous (k, i): clear it for the next one
-            for (int z = tid; z < kTileR; z += kTileThreads) L.R[buf ^ 1][z] = 0.0;
-            if (L.pok[gp] && L.pmax[gp] > kd.lo && L.pmin[gp] < kd.hi) {
-                const double* Rp = Rb + gp;
-                const int ea = gm / 3, eb = gm % 3;
-                double Sm = 0.0, S8 = 0.0;
+                // order-preserving compaction (at most 3 records a lane: two ballots)
+                const int nr = (ok[0] ? 1 : 0) + (ok[1] ? 1 : 0) + (ok[2] ? 1 : 0);
+                const uint64_t b0 = __ballot(nr & 1), b1 = __ballot(nr & 2);
+                const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+                int pos = __popcll(b0 & below) + 2 * __popcll(b1 & below);
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    double l0, l1, l2, w;
-                    rule7_point(q, l0, l1, l2, w);
-                    Sm = fma(ea == 0 ? l0 : (ea == 1 ? l1 : l2), Rp[(3 * q + eb) * kTilePairs], Sm);
-                    S8 = fma(l2, Rp[(3 * q + 2) * kTilePairs], S8);
-                }
-                const double ST = Rp[21 * kTilePairs], al = L.alpha[gp];
-                atomicAdd(&L.acc[L.aoff[9 * gp + gm]], fma(al, Sm, L.beta[9 * gp + gm] * ST));
-                if (gm == 0) atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * ST));
+                for (int m = 0; m < kSegMax; ++m)
+                    if (ok[m]) L.rec[pos++] = out[m];
+                if (lane == 0) L.nrec = __popcll(b0) + 2 * __popcll(b1);
             }
             __syncthreads();
-            for (int z = tid; z < kTileVt * kTileVs; z += kTileThreads) {
-                const double v = L.acc[z];
-                if (v != 0.0) {
-                    const int a = z / kTileVs, b = z - kTileVs * a;
-                    deposit(band, val, valf, pv, k, i, L.vt[a], L.vs[b], v);
-                    L.acc[z] = 0.0;
+            const int nrec = L.nrec;
+            if (nrec == 0) {
+                __syncthreads();                     // every wave has read nrec before the next plan
+                continue;
+            }
+            double2 st[kStageRegs];
+            {
+                const TileRec R0 = L.rec[0];
+                stage_fetch(R0, tv, st);
+                stage_store(R0, L.stage, st);
+            }
+            __syncthreads();
+            for (int n = 0; n < nrec; ++n) {
+                const TileRec R = L.rec[n];
+                const int s0 = (int)(R.s & 2047u), s1 = (int)((R.s >> 11) & 2047u);
+                const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+                const int k = (int)(R.ki & 8191u), i = (int)((R.ki >> 13) & 8191u);
+                const bool last = (R.ki >> 26) & 1u;
+                const double2* sc = L.stage;
+                const double2* sm = L.stage + kNc * np;
+                const double2* si = sm + 2 * np;
+                const double2 lohi = si[nint];
+                const bool more = n + 1 < nrec;
+                if (more) stage_fetch(L.rec[n + 1], tv, st);
+                if (!pv.y && k != kcur) {
+                    // band addresses of the lane's entries of the merged vertex tile for time row k;
+                    // the loads complete while the record is evaluated
+                    kcur = k;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int z = tid + h * kTileThreads;
+                        dz_B[h] = 0;
+                        if (z < kTileVt * kTileVs) {
+                            const int a = z / kTileVs, b = z - kTileVs * a;
+                            if (a < L.nvt && b < L.nvs) {
+                                int l = L.vt[a], j = L.vs[b];
+                                if (j > l) { const int tmp = j; j = l; l = tmp; }
+                                const int64_t tix = (int64_t)k * band.nt + band_tile(l, j);
+                                dz_ilo[h] = band.ilo[band_ilo_index(band, k, l, j)];
+                                dz_B[h] = band.B[tix];
+                                dz_vo[h] = band.voff[tix];
+                                dz_lj[h] = (l % kBT) | ((j % kBT) << 8) | ((l == j ? 1 : 0) << 16);
+                            }
+                        }
+                    }
+                }
+
+                // phase 1: the lane's chunk of sorted points, held in registers
+                const int npt = s1 - s0;
+                const int C = (npt + kTileThreads - 1) / kTileThreads;
+                const int u0 = tid * C;
+                const int cnt = max(0, min(npt - u0, C));
+                double rr[kChunkMax];
+                int cd[kChunkMax];
+#pragma unroll
+                for (int m = 0; m < kChunkMax; ++m) {
+                    rr[m] = 0.0;
+                    cd[m] = 0;
+                    if (m < cnt) {
+                        rr[m] = L.key[s0 + u0 + m];
+                        cd[m] = L.idx[s0 + u0 + m];
+                    }
+                }
+                if (cnt > 0) {
+                    int rel = piece_local(rr[0], si, nint, spt) - R.g0l;
+                    rel = rel < 0 ? 0 : (rel < np ? rel : np - 1);
+                    double rhi = sm[2 * rel].x;
+                    while (rr[0] >= rhi && rel + 1 < np) rhi = sm[2 * ++rel].x;
+                    double rc = sm[2 * rel].y, ra = sm[2 * rel + 1].x;
+                    double2 cc[kNc];
+                    auto load_piece = [&]() {
+#pragma unroll
+                        for (int m = 0; m < kNc; ++m) cc[m] = sc[rel * kNc + m];
+                    };
+                    load_piece();
+#pragma unroll
+                    for (int m = 0; m < kChunkMax; ++m) {
+                        if (m < cnt) {
+                            const double r = rr[m];
+                            if (r >= rhi && rel + 1 < np) {
+                                // sorted neighbours: almost always the next piece, read with its
+                                // coefficients in one round trip
+                                ++rel;
+                                const double2 ma = sm[2 * rel], mb = sm[2 * rel + 1];
+                                load_piece();
+                                rhi = ma.x;
+                                rc = ma.y;
+                                ra = mb.x;
+                                if (r >= rhi && rel + 1 < np) {
+                                    do {
+                                        rhi = sm[2 * ++rel].x;
+                                    } while (r >= rhi && rel + 1 < np);
+                                    rc = sm[2 * rel].y;
+                                    ra = sm[2 * rel + 1].x;
+                                    load_piece();
+                                }
+                            }
+                            const double x = (r - rc) * ra;
+                            double ps, pt;
+                            cheb_sums(cc, x, ps, pt);
+                            const int code = cd[m];
+                            const int qq = code - 49 * (code / 49);
+                            const double w = L.wqq[qq] * recip(r);
+                            L.V[code] = make_double2(ps * w, pt * w);
+                        }
+                    }
+                    nq += (unsigned long long)cnt;
+                }
+                __syncthreads();
+                if (more) stage_store(L.rec[n + 1], L.stage, st);
+                if (last) {
+                    // phase 2: lane (pair gp, row q = gm < 7) sums its row over q' into
+                    // (R_0, R_1, R_2, T)(q), kept in the row's first two slots; lane gm then forms
+                    // entry (a, b) = (gm / 3, gm % 3) (lane 0 also entry 8) over the 7 rows.  The
+                    // 8 lanes of a pair belong to one wave.
+                    const bool act = L.pok[gp] && L.pmax[gp] > lohi.x && L.pmin[gp] < lohi.y;
+                    if (act) {
+                        double2* prow = L.V + gp * 49;
+                        if (gm < 7) {
+                            double2* row = prow + gm * 7;
+                            double R0 = 0.0, R1 = 0.0, R2 = 0.0, T = 0.0;
+#pragma unroll
+                            for (int qp = 0; qp < 7; ++qp) {
+                                const double2 v = row[qp];
+                                double l0, l1, l2, w;
+                                rule7_point(qp, l0, l1, l2, w);
+                                R0 = fma(l0, v.x, R0);
+                                R1 = fma(l1, v.x, R1);
+                                R2 = fma(l2, v.x, R2);
+                                T += v.y;
+                            }
+                            row[0] = make_double2(R0, R1);
+                            row[1] = make_double2(R2, T);
+#pragma unroll
+                            for (int qp = 2; qp < 7; ++qp) row[qp] = make_double2(0.0, 0.0);
+                        }
+                        __threadfence_block();
+                        const int eb = gm - 3 * (gm / 3);
+                        double S = 0.0, S8 = 0.0, T = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 7; ++q) {
+                            const double* rq = reinterpret_cast<const double*>(prow + q * 7);
+                            double l0, l1, l2, w;
+                            rule7_point(q, l0, l1, l2, w);
+                            S = fma(la[q], rq[eb], S);
+                            S8 = fma(l2, rq[2], S8);
+                            T += rq[3];
+                        }
+                        __threadfence_block();
+                        if (gm < 7) {
+                            double2* row = prow + gm * 7;
+                            row[0] = make_double2(0.0, 0.0);
+                            row[1] = make_double2(0.0, 0.0);
+                        }
+                        const double al = L.alpha[gp];
+                        atomicAdd(&L.acc[L.aoff[9 * gp + gm]], fma(al, S, L.beta[9 * gp + gm] * T));
+                        if (gm == 0) atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * T));
+                    }
+                }
+                __syncthreads();
+                if (last) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int z = tid + h * kTileThreads;
+                        if (z < kTileVt * kTileVs) {
+                            const double v = L.acc[z];
+                            if (v != 0.0) {
+                                if (pv.y) {
+                                    const int a = z / kTileVs, b = z - kTileVs * a;
+                                    deposit(band, val, valf, pv, k, i, L.vt[a], L.vs[b], v);
+                                } else if (dz_B[h] > 0) {
+                                    const int s = i - dz_ilo[h];
+                                    if (s >= 0 && s < dz_B[h]) {
+                                        const int lr = dz_lj[h] & 255, jr = (dz_lj[h] >> 8) & 255;
+                                        const int64_t idx = dz_vo[h] + ((int64_t)lr * dz_B[h] + s) * kBT + jr;
+                                        const double vv = (dz_lj[h] >> 16) ? 2.0 * v : v;
+                                        if (valf) atomicAdd(valf + idx, (float)vv);
+                                        else atomicAdd(val + idx, vv);
+                                    }
+                                }
+                                L.acc[z] = 0.0;
+                            }
+                        }
+                    }
                 }
             }
-            buf ^= 1;
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
@@ -847,18 +1119,14 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
 }
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    const double* px, double* py, double r_far, const int2* tiles, int64_t ntiles,
-                    unsigned long long* counter, hipStream_t s)
+                    const double* px, double* py, const int2* tiles, int64_t ntiles, unsigned long long* counter,
+                    hipStream_t s)
 {
     if (ntiles <= 0) return;
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
     const ProductView pv{px, py, band.M};
-    if (valf)
-        hipLaunchKernelGGL(k_regular_tile<true>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv, r_far,
-                           tiles, ntiles, counter);
-    else
-        hipLaunchKernelGGL(k_regular_tile<false>, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv,
-                           r_far, tiles, ntiles, counter);
+    hipLaunchKernelGGL(k_regular_tile, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv, tiles, ntiles,
+                       counter);
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau, in

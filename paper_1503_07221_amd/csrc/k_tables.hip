@@ -82,8 +82,7 @@ k_table_values(const double* __restrict__ t, int N, int p1, int cut, TimeRule ru
 }
 
 __global__ void __launch_bounds__(256)
-k_table_coefs(const double2* __restrict__ values, int64_t npieces, double2* __restrict__ coef,
-              float2* __restrict__ coef32)
+k_table_coefs(const double2* __restrict__ values, int64_t npieces, double2* __restrict__ coef)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= npieces * kNc) return;
@@ -98,7 +97,6 @@ k_table_coefs(const double2* __restrict__ values, int64_t npieces, double2* __re
     }
     const double s = (m == 0 ? 1.0 : 2.0) / kNc;
     coef[gid] = make_double2(a * s, b * s);
-    coef32[gid] = make_float2((float)(a * s), (float)(b * s));
 }
 
 __global__ void __launch_bounds__(256)
@@ -132,11 +130,10 @@ void launch_table_values(const double* t, int N, int p1, int cut, TimeRule rule,
                        pc_f, pc_j, pc_p, npieces, f_k, f_i, desc, ivl, values);
 }
 
-void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, float2* coef32, hipStream_t s)
+void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, hipStream_t s)
 {
     if (npieces <= 0) return;
-    hipLaunchKernelGGL(k_table_coefs, dim3(grid_for(npieces * kNc, 256)), dim3(256), 0, s, values, npieces, coef,
-                       coef32);
+    hipLaunchKernelGGL(k_table_coefs, dim3(grid_for(npieces * kNc, 256)), dim3(256), 0, s, values, npieces, coef);
 }
 
 void launch_table_eval(TableView tv, int64_t n, const int32_t* k, const int32_t* i, const double* r, double* ps,

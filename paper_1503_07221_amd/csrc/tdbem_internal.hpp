@@ -179,30 +179,12 @@ struct TableView {
     const int32_t* fid;       // fid[k*N + i]: index into desc or -1 (identically zero kernel), N = L
     const double* ivl;        // interval starts and inverse lengths
     const double2* coef;      // Chebyshev coefficients (psi, tpsi)
-    const float2* coef32;     // the same rounded to FP32 (mixed precision far field)
     const double4* meta;      // per-piece record (rhi, rc, ra, near)
     const uint16_t* cell;     // cell table
     int32_t N;                // temporal bases L = nodes (p + 1)
     int32_t nodes, p1;        // time nodes and bases per node
     PieceTable pt;
 };
-
-// Clenshaw in FP32 for the mixed-precision far field.
-__device__ inline void clenshaw2_f32(const float2* __restrict__ c, float x, float& ps, float& pt)
-{
-    const float x2 = 2.0f * x;
-    float a1 = 0.0f, a2 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-#pragma unroll
-    for (int m = kDeg; m >= 1; --m) {
-        const float2 cm = c[m];
-        const float a0 = fmaf(x2, a1, cm.x - a2);
-        const float b0 = fmaf(x2, b1, cm.y - b2);
-        a2 = a1; a1 = a0; b2 = b1; b1 = b0;
-    }
-    const float2 c0 = c[0];
-    ps = fmaf(x, a1, c0.x - a2);
-    pt = fmaf(x, b1, c0.y - b2);
-}
 
 // Gauss-Legendre rule on [-1, 1] used for every time integral of the library.
 constexpr int kTimeGauss = 20;
@@ -325,7 +307,7 @@ void launch_table_values(const double* t, int N, int p1, int cut, TimeRule rule,
                          const int32_t* pc_j, const int32_t* pc_p, int64_t npieces, const int32_t* f_k,
                          const int32_t* f_i, const KernelDesc* desc, const double* ivl, double2* values,
                          hipStream_t s);
-void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, float2* coef32, hipStream_t s);
+void launch_table_coefs(const double2* values, int64_t npieces, double2* coef, hipStream_t s);
 void launch_table_eval(TableView tv, int64_t n, const int32_t* k, const int32_t* i, const double* r,
                        double* ps, double* tps, hipStream_t s);
 
@@ -335,8 +317,8 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
                    int32_t* Bk, hipStream_t s);
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    const double* px, double* py, double r_far, const int2* tiles, int64_t ntiles,
-                    unsigned long long* counter, hipStream_t s);
+                    const double* px, double* py, const int2* tiles, int64_t ntiles, unsigned long long* counter,
+                    hipStream_t s);
 std::vector<int32_t> regular_tiles(int E);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,

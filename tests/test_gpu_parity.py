@@ -3,8 +3,8 @@
 Tolerances: blocks of eq. (MatrixEntries) to 1e-11 relative per block (max norm); the time
 kernel tables to 1e-11 (psi) and 1e-12 (tilde psi) of each kernel's maximum; RHS and matvec to
 1e-13; solves to their residual tolerance.  Integer work (quadrature-point counts) is exact.
-The mixed-precision form (FP32 series on far-field pieces, FP32 storage, FP64 singular pairs,
-sums and solver) is held to MIXED_TOL relative per block.
+The mixed-precision form (FP64 quadrature, FP32 storage of the assembled entries, FP64 solver) is
+held to MIXED_TOL relative per block.
 """
 import numpy as np
 import pytest
@@ -15,8 +15,8 @@ from workloads import equidistant_grid, graded_grid, get_config, icosphere, toru
 pytestmark = pytest.mark.gpu
 
 BLOCK_TOL = 1e-11
-# FP32 storage rounds every entry (2^-24 relative) and the far-field series run in FP32: the
-# sum of a few hundred FP32-rounded terms of one sign, ~1e-6 of the block maximum at worst
+# FP32 storage rounds the contributions of every tile into its entries (2^-24 relative each, a
+# few dozen FP32 additions per entry): ~1e-6 of the block maximum at worst
 MIXED_TOL = 2e-6
 
 
