@@ -1733,6 +1733,91 @@ tdbem_status update_deflation(SolveCtx& S, const std::vector<double>& Hraw, int 
 // Solve A[a:b, a:b] x = rhs.  depth indexes the workspace; the preconditioner of a solve at
 // depth d (level d in Algorithm 1 numbering, the outer solve being depth 0) runs its inner
 // solves at depth d + 1.
+// An inner solve of Algorithm 1: a fixed number m of flexible Arnoldi steps from x = 0, queued
+// without a host round trip; the Hessenberg columns (both Gram-Schmidt passes and |w|^2) stay on
+// the device until the end, where one copy brings them to the host for the Givens rotations and
+// the triangular solve.  The result equals the step-by-step form: the solution is taken at the
+// first step whose residual estimate meets the tolerance, or at a breakdown (|w| = 0, after which
+// the queued steps see zero vectors).
+tdbem_status fgmres_fixed(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int m, int* its_out,
+                          double* rel_out)
+{
+    tdbem_ctx* c = S.c;
+    hipStream_t st = c->stream;
+    const int64_t n = (int64_t)(b - a) * c->M;
+    tdbem_ctx::Level& L = c->levels[depth];
+    const bool alg1 = depth < S.levels && (b - a) > c->p1;
+    double* V = L.V.as<double>();
+    double* Z = alg1 ? L.Z.as<double>() : V;
+    const int hs = 2 * (m + 1) + 1;           // column j: [0, j] h1, [m+1, m+1+j] h2, [2m+2] |w|^2
+    double* Hd = L.h.as<double>();
+    double* bn2d = Hd + (size_t)m * hs;
+    double* part = L.partial.as<double>();
+    launch_fill(x, 0.0, n, st);
+    launch_dots(rhs, 1, n, n, rhs, part, bn2d, st);
+    launch_scale_inv_sqrt(V, rhs, bn2d, n, st);     // v_0 = rhs / ||rhs|| (zero for rhs = 0)
+    for (int j = 0; j < m; ++j) {
+        double* vj = V + (int64_t)j * n;
+        double* zj = Z + (int64_t)j * n;
+        double* w = V + (int64_t)(j + 1) * n;
+        double* hc = Hd + (size_t)j * hs;
+        if (alg1) TRY(apply_precond(S, depth + 1, depth + 1, a, b, vj, zj));
+        TRY(solver_matvec(S, depth, a, b, a, b, zj, w));
+        launch_dots(V, j + 1, n, n, w, part, hc, st);
+        launch_sub_combination(w, V, j + 1, n, n, hc, -1.0, st);
+        launch_dots(V, j + 1, n, n, w, part, hc + (m + 1), st);
+        launch_sub_combination(w, V, j + 1, n, n, hc + (m + 1), -1.0, st);
+        launch_dots(w, 1, n, n, w, part, hc + 2 * (m + 1), st);
+        launch_scale_inv_sqrt(w, w, hc + 2 * (m + 1), n, st);
+        HIPCHK(c, hipGetLastError());
+    }
+    std::vector<double> hb((size_t)m * hs + 1);
+    HIPCHK(c, hipMemcpyAsync(hb.data(), Hd, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(std::max(hb[(size_t)m * hs], 0.0));
+    *its_out = 0;
+    if (bnorm == 0.0) {
+        *rel_out = 0.0;
+        return TDBEM_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1, 0.0);
+    gv[0] = bnorm;
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+        const double* hc = hb.data() + (size_t)j * hs;
+        for (int q = 0; q <= j; ++q) H[(size_t)q * m + j] = hc[q] + hc[m + 1 + q];
+        const double hn = std::sqrt(std::max(hc[2 * (m + 1)], 0.0));
+        H[(size_t)(j + 1) * m + j] = hn;
+        for (int q = 0; q < j; ++q) {
+            const double t1 = cs[q] * H[(size_t)q * m + j] + sn[q] * H[(size_t)(q + 1) * m + j];
+            H[(size_t)(q + 1) * m + j] = -sn[q] * H[(size_t)q * m + j] + cs[q] * H[(size_t)(q + 1) * m + j];
+            H[(size_t)q * m + j] = t1;
+        }
+        const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+        cs[j] = den != 0.0 ? H[(size_t)j * m + j] / den : 1.0;
+        sn[j] = den != 0.0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
+        H[(size_t)j * m + j] = cs[j] * H[(size_t)j * m + j] + sn[j] * H[(size_t)(j + 1) * m + j];
+        H[(size_t)(j + 1) * m + j] = 0.0;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        jdone = j + 1;
+        if (std::fabs(gv[j + 1]) <= S.tol * bnorm || hn == 0.0) break;
+    }
+    std::vector<double> y(jdone);
+    for (int q = jdone - 1; q >= 0; --q) {
+        double s = gv[q];
+        for (int u = q + 1; u < jdone; ++u) s -= H[(size_t)q * m + u] * y[u];
+        y[q] = s / H[(size_t)q * m + q];
+    }
+    HIPCHK(c, hipMemcpyAsync(Hd, y.data(), sizeof(double) * jdone, hipMemcpyHostToDevice, st));
+    launch_sub_combination(x, Z, jdone, n, n, Hd, 1.0, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    *its_out = jdone;
+    *rel_out = std::fabs(gv[jdone]) / bnorm;
+    return TDBEM_OK;
+}
+
 tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, double* x, int max_it, bool inner,
                     int* its_out, double* rel_out)
 {
@@ -1748,6 +1833,7 @@ tdbem_status fgmres(SolveCtx& S, int depth, int a, int b, const double* rhs, dou
     double* dbuf = L.h.as<double>();          // [0, m+1): h1, [m+1, 2m+2): h2, [2m+2]: |w|^2
     double* part = L.partial.as<double>();
     *its_out = 0;
+    if (inner) return fgmres_fixed(S, depth, a, b, rhs, x, m, its_out, rel_out);
     // ||rhs||
     launch_dots(rhs, 1, n, n, rhs, part, dbuf + 2 * (m + 1), st);
     double bn2;
@@ -1929,7 +2015,9 @@ tdbem_status tdbem_solve(tdbem_ctx* c, const double* g, double* alpha, const tdb
             ALLOC(c, L.w, sizeof(double) * n);
             ALLOC(c, L.tmp, sizeof(double) * n);
             ALLOC(c, L.partial, sizeof(double) * (size_t)(m + 2) * dots_partial_blocks(n));
-            ALLOC(c, L.h, sizeof(double) * (2 * (m + 1) + 2));
+            // the outer solve keeps one Hessenberg column on the device; an inner solve (a fixed
+            // number of steps) keeps all of its columns and ||rhs||^2
+            ALLOC(c, L.h, sizeof(double) * ((size_t)(d == 0 ? 1 : m) * (2 * (m + 1) + 1) + 2));
             L.m = m;
             L.n = n;
         }
