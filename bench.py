@@ -71,6 +71,13 @@ def parse():
     ap.add_argument("--batch-rhs", type=int, default=32,
                     help="right-hand sides of the batched learned solve (0 = skip the batched leg)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--config5", action="store_true",
+                    help="only the learned-preconditioner experiment on the 20480-triangle torus (about 12 min)")
+    ap.add_argument("--c5-geometries", type=int, default=10, help="random spheres and tori of the training pairs")
+    ap.add_argument("--c5-pairs", type=int, default=2000, help="residual/correction pairs over all geometries")
+    ap.add_argument("--c5-epochs", type=float, default=3.0, help="passes over the pairs (batch 8)")
+    ap.add_argument("--c5-learned-it", type=int, default=2400, help="iteration limit of the learned torus solve")
+    ap.add_argument("--c5-alg1-it", type=int, default=120, help="iteration limit of the Algorithm 1 torus solve")
     return ap.parse_args()
 
 
@@ -395,6 +402,130 @@ class Budget:
         return False
 
 
+def mean_edge(xyz, tri):
+    import numpy as np
+    e = np.concatenate([xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 1]],
+                        xyz[tri[:, 0]] - xyz[tri[:, 2]]])
+    return float(np.linalg.norm(e, axis=1).mean())
+
+
+def config5(args):
+    """The learned preconditioner of the torus workload, trained as that workload states: a
+    4-layer network on residual/correction pairs that the method generates on randomly sized
+    spheres and tori (residual A e of an error e drawn by the library, correction e), then used
+    as FGMRES's variable preconditioner on the 20480-triangle torus with 128 graded bases (mixed
+    storage), against Algorithm 1 (2, 10) on the same operator; iterations, time and residual,
+    and the residual of the learned solution under the FP64 matrix-free product."""
+    import numpy as np
+    import torch
+    import paper_1503_07221_amd as tb
+    from workloads import get_config, graded_grid, icosphere, torus
+
+    t_all = time.perf_counter()
+    rng = np.random.default_rng(5)
+    per = args.c5_pairs // args.c5_geometries
+    geoms, desc = [], []
+    t0 = time.perf_counter()
+    for gi in range(args.c5_geometries):
+        if gi % 2 == 0:
+            lev = int(rng.choice([2, 3]))
+            rad = float(rng.uniform(0.7, 1.3))
+            xyz, tri = icosphere(lev)
+            xyz = xyz * rad
+            name = f"sphere L{lev} radius {rad:.3f}"
+        else:
+            R = float(rng.uniform(0.8, 1.2))
+            r = R * float(rng.uniform(0.25, 0.45))
+            nu = int(rng.choice([24, 32, 40]))
+            nv = max(8, int(round(nu * 1.25 * r / R)))
+            xyz, tri = torus(nu, nv, R, r)
+            name = f"torus {nu}x{nv} R {R:.3f} r {r:.3f}"
+        N = int(rng.integers(16, 33))
+        T = float(rng.uniform(1.5, 3.0)) * mean_edge(xyz, tri) * (N - 1)
+        grid = graded_grid(N, T, seed=100 + gi)
+        c = tb.Context(0)
+        c.set_mesh(xyz, tri)
+        c.set_time_grid(grid, "bump")
+        c.assemble(tb.FP64)
+        V, Z = c.lp_make_pairs(per, seed=200 + gi)
+        geoms.append((c, V, Z))
+        desc.append({"mesh": name, "triangles": int(len(tri)), "time_bases": N, "T": T, "pairs": per})
+        print(f"# config5: {name}, {len(tri)} triangles, {N} bases on [0, {T:.2f}], {per} pairs",
+              file=sys.stderr, flush=True)
+    pairs_s = time.perf_counter() - t0
+    net = tb.Context(0)
+    net.lp_init(4, seed=6)
+    steps_total = int(args.c5_epochs * args.c5_pairs / 8)
+    chunk = 5
+    rounds = max(1, steps_total // (chunk * len(geoms)))
+    hist = []
+    t0 = time.perf_counter()
+    for rd in range(rounds):
+        lr = 1e-3 if rd < (2 * rounds) // 3 else 5e-4
+        for gi, (c, V, Z) in enumerate(geoms):
+            h, _ = net.lp_train_pairs(c, V, Z, steps=chunk, batch=8, lr=lr, seed=1000 * rd + gi)
+            hist.append(h)
+        if rd % 5 == 0 or rd == rounds - 1:
+            print(f"# config5: training round {rd + 1}/{rounds}, loss {np.concatenate(hist[-len(geoms):]).mean():.3f}",
+                  file=sys.stderr, flush=True)
+    train_s = time.perf_counter() - t0
+    hist = np.concatenate(hist)
+    params = net.lp_get_params()
+    for c, V, Z in geoms:
+        c.close()
+    del geoms
+    net.close()
+    torch.cuda.empty_cache()
+
+    cfg = get_config("torus20480_graded128")
+    xyz, tri = cfg["mesh"]
+    ctx = tb.Context(0)
+    ctx.set_mesh(xyz, tri)
+    ctx.set_time_grid(cfg["grid"], cfg["cutoff"])
+    t0 = time.perf_counter()
+    arep = ctx.assemble(tb.MIXED)
+    asm_s = time.perf_counter() - t0
+    print(f"# config5: torus assembled (mixed) in {asm_s:.1f} s, {arep['quad_evals']:.3e} quad-evals",
+          file=sys.stderr, flush=True)
+    g = ctx.rhs_plane_pulse(cfg["direction"], cfg["t0"], cfg["width"])
+    gn = torch.linalg.norm(g).item()
+    ctx.lp_init(4, seed=0)
+    ctx.lp_set_params(params)
+    out = {"workload": "torus20480_graded128", "precision": "mixed (FP32 storage, FP64 solver)",
+           "training": {"geometries": desc, "pairs": per * len(desc), "pair_generation_s": pairs_s,
+                        "adam_steps": int(len(hist)), "batch": 8, "train_s": train_s,
+                        "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean())},
+           "assembly_s": asm_s, "quad_evals": int(arep["quad_evals"])}
+
+    def progress(tag, every):
+        def cb(it, est):
+            if it % every == 0:
+                print(f"# config5 {tag}: iteration {it}, estimate {est:.3e}", file=sys.stderr, flush=True)
+        return cb
+
+    a_l, r_l = ctx.solve(g, tol=1e-8, restart=600, max_it=args.c5_learned_it, precond_kind=tb.PRECOND_LEARNED,
+                         progress=progress("learned", 300))
+    res_l = torch.linalg.norm(g - ctx.matvec(a_l)).item() / gn
+    out["learned"] = {"solver": "FGMRES(600) + network", "iterations": int(r_l["iterations"]),
+                      "ms": r_l["ms"], "rel_residual": res_l, "converged": bool(r_l["converged"])}
+    print(f"# config5 learned: {r_l['iterations']} it, {r_l['ms'] / 1e3:.1f} s, residual {res_l:.3e}",
+          file=sys.stderr, flush=True)
+    yf, _ = ctx.matvec_free(a_l)
+    out["learned"]["rel_residual_fp64_matrix_free"] = torch.linalg.norm(g - yf).item() / gn
+    print(f"# config5 learned: FP64 matrix-free residual {out['learned']['rel_residual_fp64_matrix_free']:.3e}",
+          file=sys.stderr, flush=True)
+    a_a, r_a = ctx.solve(g, tol=1e-8, restart=300, max_it=args.c5_alg1_it, precond_inner=(2, 10),
+                         progress=progress("alg1", 20))
+    res_a = torch.linalg.norm(g - ctx.matvec(a_a)).item() / gn
+    out["alg1"] = {"solver": "FGMRES(300) + Algorithm 1 (2, 10)", "iterations": int(r_a["iterations"]),
+                   "ms": r_a["ms"], "rel_residual": res_a, "converged": bool(r_a["converged"])}
+    print(f"# config5 alg1: {r_a['iterations']} it, {r_a['ms'] / 1e3:.1f} s, residual {res_a:.3e}",
+          file=sys.stderr, flush=True)
+    out["wall_s"] = time.perf_counter() - t_all
+    print(json.dumps({"config5": out}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -403,6 +534,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.config5:
+        config5(args)
         return
     budget = Budget(args.budget_s)
     import numpy as np

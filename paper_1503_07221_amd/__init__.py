@@ -32,7 +32,8 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_matvec_multi", "tdbem_solve_multi", "tdbem_potential_dl",
                     "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
-                    "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train"]
+                    "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train",
+                    "tdbem_lp_make_pairs", "tdbem_lp_train_pairs"]
 
 # preconditioner kinds of SolveOpts.precond_kind
 PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1, PRECOND_DEFLATION = 0, 1, 2, 3
@@ -143,6 +144,8 @@ def load_library(path=LIB_PATH):
     L.tdbem_lp_gradient.argtypes = [vp, vp, vp, vp, fp]
     L.tdbem_matvec_transpose.argtypes = [vp, vp, vp]
     L.tdbem_lp_train.argtypes = [vp, P(TrainOpts), fp, P(TrainReport)]
+    L.tdbem_lp_make_pairs.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
+    L.tdbem_lp_train_pairs.argtypes = [vp, vp, vp, vp, i64, P(TrainOpts), fp, P(TrainReport)]
     for name in EXPORTED_SYMBOLS:
         if name not in ("tdbem_destroy", "tdbem_last_error", "tdbem_lp_num_params"):
             getattr(L, name).restype = ctypes.c_int
@@ -413,6 +416,29 @@ class Context:
         n = self.N * self.M
         self._check(self.lib.tdbem_matvec_transpose(self.h, self._dev(y, n), self._dev(x, n)))
         return x
+
+    def lp_make_pairs(self, count, seed=0):
+        """(V, Z): count residuals V[s] = A Z[s] of errors Z[s] drawn by the library (device
+        tensors of shape (count, N*M))."""
+        n = self.N * self.M
+        V = self.torch.empty((int(count), n), dtype=self.torch.float64, device=self.device)
+        Z = self.torch.empty_like(V)
+        self._check(self.lib.tdbem_lp_make_pairs(self.h, int(count), int(seed), self._dev2(V), self._dev2(Z)))
+        return V, Z
+
+    def lp_train_pairs(self, geom, V, Z, steps, batch=8, lr=1e-3, seed=0):
+        """Train this context's network on the pairs (V[s], Z[s]) of the mesh and grid of `geom`
+        (another Context, or self); returns (per-step losses, report dict)."""
+        o = TrainOpts(int(steps), int(batch), float(lr), int(seed))
+        hist = np.zeros(int(steps), dtype=np.float32)
+        rep = TrainReport()
+        n = geom.N * geom.M
+        if V.shape != Z.shape or V.dim() != 2 or V.shape[1] != n:
+            raise ValueError(f"pairs must be two (count, {n}) tensors")
+        self._check(self.lib.tdbem_lp_train_pairs(self.h, geom.h, geom._dev2(V), geom._dev2(Z), int(V.shape[0]),
+                                                  ctypes.byref(o), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                  ctypes.byref(rep)))
+        return hist, rep.as_dict()
 
     def lp_train(self, steps, batch=8, lr=1e-3, seed=0):
         """Train the network on the assembled operator; returns (per-step losses, report dict)."""

@@ -1172,10 +1172,10 @@ tdbem_status lp_operator_graph(tdbem_ctx* c)
     return TDBEM_OK;
 }
 
-tdbem_status lp_need_train_buffers(tdbem_ctx* c)
+// Training buffers of the network of c for graphs of up to n = N*M nodes.
+tdbem_status lp_need_train_n(tdbem_ctx* c, int64_t n)
 {
     tdbem_ctx::Learned& L = c->lp;
-    const int64_t n = (int64_t)c->N * c->M;
     if (L.ntrain >= n) return TDBEM_OK;
     const size_t f = sizeof(float) * (size_t)n * kLpHidden;
     ALLOC(c, L.H, f * (L.layers + 1));
@@ -1192,6 +1192,8 @@ tdbem_status lp_need_train_buffers(tdbem_ctx* c)
     L.ntrain = n;
     return TDBEM_OK;
 }
+
+tdbem_status lp_need_train_buffers(tdbem_ctx* c) { return lp_need_train_n(c, (int64_t)c->N * c->M); }
 
 // Forward pass keeping every layer's input and pre-activation, then add the gradient of <dz, z>
 // to lp.grad.  The scale of v must be in dots[2..3] (lp_scale).
@@ -1397,6 +1399,133 @@ tdbem_status tdbem_lp_train(tdbem_ctx* c, const tdbem_lp_train_opts* o, float* l
             launch_scale_copy(dz, dz, 2.0 / vv, n, st);              // d loss / d z = 2 A^T r / |v|^2
             HIPCHK(c, hipGetLastError());
             TRY(lp_forward_backward(c, v, z, dz, true));
+        }
+        if (used == 0) continue;
+        ++L.step;
+        launch_lp_adam(L.P, L.params.as<float>(), L.grad.as<float>(), L.m1.as<float>(), L.m2.as<float>(),
+                       (float)o->lr, L.step, 1.0f / (float)used, L.wq.as<uint16_t>(), st);
+        HIPCHK(c, hipGetLastError());
+        const double loss = sum / used;
+        if (step == 0) first = loss;
+        last = loss;
+        if (loss_history) loss_history[step] = (float)loss;
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (rep) {
+        rep->steps = o->steps;
+        rep->samples = (int64_t)o->steps * o->batch;
+        rep->loss_first = first;
+        rep->loss_last = last;
+        rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_make_pairs(tdbem_ctx* c, int64_t count, uint64_t seed, double* V, double* Z)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (count < 1 || !V || !Z) FAIL(c, TDBEM_EINVAL, "need count >= 1 and two device arrays");
+    if (!c->assembled) FAIL(c, TDBEM_ESTATE, "assemble before forming pairs (the residual applies A)");
+    TRY(set_device(c));
+    TRY(lp_graph(c));
+    const int64_t n = (int64_t)c->N * c->M;
+    hipStream_t st = c->stream;
+    DBuf tmp;
+    ALLOC(c, tmp, sizeof(double) * n);
+    for (int64_t s = 0; s < count; ++s) {
+        // the error: a normal vector smoothed 0..3 times over the mesh (the number of passes from
+        // the seed), the residual it leaves: A times it
+        double* z = Z + s * n;
+        double* v = V + s * n;
+        const uint64_t h = host_splitmix64(seed ^ host_splitmix64((uint64_t)s));
+        launch_lp_randn(n, seed, (uint64_t)s, z, st);
+        const int q = (int)(h & 3);
+        for (int u = 0; u < q; ++u) {
+            launch_lp_smooth(lp_view(c), z, tmp.as<double>(), st);
+            launch_scale_copy(z, tmp.as<double>(), 1.0, n, st);
+        }
+        HIPCHK(c, hipGetLastError());
+        TRY(matvec_range(c, 0, c->N, 0, c->N, z, v));
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_lp_train_pairs(tdbem_ctx* c, tdbem_ctx* g, const double* V, const double* Z, int64_t count,
+                                  const tdbem_lp_train_opts* o, float* loss_history, tdbem_lp_train_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (!g || !V || !Z || !o || count < 1) FAIL(c, TDBEM_EINVAL, "null argument or count < 1");
+    if (o->steps < 1 || o->batch < 1 || !(o->lr > 0.0)) FAIL(c, TDBEM_EINVAL, "bad training options");
+    TRY(lp_need_params(c));
+    if (g->device != c->device) FAIL(c, TDBEM_EINVAL, "the network and the pairs must be on one device");
+    if (g != c) {
+        g->err.clear();
+        TRY(set_device(g));
+        const tdbem_status sg = lp_graph(g);
+        if (sg != TDBEM_OK) FAIL(c, sg, "geometry of the pairs: %s", g->err.c_str());
+        HIPCHK(c, hipStreamSynchronize(g->stream));   // its graph arrays are used on this stream
+    }
+    TRY(set_device(c));
+    if (g == c) TRY(lp_graph(c));
+    const int64_t n = (int64_t)g->N * g->M;
+    TRY(lp_need_train_n(c, n));
+    double* d;
+    TRY(lp_dots(c, n, &d));
+    const auto t_start = std::chrono::steady_clock::now();
+    tdbem_ctx::Learned& L = c->lp;
+    hipStream_t st = c->stream;
+    const LpGraph gv = lp_view(g);
+    const int64_t hs = n * kLpHidden;
+    const double* sc = L.dots.as<double>() + 2;
+    double* pz = L.zb.as<double>();
+    double* r = L.rb.as<double>();
+    double* dz = L.db.as<double>();
+    // pairs in a seeded random order, reshuffled after every pass over them
+    std::vector<int64_t> order(count);
+    int64_t pos = count, pass = 0;
+    auto next = [&]() {
+        if (pos == count) {
+            for (int64_t s = 0; s < count; ++s) order[s] = s;
+            uint64_t state = host_splitmix64(o->seed ^ host_splitmix64(0x5EEDull + (uint64_t)pass++));
+            for (int64_t s = count - 1; s > 0; --s) {
+                state = host_splitmix64(state);
+                std::swap(order[s], order[(int64_t)(state % (uint64_t)(s + 1))]);
+            }
+            pos = 0;
+        }
+        return order[pos++];
+    };
+    double first = 0.0, last = 0.0;
+    for (int step = 0; step < o->steps; ++step) {
+        HIPCHK(c, hipMemsetAsync(L.grad.p, 0, sizeof(float) * L.P, st));
+        double sum = 0.0;
+        int used = 0;
+        for (int b = 0; b < o->batch; ++b) {
+            const int64_t s = next();
+            const double* v = V + s * n;
+            const double* z = Z + s * n;
+            double zz;
+            TRY(lp_norm2(c, z, n, &zz));
+            if (!(zz > 0.0)) continue;
+            TRY(lp_scale(c, v, n, st));
+            launch_lp_forward(gv, L.layers, L.params.as<float>(), L.wq.as<uint16_t>(), v, sc, L.H.as<float>(), hs,
+                              L.U.as<float>(), pz, st);
+            launch_scale_copy(r, pz, 1.0, n, st);
+            launch_axpby(r, z, -1.0, 1.0, n, st);                       // r = P(v) - z
+            HIPCHK(c, hipGetLastError());
+            double rr;
+            TRY(lp_norm2(c, r, n, &rr));
+            sum += rr / zz;
+            ++used;
+            launch_scale_copy(dz, r, 2.0 / zz, n, st);                  // d loss / d P(v)
+            launch_lp_backward(gv, L.layers, L.wq.as<uint16_t>(), v, sc, L.H.as<float>(), L.U.as<float>(), dz,
+                               L.dH2.as<float>(), L.DU.as<float>(), L.dX.as<float>(), L.partial.as<float>(),
+                               L.grad.as<float>(), st);
+            HIPCHK(c, hipGetLastError());
+            ++L.samples;
         }
         if (used == 0) continue;
         ++L.step;

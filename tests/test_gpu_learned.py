@@ -164,6 +164,64 @@ def test_training_cuts_iterations(ctx, tb):
     assert torch.linalg.norm(alpha2 - alpha).item() <= 1e-6 * torch.linalg.norm(alpha).item()
 
 
+def test_pairs_training_across_geometries(tb):
+    """Residual/correction pairs generated by the operator (V = A Z) on a sphere and a torus train
+    one network in turn (the config-5 procedure at small size): every pair satisfies V = A Z, the
+    loss falls, training through a separate network context equals training in the geometry's own
+    context, and the network cuts the FGMRES iterations of a problem it was not trained on."""
+    import torch
+    from workloads import torus
+    geoms = []
+    for xyz, tri, grid in ((*icosphere(2), graded_grid(14, 6.0, seed=41)),
+                           (*torus(24, 12), graded_grid(14, 6.0, seed=42))):
+        c = tb.Context(0)
+        c.set_mesh(xyz, tri); c.set_time_grid(grid); c.assemble()
+        V, Z = c.lp_make_pairs(48, seed=43)
+        for s in (0, 17, 47):
+            av = c.matvec(Z[s].contiguous())
+            assert torch.linalg.norm(av - V[s]).item() <= 1e-14 * torch.linalg.norm(av).item()
+        assert torch.linalg.norm(Z[0] - Z[1]).item() > 0.1 * torch.linalg.norm(Z[0]).item()
+        geoms.append((c, V, Z))
+    net = tb.Context(0)
+    net.lp_init(3, seed=44)
+    p0 = net.lp_get_params()
+    hists = []
+    for rnd in range(8):
+        for c, V, Z in geoms:
+            h, rep = net.lp_train_pairs(c, V, Z, steps=25, batch=8, lr=2e-3, seed=45 + rnd)
+            assert rep["steps"] == 25 and np.all(np.isfinite(h))
+            hists.append(h)
+    first = np.mean([hh[:3].mean() for hh in hists[:2]])
+    final = np.mean([hh[-5:].mean() for hh in hists[-2:]])
+    assert final < 0.7 * first, (first, final)
+    # the same steps in the geometry's own context give the same network
+    c, V, Z = geoms[0]
+    c.lp_init(3, seed=44); c.lp_set_params(p0)
+    a = tb.Context(0); a.lp_init(3, seed=44); a.lp_set_params(p0)
+    ha, _ = a.lp_train_pairs(c, V, Z, steps=10, batch=4, lr=2e-3, seed=46)
+    hc, _ = c.lp_train_pairs(c, V, Z, steps=10, batch=4, lr=2e-3, seed=46)
+    pa, pc = a.lp_get_params(), c.lp_get_params()
+    assert np.allclose(ha, hc, rtol=1e-6, atol=0.0)
+    assert np.linalg.norm(pa - pc) <= 1e-6 * np.linalg.norm(pc)
+    # another problem (a grid it was not trained on): the trained network, through the parameter
+    # vector, against plain FGMRES
+    t = tb.Context(0)
+    t.set_mesh(*icosphere(2)); t.set_time_grid(graded_grid(17, 8.0, seed=2)); t.assemble()
+    t.lp_init(3, seed=0); t.lp_set_params(net.lp_get_params())
+    g = t.rhs_plane_pulse(pulse_direction(3), 1.9, 0.6)
+    _, plain = t.solve(g, tol=1e-8, restart=800, max_it=800)
+    alpha, lrn = t.solve(g, tol=1e-8, restart=800, max_it=800, precond_kind=tb.PRECOND_LEARNED)
+    assert plain["converged"] and lrn["converged"]
+    assert lrn["iterations"] < 0.7 * plain["iterations"], (lrn["iterations"], plain["iterations"])
+    r = g - t.matvec(alpha)
+    assert torch.linalg.norm(r).item() <= 1.01e-8 * torch.linalg.norm(g).item()
+    with pytest.raises(tb.TdbemError) as e:
+        net.lp_make_pairs(4)                              # no assembled operator
+    assert e.value.status in (-6, -1)
+    for x in (t, a, net) + tuple(gg[0] for gg in geoms):
+        x.close()
+
+
 def test_learned_error_paths(tb):
     import torch
     c = tb.Context(0)
