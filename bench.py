@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--c5-geometries", type=int, default=10, help="random spheres and tori of the training pairs")
     ap.add_argument("--c5-pairs", type=int, default=2000, help="residual/correction pairs over all geometries")
     ap.add_argument("--c5-epochs", type=float, default=3.0, help="passes over the pairs (batch 8)")
+    ap.add_argument("--c5-layers", type=int, default=4, help="message-passing layers of the network")
+    ap.add_argument("--c5-restart", type=int, default=600, help="FGMRES restart of the learned torus solve")
     ap.add_argument("--c5-learned-it", type=int, default=2400, help="iteration limit of the learned torus solve")
     ap.add_argument("--c5-alg1-it", type=int, default=120, help="iteration limit of the Algorithm 1 torus solve")
     return ap.parse_args()
@@ -454,7 +456,7 @@ def config5(args):
               file=sys.stderr, flush=True)
     pairs_s = time.perf_counter() - t0
     net = tb.Context(0)
-    net.lp_init(4, seed=6)
+    net.lp_init(args.c5_layers, seed=6)
     steps_total = int(args.c5_epochs * args.c5_pairs / 8)
     chunk = 5
     rounds = max(1, steps_total // (chunk * len(geoms)))
@@ -489,9 +491,10 @@ def config5(args):
           file=sys.stderr, flush=True)
     g = ctx.rhs_plane_pulse(cfg["direction"], cfg["t0"], cfg["width"])
     gn = torch.linalg.norm(g).item()
-    ctx.lp_init(4, seed=0)
+    ctx.lp_init(args.c5_layers, seed=0)
     ctx.lp_set_params(params)
     out = {"workload": "torus20480_graded128", "precision": "mixed (FP32 storage, FP64 solver)",
+           "layers": args.c5_layers,
            "training": {"geometries": desc, "pairs": per * len(desc), "pair_generation_s": pairs_s,
                         "adam_steps": int(len(hist)), "batch": 8, "train_s": train_s,
                         "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean())},
@@ -503,10 +506,10 @@ def config5(args):
                 print(f"# config5 {tag}: iteration {it}, estimate {est:.3e}", file=sys.stderr, flush=True)
         return cb
 
-    a_l, r_l = ctx.solve(g, tol=1e-8, restart=600, max_it=args.c5_learned_it, precond_kind=tb.PRECOND_LEARNED,
-                         progress=progress("learned", 300))
+    a_l, r_l = ctx.solve(g, tol=1e-8, restart=args.c5_restart, max_it=args.c5_learned_it,
+                         precond_kind=tb.PRECOND_LEARNED, progress=progress("learned", 300))
     res_l = torch.linalg.norm(g - ctx.matvec(a_l)).item() / gn
-    out["learned"] = {"solver": "FGMRES(600) + network", "iterations": int(r_l["iterations"]),
+    out["learned"] = {"solver": f"FGMRES({args.c5_restart}) + network", "iterations": int(r_l["iterations"]),
                       "ms": r_l["ms"], "rel_residual": res_l, "converged": bool(r_l["converged"])}
     print(f"# config5 learned: {r_l['iterations']} it, {r_l['ms'] / 1e3:.1f} s, residual {res_l:.3e}",
           file=sys.stderr, flush=True)
@@ -514,13 +517,14 @@ def config5(args):
     out["learned"]["rel_residual_fp64_matrix_free"] = torch.linalg.norm(g - yf).item() / gn
     print(f"# config5 learned: FP64 matrix-free residual {out['learned']['rel_residual_fp64_matrix_free']:.3e}",
           file=sys.stderr, flush=True)
-    a_a, r_a = ctx.solve(g, tol=1e-8, restart=300, max_it=args.c5_alg1_it, precond_inner=(2, 10),
-                         progress=progress("alg1", 20))
-    res_a = torch.linalg.norm(g - ctx.matvec(a_a)).item() / gn
-    out["alg1"] = {"solver": "FGMRES(300) + Algorithm 1 (2, 10)", "iterations": int(r_a["iterations"]),
-                   "ms": r_a["ms"], "rel_residual": res_a, "converged": bool(r_a["converged"])}
-    print(f"# config5 alg1: {r_a['iterations']} it, {r_a['ms'] / 1e3:.1f} s, residual {res_a:.3e}",
-          file=sys.stderr, flush=True)
+    if args.c5_alg1_it > 0:
+        a_a, r_a = ctx.solve(g, tol=1e-8, restart=300, max_it=args.c5_alg1_it, precond_inner=(2, 10),
+                             progress=progress("alg1", 20))
+        res_a = torch.linalg.norm(g - ctx.matvec(a_a)).item() / gn
+        out["alg1"] = {"solver": "FGMRES(300) + Algorithm 1 (2, 10)", "iterations": int(r_a["iterations"]),
+                       "ms": r_a["ms"], "rel_residual": res_a, "converged": bool(r_a["converged"])}
+        print(f"# config5 alg1: {r_a['iterations']} it, {r_a['ms'] / 1e3:.1f} s, residual {res_a:.3e}",
+              file=sys.stderr, flush=True)
     out["wall_s"] = time.perf_counter() - t_all
     print(json.dumps({"config5": out}), flush=True)
     ctx.close()
@@ -636,6 +640,8 @@ def main():
         "assembly_breakdown_ms": {k: float(np.mean([r[k] for r in reps]))
                                   for k in ("ms_tables", "ms_layout", "ms_regular", "ms_singular")},
         "matrix_bytes": int(reps[-1]["bytes_matrix"]),
+        "regular_tiles": {"shape": "%dx%d" % ctx.assemble_tuning()[0],
+                          "timed_ms_per_launch": {"4x8": ctx.assemble_tuning()[1][0], "8x8": ctx.assemble_tuning()[1][1]}},
         "roofline": {"bound": "alu", "kernel": REGULAR_KERNEL, "achieved": achieved_tflops,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,

@@ -129,9 +129,10 @@ const char *tdbem_last_error(const tdbem_ctx *ctx);
 tdbem_status tdbem_set_mesh(tdbem_ctx *ctx, const double *xyz, int64_t M, const int32_t *tri, int64_t E);
 
 /* Time grid 0 = t_0 < t_1 < ... < t_{N-1} = T (host, float64) and temporal order p (Section 3,
- * eq. (BasisFunctions): p + 1 bases per node, L = N (p + 1) in all).  This library implements
- * p = 0, one basis per node (mu_i from the cutoff, b_0 with the causal factor 8 (t/h_1)^2);
- * another p gives TDBEM_EINVAL.  Resets any assembled matrix.  TDBEM_EGRID unless 2 <= N <= 4096,
+ * eq. (BasisFunctions): p + 1 bases per node, the node's bump mu_n times the Legendre
+ * polynomials P_0..P_p of the node's support mapped to [-1, 1], b_0 with the causal factor
+ * 8 (t/h_1)^2; L = N (p + 1) temporal bases, basis n (p + 1) + m).  Resets any assembled matrix.
+ * TDBEM_EINVAL unless 0 <= p <= 4 and N (p + 1) <= 8192; TDBEM_EGRID unless 2 <= N <= 4096,
  * t_0 = 0 and t strictly increasing. */
 tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdbem_cutoff cutoff, int32_t p);
 
@@ -142,6 +143,18 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdb
  * range of the two hats (eq. (SparsitySmallBlock)).  rep may be NULL.
  * TDBEM_ESTATE without mesh and grid, TDBEM_ENOMEM if the storage does not fit. */
 tdbem_status tdbem_assemble(tdbem_ctx *ctx, tdbem_precision prec, tdbem_assembly_report *rep);
+
+/* The regular-pair kernel is compiled for two tile shapes (test x trial triangles per workgroup:
+ * 4 x 8 on 256 lanes, 8 x 8 on 512).  At the first assembly of a mesh and time grid the library
+ * times each shape on every 32nd tile, keeps the faster for that mesh and grid, and zeroes the
+ * storage again (the timing is part of that assembly's layout time).  This call reports the
+ * shape in use (0 x 0 before any assembly) and, through ms[0..1] when ms is not NULL, each
+ * shape's timed estimate for the whole launch (-1 if not timed).  Any pointer may be NULL. */
+tdbem_status tdbem_assemble_tuning(tdbem_ctx *ctx, int32_t *tile_test, int32_t *tile_trial, double *ms);
+
+/* Use tile shape v (0: 4 x 8, 1: 8 x 8; the count goes to nvariants when not NULL) for every later
+ * assembly instead of the timed choice; v = -1 returns to timing.  TDBEM_EINVAL for another v. */
+tdbem_status tdbem_assemble_set_tiles(tdbem_ctx *ctx, int32_t v, int32_t *nvariants);
 
 /* Assemble the problems of n distinct contexts (meshes and grids of any sizes, all on one device)
  * concurrently: one host thread per context runs tdbem_assemble on that context's stream, so the

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train",
-                    "tdbem_lp_make_pairs", "tdbem_lp_train_pairs"]
+                    "tdbem_lp_make_pairs", "tdbem_lp_train_pairs", "tdbem_assemble_tuning", "tdbem_assemble_set_tiles"]
 
 # preconditioner kinds of SolveOpts.precond_kind
 PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1, PRECOND_DEFLATION = 0, 1, 2, 3
@@ -145,6 +145,8 @@ def load_library(path=LIB_PATH):
     L.tdbem_matvec_transpose.argtypes = [vp, vp, vp]
     L.tdbem_lp_train.argtypes = [vp, P(TrainOpts), fp, P(TrainReport)]
     L.tdbem_lp_make_pairs.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
+    L.tdbem_assemble_tuning.argtypes = [vp, P(i32), P(i32), P(dp)]
+    L.tdbem_assemble_set_tiles.argtypes = [vp, i32, P(i32)]
     L.tdbem_lp_train_pairs.argtypes = [vp, vp, vp, vp, i64, P(TrainOpts), fp, P(TrainReport)]
     for name in EXPORTED_SYMBOLS:
         if name not in ("tdbem_destroy", "tdbem_last_error", "tdbem_lp_num_params"):
@@ -240,6 +242,20 @@ class Context:
         rep = AssemblyReport()
         self._check(self.lib.tdbem_assemble(self.h, int(precision), ctypes.byref(rep)))
         return rep.as_dict()
+
+    def assemble_tuning(self):
+        """(test, trial) triangles of the regular-pair tile shape in use and the timed estimate of
+        every shape (ms per launch, -1 where not timed)."""
+        tt, ts = ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_double * 2)()
+        self._check(self.lib.tdbem_assemble_tuning(self.h, ctypes.byref(tt), ctypes.byref(ts), ms))
+        return (tt.value, ts.value), [ms[0], ms[1]]
+
+    def assemble_set_tiles(self, v):
+        """Force tile shape v (0: 4 x 8, 1: 8 x 8) for later assemblies; -1 returns to timing."""
+        n = ctypes.c_int32()
+        self._check(self.lib.tdbem_assemble_set_tiles(self.h, int(v), ctypes.byref(n)))
+        return n.value
 
     def get_entries(self, k, i, j, l):
         k, i, j, l = (np.ascontiguousarray(np.broadcast_to(a, np.broadcast(k, i, j, l).shape).ravel(), dtype=np.int32)

@@ -146,6 +146,9 @@ void ss_point(int kind, int reg, double xi, double e1, double e2, double e3, dou
 
 }  // namespace
 
+// every kTileSampleStride-th tile of the regular-pair kernel is timed to pick its tile shape
+static constexpr int64_t kTileSampleStride = 32;
+
 struct tdbem_ctx {
     int device = 0;
     void* scratch = nullptr;      // device address of the allocation-free staging array
@@ -162,8 +165,15 @@ struct tdbem_ctx {
     bool have_mesh = false, have_grid = false;
 
     // mesh on the device
-    DBuf d_xyz, d_tri, d_rho, g_P, g_n, g_area, g_curl, g_qp, g_v, d_pairs, d_rules, d_roff, d_rcnt, d_tiles;
-    int64_t ntiles = 0;
+    DBuf d_xyz, d_tri, d_rho, g_P, g_n, g_area, g_curl, g_qp, g_v, d_pairs, d_rules, d_roff, d_rcnt;
+    // tiles of the regular-pair kernel per tile shape, and a strided sample of them for the timing
+    // that picks the shape (once per mesh and time grid unless a shape is forced)
+    DBuf d_tiles[2], d_tiles_sample[2];
+    int64_t ntiles[2] = {0, 0}, ntiles_sample[2] = {0, 0};
+    int tile_v = -1;
+    bool tile_forced = false;
+    uint64_t tile_key = ~0ull;
+    double tile_ms[2] = {-1.0, -1.0};
     int64_t npairs = 0, npairs_kind[3] = {0, 0, 0};
     // time grid
     DBuf d_t;
@@ -490,9 +500,19 @@ tdbem_status tdbem_set_mesh(tdbem_ctx* c, const double* xyz, int64_t M, const in
     TRY(upload(c, c->d_tri, c->tri.data(), c->tri.size()));
     TRY(upload(c, c->d_rho, rho.data(), rho.size()));
     TRY(upload(c, c->d_pairs, pairs.data(), pairs.size()));
-    const std::vector<int32_t> tiles = regular_tiles((int)E);
-    c->ntiles = (int64_t)tiles.size() / 2;
-    TRY(upload(c, c->d_tiles, tiles.data(), tiles.size()));
+    for (int v = 0; v < tile_variants(); ++v) {
+        const std::vector<int32_t> tiles = regular_tiles((int)E, v);
+        c->ntiles[v] = (int64_t)tiles.size() / 2;
+        TRY(upload(c, c->d_tiles[v], tiles.data(), tiles.size()));
+        std::vector<int32_t> sample;
+        for (int64_t q = 0; q < c->ntiles[v]; q += kTileSampleStride) {
+            sample.push_back(tiles[2 * q]);
+            sample.push_back(tiles[2 * q + 1]);
+        }
+        c->ntiles_sample[v] = (int64_t)sample.size() / 2;
+        TRY(upload(c, c->d_tiles_sample[v], sample.data(), std::max<size_t>(sample.size(), 2)));
+    }
+    if (!c->tile_forced) c->tile_v = -1;
     TRY(upload(c, c->d_rules, rules.data(), rules.size()));
     TRY(upload(c, c->d_roff, roff, 3));
     TRY(upload(c, c->d_rcnt, rcnt, 3));
@@ -682,6 +702,45 @@ static tdbem_status build_layout(tdbem_ctx* c, int prec)
     return TDBEM_OK;
 }
 
+// Tile shape of the regular-pair kernel: each shape runs on its strided sample of tiles (after a
+// short warm-up launch), timed with events; the faster per tile of the full list is kept for this
+// mesh and time grid.  The sample writes into the zeroed storage, which is zeroed again.
+
+static tdbem_status tune_tiles(tdbem_ctx* c, double* v64, float* v32)
+{
+    if (c->tile_forced || (c->tile_v >= 0 && c->tile_key == c->graph_version)) return TDBEM_OK;
+    DBuf scratch_count;
+    ALLOC(c, scratch_count, sizeof(unsigned long long));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    struct Guard {
+        hipEvent_t a, b;
+        ~Guard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } guard{e0, e1};
+    int best = 0;
+    for (int v = 0; v < tile_variants(); ++v) {
+        const int2* smp = c->d_tiles_sample[v].as<int2>();
+        launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
+                       std::min<int64_t>(c->ntiles_sample[v], 64), v, scratch_count.as<unsigned long long>(),
+                       c->stream);
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
+                       c->ntiles_sample[v], v, scratch_count.as<unsigned long long>(), c->stream);
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        c->tile_ms[v] = c->ntiles_sample[v] > 0 ? ms * (double)c->ntiles[v] / (double)c->ntiles_sample[v] : 0.0;
+        if (c->tile_ms[v] < c->tile_ms[best]) best = v;
+    }
+    HIPCHK(c, hipMemsetAsync(c->d_val.p, 0, c->d_val.bytes, c->stream));
+    c->tile_v = best;
+    c->tile_key = c->graph_version;
+    return TDBEM_OK;
+}
+
 tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_report* rep)
 {
     if (!c) return TDBEM_EINVAL;
@@ -708,10 +767,11 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
     float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
     unsigned long long* cnt = c->d_counter.as<unsigned long long>();
+    TRY(tune_tiles(c, v64, v32));
     // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
     // storage
     launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr,
-                   c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
+                   c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
@@ -792,8 +852,9 @@ tdbem_status tdbem_matvec_free(tdbem_ctx* c, const double* x, double* y, tdbem_a
     HIPCHK(c, hipMemsetAsync(counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
     HIPCHK(c, hipEventRecord(ev[2], c->stream));
     unsigned long long* cnt = counter.as<unsigned long long>();
+    const int tv = c->tile_v >= 0 ? c->tile_v : 0;
     launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), nullptr, nullptr, x, y,
-                   c->d_tiles.as<int2>(), c->ntiles, cnt, c->stream);
+                   c->d_tiles[tv].as<int2>(), c->ntiles[tv], tv, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
@@ -2260,6 +2321,31 @@ tdbem_status multi_tune(tdbem_ctx* c)
     return TDBEM_OK;
 }
 }  // namespace
+
+tdbem_status tdbem_assemble_tuning(tdbem_ctx* c, int32_t* tile_test, int32_t* tile_trial, double* ms)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    int tt = 0, ts = 0;
+    if (c->tile_v >= 0 && (c->assembled || c->tile_forced)) tile_shape(c->tile_v, &tt, &ts);
+    if (tile_test) *tile_test = tt;
+    if (tile_trial) *tile_trial = ts;
+    if (ms)
+        for (int v = 0; v < tile_variants(); ++v) ms[v] = c->tile_ms[v];
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_assemble_set_tiles(tdbem_ctx* c, int32_t v, int32_t* nvariants)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (nvariants) *nvariants = tile_variants();
+    if (v < -1 || v >= tile_variants()) FAIL(c, TDBEM_EINVAL, "tile shape %d outside -1..%d", v, tile_variants() - 1);
+    c->tile_forced = v >= 0;
+    c->tile_v = v;
+    if (v < 0) c->tile_key = ~0ull;
+    return TDBEM_OK;
+}
 
 tdbem_status tdbem_matvec_multi_tuning(tdbem_ctx* c, int32_t* rhs_per_pass, int32_t* staged_range,
                                        double* ms_per_rhs)

@@ -233,9 +233,9 @@ __device__ inline double recip(double r)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Regular pairs, tiled.  One workgroup (256 lanes) owns a tile of kTileT consecutive test
-// triangles tau and kTileS consecutive trial triangles sigma (the unordered pairs sigma > tau
-// without a common vertex: 32 x 49 point pairs).  It sorts the point-pair distances once; for
+// Regular pairs, tiled.  One workgroup (8 lanes per triangle pair) owns a tile of TT consecutive
+// test triangles tau and TS consecutive trial triangles sigma (the unordered pairs sigma > tau
+// without a common vertex: TT TS x 49 point pairs).  It sorts the point-pair distances once; for
 // every (k, i) the distances inside supp psi_{k,i} form one range of the sorted list.
 //
 //   plan     one wave takes up to kPlan candidates (k, i) at once (one per lane): the range
@@ -255,52 +255,64 @@ __device__ inline double recip(double r)
 //            before one atomic add per (vertex, vertex) entry goes to the band storage.
 // Two barriers per record.
 // ---------------------------------------------------------------------------------------------
-constexpr int kTileT = 4, kTileS = 8;
-constexpr int kTilePairs = kTileT * kTileS;          // 32
-constexpr int kTileEl = kTilePairs * 49;             // 1568
-constexpr int kTileSort = 2048;
-constexpr int kTileThreads = 256;
-constexpr int kTileVt = 3 * kTileT, kTileVs = 3 * kTileS;
 constexpr int kStage = 64;                           // pieces of one record held in LDS
 constexpr int kStageSlots = kStage * (kNc + 2) + kMaxIntervals + 1;   // double2 slots
-constexpr int kStageRegs = (kStageSlots + kTileThreads - 1) / kTileThreads;
 constexpr int kPlan = 64;                            // candidates planned at once (one wave)
 constexpr int kSegMax = 3;                           // segments of one round (kMaxIntervals * kPieces pieces)
 constexpr int kMaxRec = kSegMax * kPlan;
-constexpr int kChunkMax = (kTileEl + kTileThreads - 1) / kTileThreads;   // sorted points of one lane
 static_assert((kStage - 1) * (kSegMax - 1) + kStage >= kMaxIntervals * kPieces, "segments cover a kernel");
 static_assert(kSegMax == 3, "the record compaction counts three slots");
+
+// Tile shape: TT test x TS trial triangles on THREADS lanes (8 lanes per triangle pair), SORT the
+// power of two >= the point pairs that the bitonic sort runs on.  Larger tiles put more point pairs
+// behind every record (the fixed cost of a record is its latency chain and two barriers); the LDS
+// of the sorted keys and per-point slots bounds the size.  The host times the compiled shapes.
+template <int TT, int TS, int THREADS, int SORT>
+struct TileShape {
+    static constexpr int kT = TT, kS = TS, kThreads = THREADS, kSort = SORT;
+    static constexpr int kPairs = TT * TS, kEl = kPairs * 49;
+    static constexpr int kVt = 3 * TT, kVs = 3 * TS;
+    static constexpr int kStageRegs = (kStageSlots + THREADS - 1) / THREADS;
+    static constexpr int kChunkMax = (kEl + THREADS - 1) / THREADS;   // sorted points of one lane
+    static constexpr int kDz = (kVt * kVs + THREADS - 1) / THREADS;   // vertex-tile entries of one lane
+    static_assert(SORT >= kEl && (SORT & (SORT - 1)) == 0, "bitonic sort size");
+    static_assert(kEl < 4096, "a record packs sorted indices in 12 bits");
+    static_assert(THREADS == 8 * kPairs && THREADS >= 192 + kPairs, "8 lanes per pair; the setup roles");
+};
+using TileA = TileShape<4, 8, 256, 2048>;     // 1568 point pairs, 77.9 KB of LDS: 2 workgroups per CU
+using TileB = TileShape<8, 8, 512, 4096>;     // 3136 point pairs, 131.7 KB: 1 workgroup (8 waves) per CU
 
 // One record: the sorted range [s0, s1) of a round (k, i) = kernel f, whose pieces
 // g0 .. g0 + np - 1 (kernel-local g0l; absolute g0) cover it; last = 1 on a round's last segment.
 struct TileRec {
     int32_t f;
     int32_t g0;
-    uint32_t s;      // s0 | s1 << 11 | (np - 1) << 22 | nint << 28
+    uint32_t s;      // s0 | s1 << 12 | (np - 1) << 24 (s0, s1 <= 4096 point pairs, np <= 64)
     uint32_t ki;     // k | i << 13 | last << 26
-    int32_t g0l;
+    int32_t g0l;     // kernel-local first piece (< 256) | nint << 8
     int32_t bpo;     // the kernel's first interval start in ivl
 };
 
+template <class Tile>
 struct TileLds {
-    double key[kTileSort];
-    double2 V[kTileEl];              // (psi w/r, tpsi w/r) of every point pair; zero off the support
+    double key[Tile::kSort];
+    double2 V[Tile::kEl];              // (psi w/r, tpsi w/r) of every point pair; zero off the support
     double2 stage[kStageSlots];      // 15 np coefficients, 2 np piece records, intervals, (lo, hi)
-    double acc[kTileVt * kTileVs];
-    double alpha[kTilePairs];        // (n_tau . n_sigma) |tau||sigma| / (4 pi)
-    double beta[kTilePairs * 9];     // C_ab |tau||sigma| / (4 pi), entry e = 3a + b
+    double acc[Tile::kVt * Tile::kVs];
+    double alpha[Tile::kPairs];        // (n_tau . n_sigma) |tau||sigma| / (4 pi)
+    double beta[Tile::kPairs * 9];     // C_ab |tau||sigma| / (4 pi), entry e = 3a + b
     double wqq[49];                  // w_q w_q'
     double lam[7 * 3];               // lam_b(q')
-    double pmin[kTilePairs], pmax[kTilePairs];
+    double pmin[Tile::kPairs], pmax[Tile::kPairs];
     TileRec rec[kMaxRec];
-    int32_t bcum[kTileThreads + 1];  // candidates of the k-block: exclusive prefix over k
-    int32_t bia[kTileThreads];       // first trial index of each k's band
-    uint16_t idx[kTileSort];         // point pair p * 49 + 7 q + q' of each sorted distance
-    uint16_t aoff[kTilePairs * 9];   // entry (v_a(tau), v_b(sigma)) of the merged vertex tile
-    int32_t vt[kTileVt], vs[kTileVs];
-    int32_t pok[kTilePairs];
+    int32_t bcum[Tile::kThreads + 1];  // candidates of the k-block: exclusive prefix over k
+    int32_t bia[Tile::kThreads];       // first trial index of each k's band
+    uint16_t idx[Tile::kSort];         // point pair p * 49 + 7 q + q' of each sorted distance
+    uint16_t aoff[Tile::kPairs * 9];   // entry (v_a(tau), v_b(sigma)) of the merged vertex tile
+    int32_t vt[Tile::kVt], vs[Tile::kVs];
+    int32_t pok[Tile::kPairs];
     int32_t nvt, nvs, nrec;
-    int32_t wtot[kTileThreads / 64];
+    int32_t wtot[Tile::kThreads / 64];
 };
 
 // Number of keys <= v (le) or < v among the ascending key[0..n), one lane.
@@ -348,16 +360,17 @@ __device__ inline double group8_sum_dpp(double v)
     return v;
 }
 
-// Loads the LDS stage of record R into registers (slot e = tid + kTileThreads m).
-__device__ inline void stage_fetch(const TileRec& R, const TableView& tv, double2 (&st)[kStageRegs])
+// Loads the LDS stage of record R into registers (slot e = tid + threads m).
+template <class Tile>
+__device__ inline void stage_fetch(const TileRec& R, const TableView& tv, double2 (&st)[Tile::kStageRegs])
 {
-    const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+    const int np = (int)((R.s >> 24) & 63u) + 1, nint = R.g0l >> 8;
     const int nc = kNc * np, nm = nc + 2 * np, ni = nm + nint;
     const double2* meta2 = reinterpret_cast<const double2*>(tv.meta);
     const double2* ivl2 = reinterpret_cast<const double2*>(tv.ivl);
 #pragma unroll
-    for (int m = 0; m < kStageRegs; ++m) {
-        const int e = threadIdx.x + kTileThreads * m;
+    for (int m = 0; m < Tile::kStageRegs; ++m) {
+        const int e = threadIdx.x + Tile::kThreads * m;
         double2 v = make_double2(0.0, 0.0);
         if (e < nc) v = tv.coef[(int64_t)R.g0 * kNc + e];
         else if (e < nm) v = meta2[2 * (int64_t)R.g0 + (e - nc)];
@@ -367,21 +380,26 @@ __device__ inline void stage_fetch(const TileRec& R, const TableView& tv, double
     }
 }
 
-__device__ inline void stage_store(const TileRec& R, double2* stage, const double2 (&st)[kStageRegs])
+template <class Tile>
+__device__ inline void stage_store(const TileRec& R, double2* stage, const double2 (&st)[Tile::kStageRegs])
 {
-    const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+    const int np = (int)((R.s >> 24) & 63u) + 1, nint = R.g0l >> 8;
     const int used = (kNc + 2) * np + nint + 1;
 #pragma unroll
-    for (int m = 0; m < kStageRegs; ++m) {
-        const int e = threadIdx.x + kTileThreads * m;
+    for (int m = 0; m < Tile::kStageRegs; ++m) {
+        const int e = threadIdx.x + Tile::kThreads * m;
         if (e < used) stage[e] = st[m];
     }
 }
 
-__global__ void __launch_bounds__(kTileThreads, 2)
+template <class Tile>
+__global__ void __launch_bounds__(Tile::kThreads, 2)
 k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
                ProductView pv, const int2* __restrict__ tiles, int64_t ntiles, unsigned long long* counter)
 {
+    constexpr int kTileT = Tile::kT, kTileS = Tile::kS, kTilePairs = Tile::kPairs, kTileEl = Tile::kEl, kTileSort = Tile::kSort;
+    constexpr int kTileThreads = Tile::kThreads, kTileVt = Tile::kVt, kTileVs = Tile::kVs, kChunkMax = Tile::kChunkMax;
+    constexpr int kDz = Tile::kDz, kStageRegs = Tile::kStageRegs;
     // consecutive workgroups go to the 8 XCDs in turn: give each XCD one contiguous range of the
     // tile list (same test rows, shared L2 lines for the output)
     const int64_t per = (ntiles + 7) / 8;
@@ -393,7 +411,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     __shared__ PieceTable spt;
-    __shared__ TileLds L;
+    __shared__ TileLds<Tile> L;
     load_piece_table(spt, tv.pt);
     if (tid == 0) {
         int n = 0;
@@ -534,10 +552,10 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
         rule7_point(q, l0, l1, l2, w);
         la[q] = gm < 3 ? l0 : (gm < 6 ? l1 : l2);
     }
-    // band addresses of the lane's entries z = tid, tid + 256 of the merged vertex tile (time row kcur)
+    // band addresses of the lane's entries z = tid + threads h of the merged vertex tile (time row kcur)
     int kcur = -1;
-    int dz_ilo[2] = {0, 0}, dz_B[2] = {0, 0}, dz_lj[2] = {0, 0};
-    int64_t dz_vo[2] = {0, 0};
+    int dz_ilo[kDz] = {}, dz_B[kDz] = {}, dz_lj[kDz] = {};
+    int64_t dz_vo[kDz] = {};
     for (int kb = 0; kb < N; kb += kTileThreads) {
         // band [ia, ib] of every k of the block: supp psi_{k,i} meets (wmin, wmax); both ends of the
         // support are non-increasing in i, so both ends of the band are binary searches
@@ -626,10 +644,9 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                                     TileRec& R = out[sg];
                                     R.f = f;
                                     R.g0 = base + ga;
-                                    R.s = (uint32_t)sa | ((uint32_t)sb << 11) | ((uint32_t)(np - 1) << 22) |
-                                          ((uint32_t)kd.nint << 28);
+                                    R.s = (uint32_t)sa | ((uint32_t)sb << 12) | ((uint32_t)(np - 1) << 24);
                                     R.ki = (uint32_t)k | ((uint32_t)i << 13) | ((uint32_t)last << 26);
-                                    R.g0l = ga;
+                                    R.g0l = ga | (kd.nint << 8);
                                     R.bpo = kd.bp_off;
                                     ok[sg] = true;
                                 }
@@ -662,14 +679,14 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
             double2 st[kStageRegs];
             {
                 const TileRec R0 = L.rec[0];
-                stage_fetch(R0, tv, st);
-                stage_store(R0, L.stage, st);
+                stage_fetch<Tile>(R0, tv, st);
+                stage_store<Tile>(R0, L.stage, st);
             }
             __syncthreads();
             for (int n = 0; n < nrec; ++n) {
                 const TileRec R = L.rec[n];
-                const int s0 = (int)(R.s & 2047u), s1 = (int)((R.s >> 11) & 2047u);
-                const int np = (int)((R.s >> 22) & 63u) + 1, nint = (int)(R.s >> 28);
+                const int s0 = (int)(R.s & 4095u), s1 = (int)((R.s >> 12) & 4095u);
+                const int np = (int)((R.s >> 24) & 63u) + 1, nint = R.g0l >> 8, g0l = R.g0l & 255;
                 const int k = (int)(R.ki & 8191u), i = (int)((R.ki >> 13) & 8191u);
                 const bool last = (R.ki >> 26) & 1u;
                 const double2* sc = L.stage;
@@ -677,13 +694,13 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                 const double2* si = sm + 2 * np;
                 const double2 lohi = si[nint];
                 const bool more = n + 1 < nrec;
-                if (more) stage_fetch(L.rec[n + 1], tv, st);
+                if (more) stage_fetch<Tile>(L.rec[n + 1], tv, st);
                 if (!pv.y && k != kcur) {
                     // band addresses of the lane's entries of the merged vertex tile for time row k;
                     // the loads complete while the record is evaluated
                     kcur = k;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < kDz; ++h) {
                         const int z = tid + h * kTileThreads;
                         dz_B[h] = 0;
                         if (z < kTileVt * kTileVs) {
@@ -718,7 +735,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                     }
                 }
                 if (cnt > 0) {
-                    int rel = piece_local(rr[0], si, nint, spt) - R.g0l;
+                    int rel = piece_local(rr[0], si, nint, spt) - g0l;
                     rel = rel < 0 ? 0 : (rel < np ? rel : np - 1);
                     double rhi = sm[2 * rel].x;
                     while (rr[0] >= rhi && rel + 1 < np) rhi = sm[2 * ++rel].x;
@@ -763,7 +780,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                     nq += (unsigned long long)cnt;
                 }
                 __syncthreads();
-                if (more) stage_store(L.rec[n + 1], L.stage, st);
+                if (more) stage_store<Tile>(L.rec[n + 1], L.stage, st);
                 if (last) {
                     // phase 2: lane (pair gp, row q = gm < 7) sums its row over q' into
                     // (R_0, R_1, R_2, T)(q), kept in the row's first two slots; lane gm then forms
@@ -816,7 +833,7 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
                 __syncthreads();
                 if (last) {
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < kDz; ++h) {
                         const int z = tid + h * kTileThreads;
                         if (z < kTileVt * kTileVs) {
                             const double v = L.acc[z];
@@ -1118,28 +1135,42 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
                        ilo, Bt);
 }
 
+int tile_variants() { return 2; }
+
+void tile_shape(int variant, int* test, int* trial)
+{
+    *test = variant == 1 ? TileB::kT : TileA::kT;
+    *trial = variant == 1 ? TileB::kS : TileA::kS;
+}
+
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    const double* px, double* py, const int2* tiles, int64_t ntiles, unsigned long long* counter,
-                    hipStream_t s)
+                    const double* px, double* py, const int2* tiles, int64_t ntiles, int variant,
+                    unsigned long long* counter, hipStream_t s)
 {
     if (ntiles <= 0) return;
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
     const ProductView pv{px, py, band.M};
-    hipLaunchKernelGGL(k_regular_tile, grid, dim3(kTileThreads), 0, s, g, tv, t, band, val, valf, pv, tiles, ntiles,
-                       counter);
+    if (variant == 1)
+        hipLaunchKernelGGL(k_regular_tile<TileB>, grid, dim3(TileB::kThreads), 0, s, g, tv, t, band, val, valf, pv,
+                           tiles, ntiles, counter);
+    else
+        hipLaunchKernelGGL(k_regular_tile<TileA>, grid, dim3(TileA::kThreads), 0, s, g, tv, t, band, val, valf, pv,
+                           tiles, ntiles, counter);
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau, in
 // row order.  (Ordering the tiles by the distance of the two blocks, so that workgroups running
-// together share Chebyshev pieces, measured slower: 1.69 s against 1.59 s on the 5120-triangle
-// sphere with 64 bases.)
-std::vector<int32_t> regular_tiles(int E)
+// together share Chebyshev pieces, measured slower with per-lane global coefficient loads: 1.69 s
+// against 1.59 s on the 5120-triangle sphere with 64 bases.)
+std::vector<int32_t> regular_tiles(int E, int variant)
 {
+    int TT, TS;
+    tile_shape(variant, &TT, &TS);
     std::vector<int32_t> out;
-    const int nA = (E + kTileT - 1) / kTileT, nB = (E + kTileS - 1) / kTileS;
+    const int nA = (E + TT - 1) / TT, nB = (E + TS - 1) / TS;
     for (int a = 0; a < nA; ++a)
         for (int b = 0; b < nB; ++b)
-            if (b * kTileS + kTileS - 1 > a * kTileT) {
+            if (b * TS + TS - 1 > a * TT) {
                 out.push_back(a);
                 out.push_back(b);
             }

@@ -316,10 +316,14 @@ void launch_geometry(const double* xyz, const int32_t* tri, int E, double* geo_P
 void launch_layout(BandView band, const double* xyz, const double* rho, const double* t, int16_t* ilo,
                    int32_t* Bk, hipStream_t s);
 
+// Tile shapes of the regular-pair kernel: variant 0 = 4 x 8 triangles on 256 lanes, 1 = 8 x 8 on
+// 512; tiles of a shape from regular_tiles(E, variant).
+int tile_variants();
+void tile_shape(int variant, int* test, int* trial);
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
-                    const double* px, double* py, const int2* tiles, int64_t ntiles, unsigned long long* counter,
-                    hipStream_t s);
-std::vector<int32_t> regular_tiles(int E);
+                    const double* px, double* py, const int2* tiles, int64_t ntiles, int variant,
+                    unsigned long long* counter, hipStream_t s);
+std::vector<int32_t> regular_tiles(int E, int variant);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      int max_points, double* val, float* valf, const double* px, double* py,

@@ -142,6 +142,37 @@ def test_small_meshes_every_block(tb, oracle_mod, case):
     ctx.close()
 
 
+def test_tile_shapes_every_block(tb, oracle_mod):
+    """Both tile shapes of the regular-pair kernel (4 x 8 and 8 x 8 triangles), forced in turn, on a
+    70-triangle torus (ragged in both shapes): every block against the oracle, the exact
+    quadrature-point count; then the timed choice reports an estimate for each shape."""
+    xyz, tri = torus(7, 5)
+    grid = graded_grid(6, 3.0, seed=23)
+    T = oracle_mod.fast_tables(xyz, grid, "bump")
+    A = oracle_mod.assemble_dense(xyz, tri, grid, tables=T)
+    count = oracle_mod.count_quad_evals(xyz, tri, grid)
+    ctx = tb.Context(0)
+    ctx.set_mesh(xyz, tri)
+    ctx.set_time_grid(grid, "bump")
+    blocks = {}
+    for v, shape in ((0, (4, 8)), (1, (8, 8))):
+        assert ctx.assemble_set_tiles(v) == 2
+        rep = ctx.assemble()
+        assert ctx.assemble_tuning()[0] == shape
+        blocks[v] = gpu_blocks(ctx, len(grid), len(xyz))
+        assert_blocks_close(blocks[v], A)
+        assert rep["quad_evals"] == count
+    assert np.abs(blocks[0] - blocks[1]).max() <= 1e-13 * np.abs(blocks[0]).max()
+    ctx.assemble_set_tiles(-1)
+    ctx.assemble()
+    shape, ms = ctx.assemble_tuning()
+    assert shape in ((4, 8), (8, 8)) and min(ms) > 0.0
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.assemble_set_tiles(2)
+    assert e.value.status == -1
+    ctx.close()
+
+
 def _sample_pairs(xyz, tri, rng, n_far):
     """Vertex pairs (j, l): the diagonal, edge neighbours, one at distance ~1, far ones."""
     l0 = int(tri[0][0])
