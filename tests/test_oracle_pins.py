@@ -255,6 +255,69 @@ def test_local_integrals_with_linear_psi(oracle_mod, rel):
             assert abs(loc[a, b] - ref) < 1e-14 * (abs(ref) + 1e-3)
 
 
+def _duffy_rule(P, n):
+    """Product Gauss-Legendre rule of n x n points on the triangle P (collapsed square: barycentrics
+    (1 - s, s (1 - t), s t), weight 2|P| s w_s w_t); returns points, weights (summing to |P|) and
+    the barycentrics."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    u, wu = 0.5 * (x + 1.0), 0.5 * w
+    S, T = np.meshgrid(u, u, indexing="ij")
+    W = np.outer(wu, wu)
+    lam = np.stack([1.0 - S, S * (1.0 - T), S * T], axis=-1).reshape(-1, 3)
+    area = 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+    return lam @ P, (2.0 * area * S * W).ravel(), lam
+
+
+def _pair_reference(oracle_mod, xyz, tri, ex, ey, grid, tables, n, swap=False):
+    """The regular-pair block of eq. (MatrixEntries) by the n x n-point product rule on both
+    triangles; swap exchanges psi and tilde psi."""
+    N = len(grid)
+    Px, nx, ax, ea = _geom(xyz, tri, ex)
+    Py, ny, ay, eb = _geom(xyz, tri, ey)
+    C = np.array([[np.dot(ea[a], eb[b]) / (4 * ax * ay) for b in range(3)] for a in range(3)])
+    X, WX, LX = _duffy_rule(Px, n)
+    Y, WY, LY = _duffy_rule(Py, n)
+    r = np.linalg.norm(X[:, None, :] - Y[None, :, :], axis=2).ravel()
+    W = (WX[:, None] * WY[None, :]).ravel() / (4 * np.pi * r)
+    a, b = (1, 0) if swap else (0, 1)
+    ref = np.zeros((N, N, 3, 3))
+    for k in range(N):
+        for i in range(N):
+            ps = np.array([tables.psi(k, i, rr) for rr in r])
+            if np.any(ps):
+                ref[k, i] = (np.dot(nx, ny) * (LX.T @ (ps[:, a] * W).reshape(len(X), len(Y)) @ LY)
+                             + (ps[:, b] * W).sum() * C)
+    return ref
+
+
+def test_regular_pair_against_high_order_rule(oracle_mod):
+    """P13: pairs without a common vertex at centroid distance ~0.8, with the real psi, tilde psi
+    of a graded grid: the oracle's 7 x 7-point value of eq. (MatrixEntries) against a 196 x
+    196-point product Gauss rule of the same integrand (psi, tilde psi from the oracle's tables,
+    pinned against their definition elsewhere).  The difference is the 7-point rule's error: it must
+    be small on icosphere level 3 and fall by more than 8 from level 2 (it falls as the triangles
+    shrink at fixed kernels); a wrong weight, barycentric or area factor, or a psi <-> tilde psi
+    swap, would stay of the size of the block."""
+    grid = graded_grid(6, 3.0, seed=31)
+    errs = {}
+    for lev in (2, 3):
+        xyz, tri = icosphere(lev)
+        sets = [set(t) for t in tri]
+        cen = xyz[tri].mean(axis=1)
+        d = np.linalg.norm(cen - cen[0], axis=1)
+        ey = min((e for e in range(1, len(tri)) if not (sets[0] & sets[e])), key=lambda e: abs(d[e] - 0.8))
+        tables = oracle_mod.fast_tables(xyz, grid, "bump")
+        loc = oracle_mod.pair_local(xyz, tri, 0, ey, grid)
+        ref = _pair_reference(oracle_mod, xyz, tri, 0, ey, grid, tables, 14)
+        scale = np.abs(ref).max()
+        assert scale > 0
+        errs[lev] = np.abs(loc - ref).max() / scale
+        if lev == 3:
+            swapped = _pair_reference(oracle_mod, xyz, tri, 0, ey, grid, tables, 14, swap=True)
+            assert np.abs(loc - swapped).max() / scale > 100 * errs[3]
+    assert errs[3] < 5e-4 and errs[2] > 8 * errs[3], errs
+
+
 @pytest.mark.parametrize("rel", ["coincident", "edge", "vertex"])
 def test_singular_rules_exact_for_polynomial_kernel(oracle_mod, rel):
     """P8: with psi = tilde psi = r^3 the kernel is |x-y|^2, a polynomial of degree 2 in x and
