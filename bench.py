@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
     ap.add_argument("--no-potential", action="store_true", help="skip the field evaluation leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-meshes group assembly leg")
+    ap.add_argument("--no-equal-blocks", action="store_true",
+                    help="skip the equidistant-grid leg (equal blocks copied against integrated)")
     ap.add_argument("--batch-rhs", type=int, default=32,
                     help="right-hand sides of the batched learned solve (0 = skip the batched leg)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -230,6 +232,36 @@ def uneven_leg(tb):
     return {"meshes": [20 * nu * nu for nu in nus], "time_bases": [16 + (64 - 16) * r // 7 for r in range(8)],
             "quad_evals": int(quad), "sequential_ms": seq, "group_ms": grp,
             "sequential_quad_evals_per_s": quad / (seq * 1e-3), "group_quad_evals_per_s": quad / (grp * 1e-3)}
+
+
+def equal_blocks_leg(tb, cfg):
+    """The workload's mesh with 64 equidistant bases on the same [0, T]: FP64 assembly integrating
+    every block against the assembly that copies the equal blocks of the inner nodes (eq.
+    (relationAtildeBlock)); time, quadrature points integrated, and the largest difference of
+    200000 sampled entries relative to the largest sampled entry."""
+    import numpy as np
+    from workloads import equidistant_grid
+    xyz, tri = cfg["mesh"]
+    grid = equidistant_grid(len(cfg["grid"]), float(cfg["grid"][-1]))
+    c = tb.Context(0)
+    c.set_mesh(xyz, tri)
+    c.set_time_grid(grid, "bump")
+    sample = sample_entries(c, {"mesh": cfg["mesh"], "grid": grid}, 200000, 7)
+    res = {}
+    for reuse in (0, 1):
+        c.set_block_reuse(reuse)
+        r = [c.assemble(tb.FP64) for _ in range(2)][-1]
+        res[reuse] = (r, c.get_entries(*sample))
+        print(f"# equal blocks {'copied' if reuse else 'integrated'}: assembly {r['ms_total']:.1f} ms "
+              f"(regular {r['ms_regular']:.1f}, copies {r['ms_reuse']:.1f})", file=sys.stderr, flush=True)
+    c.close()
+    (r0, e0), (r1, e1) = res[0], res[1]
+    return {"workload": f"{cfg['name'].split('_')[0]}_eq{len(grid)}", "time_bases": len(grid),
+            "integrated": {"ms": r0["ms_total"], "ms_regular": r0["ms_regular"], "quad_evals": int(r0["quad_evals"])},
+            "copied": {"ms": r1["ms_total"], "ms_regular": r1["ms_regular"], "ms_copies": r1["ms_reuse"],
+                       "quad_evals": int(r1["quad_evals"]), "blocks_copied": int(r1["blocks_reused"])},
+            "speedup": r0["ms_total"] / r1["ms_total"],
+            "sampled_max_rel_diff": float(np.abs(e1 - e0).max() / max(np.abs(e0).max(), 1e-300))}
 
 
 def potential_leg(ctx, tb, alpha, cfg):
@@ -685,6 +717,8 @@ def main():
         out["learned"] = learned_leg(ctx, tb, args, g, alpha, out.get("solve"), budget)
     if not args.no_uneven and budget.allows("uneven", 30):
         out["uneven"] = uneven_leg(tb)
+    if not args.no_equal_blocks and budget.allows("equal_blocks", 25):
+        out["equal_blocks"] = equal_blocks_leg(tb, cfg)
     ctx.close()
     emit()
 

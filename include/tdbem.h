@@ -70,6 +70,11 @@ typedef struct {
     int64_t bytes_matrix;        /* device bytes of the assembled blocks */
     double ms_tables, ms_layout, ms_regular, ms_singular, ms_total;
     int64_t quad_evals_regular;  /* the part of quad_evals computed by the regular-pair kernel */
+    int64_t blocks_reused;       /* nonzero time blocks A_{k,i} (temporal bases k, i) copied from an
+                                    equal block instead of integrated (equidistant grids, eq.
+                                    (relationAtildeBlock)); quad_evals counts only the integrated
+                                    ones.  0 on other grids and with reuse off */
+    double ms_reuse;             /* time of those copies (part of ms_total) */
 } tdbem_assembly_report;
 
 typedef struct {
@@ -155,6 +160,17 @@ tdbem_status tdbem_assemble_tuning(tdbem_ctx *ctx, int32_t *tile_test, int32_t *
 /* Use tile shape v (0: 4 x 8, 1: 8 x 8; the count goes to nvariants when not NULL) for every later
  * assembly instead of the timed choice; v = -1 returns to timing.  TDBEM_EINVAL for another v. */
 tdbem_status tdbem_assemble_set_tiles(tdbem_ctx *ctx, int32_t v, int32_t *nvariants);
+
+/* Equal blocks (eq. (relationAtildeBlock), Section 5.1).  On an equidistant grid (every
+ * |t_n - n T / (N - 1)| <= 1e-12 T) the bases of the inner nodes 1..N-2 are translates, so the
+ * node block of inner nodes (k, i) with 2 <= i <= k equals block (k - i + 1, 1) and the
+ * superdiagonal block (k, k + 1), k >= 2, equals (1, 2).  With enable = 1 (the default) such an
+ * assembly integrates only the first two block columns, the last block row and the blocks (1, 2),
+ * (N - 2, N - 1), and copies the stored values of the others (O(N) instead of O(N^2) blocks
+ * integrated; the report's blocks_reused counts the copies).  enable = 0 integrates every
+ * block.  Takes effect at the next tdbem_assemble; no effect on other grids or on
+ * tdbem_matvec_free.  TDBEM_EINVAL unless enable is 0 or 1. */
+tdbem_status tdbem_set_block_reuse(tdbem_ctx *ctx, int32_t enable);
 
 /* Assemble the problems of n distinct contexts (meshes and grids of any sizes, all on one device)
  * concurrently: one host thread per context runs tdbem_assemble on that context's stream, so the

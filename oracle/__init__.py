@@ -68,7 +68,7 @@ def lib():
         L.orc_rhs_plane_pulse.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp]
         L.orc_count_quad_evals.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int]
+                                           ctypes.c_int, vp]
         L.orc_count_quad_evals.restype = ctypes.c_int64
         L.orc_local_batch.argtypes = [dp, ip, ctypes.c_int, ip, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, vp, dp]
@@ -244,9 +244,16 @@ def rhs_plane_pulse(xyz, tri, grid, direction, t0, width, kind="bump", p=0):
     return out
 
 
-def count_quad_evals(xyz, tri, grid, ss_order=4, p=0):
+def count_quad_evals(xyz, tri, grid, ss_order=4, p=0, node_blocks=None):
+    """Quadrature-point count; node_blocks: optional (N, N) boolean mask of the node blocks
+    (test node, trial node) to count."""
     x, xp = _d(xyz); t, tp = _i(tri); g, gp = _d(grid)
-    return int(lib().orc_count_quad_evals(xp, len(x), tp, len(t), gp, len(g), p, ss_order))
+    mask = None
+    if node_blocks is not None:
+        mask = np.ascontiguousarray(node_blocks, dtype=np.uint8)
+        assert mask.shape == (len(g), len(g))
+    return int(lib().orc_count_quad_evals(xp, len(x), tp, len(t), gp, len(g), p, ss_order,
+                                          mask.ctypes.data_as(ctypes.c_void_p) if mask is not None else None))
 
 
 def local_batch(xyz, tri, taus, sigmas, grid, kind="bump", ss_order=4, tables=None, p=0):

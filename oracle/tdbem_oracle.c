@@ -933,9 +933,11 @@ int orc_potential_dl(const double *xyz, int M, const int32_t *tri, int E, const 
 }
 
 /* Quadrature-point count of the method (one unit = one (x_q, y_q', k, i) with r inside the open
- * support of psi_{k,i}), over unordered triangle pairs, computed by brute force. */
+ * support of psi_{k,i}), over unordered triangle pairs, computed by brute force.  node_mask
+ * (N x N, row = test node) restricts the count to the bases of the node blocks marked nonzero;
+ * NULL counts every block. */
 int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E, const double *t,
-                             int N, int porder, int ss_order)
+                             int N, int porder, int ss_order, const unsigned char *node_mask)
 {
     (void)M;
     int64_t total = 0;
@@ -981,6 +983,7 @@ int64_t orc_count_quad_evals(const double *xyz, int M, const int32_t *tri, int E
                     for (int k = 0; k < L; ++k)
                         for (int i = 0; i < L; ++i) {
                             double lo, hi;
+                            if (node_mask && !node_mask[(k / (porder + 1)) * N + i / (porder + 1)]) continue;
                             orc_support(t, N, porder, k, i, &lo, &hi);
                             if (r > lo && r < hi) ++total;
                         }

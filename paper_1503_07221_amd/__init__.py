@@ -33,7 +33,8 @@ EXPORTED_SYMBOLS = ["tdbem_create", "tdbem_destroy", "tdbem_last_error", "tdbem_
                     "tdbem_matvec_multi_tuning", "tdbem_matvec_multi_set_variant", "tdbem_assemble_group",
                     "tdbem_lp_num_params", "tdbem_lp_init", "tdbem_lp_set_params", "tdbem_lp_get_params",
                     "tdbem_lp_apply", "tdbem_lp_gradient", "tdbem_matvec_transpose", "tdbem_lp_train",
-                    "tdbem_lp_make_pairs", "tdbem_lp_train_pairs", "tdbem_assemble_tuning", "tdbem_assemble_set_tiles"]
+                    "tdbem_lp_make_pairs", "tdbem_lp_train_pairs", "tdbem_assemble_tuning", "tdbem_assemble_set_tiles",
+                    "tdbem_set_block_reuse"]
 
 # preconditioner kinds of SolveOpts.precond_kind
 PRECOND_ALG1, PRECOND_LEARNED, PRECOND_LEARNED_THEN_ALG1, PRECOND_DEFLATION = 0, 1, 2, 3
@@ -55,7 +56,8 @@ class AssemblyReport(ctypes.Structure):
                 ("pairs_vertex", ctypes.c_int64), ("table_functions", ctypes.c_int64),
                 ("bytes_matrix", ctypes.c_int64), ("ms_tables", ctypes.c_double), ("ms_layout", ctypes.c_double),
                 ("ms_regular", ctypes.c_double), ("ms_singular", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("quad_evals_regular", ctypes.c_int64)]
+                ("quad_evals_regular", ctypes.c_int64), ("blocks_reused", ctypes.c_int64),
+                ("ms_reuse", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -147,6 +149,7 @@ def load_library(path=LIB_PATH):
     L.tdbem_lp_make_pairs.argtypes = [vp, i64, ctypes.c_uint64, vp, vp]
     L.tdbem_assemble_tuning.argtypes = [vp, P(i32), P(i32), P(dp)]
     L.tdbem_assemble_set_tiles.argtypes = [vp, i32, P(i32)]
+    L.tdbem_set_block_reuse.argtypes = [vp, i32]
     L.tdbem_lp_train_pairs.argtypes = [vp, vp, vp, vp, i64, P(TrainOpts), fp, P(TrainReport)]
     for name in EXPORTED_SYMBOLS:
         if name not in ("tdbem_destroy", "tdbem_last_error", "tdbem_lp_num_params"):
@@ -256,6 +259,11 @@ class Context:
         n = ctypes.c_int32()
         self._check(self.lib.tdbem_assemble_set_tiles(self.h, int(v), ctypes.byref(n)))
         return n.value
+
+    def set_block_reuse(self, enable):
+        """1: copy the equal blocks of an equidistant grid instead of integrating them (default);
+        0: integrate every block.  Takes effect at the next assembly."""
+        self._check(self.lib.tdbem_set_block_reuse(self.h, int(enable)))
 
     def get_entries(self, k, i, j, l):
         k, i, j, l = (np.ascontiguousarray(np.broadcast_to(a, np.broadcast(k, i, j, l).shape).ravel(), dtype=np.int32)

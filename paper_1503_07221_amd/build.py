@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdbem.so")
-SOURCES = ["api.hip", "k_tables.hip", "k_assemble.hip", "k_linalg.hip", "k_learned.hip", "k_batched.hip", "k_potential.hip"]
+SOURCES = ["api.hip", "k_tables.hip", "k_assemble.hip", "k_blocks.hip", "k_linalg.hip", "k_learned.hip", "k_batched.hip", "k_potential.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # keep the compiler from forming packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -182,6 +182,11 @@ struct tdbem_ctx {
     // tables
     DBuf d_desc, d_fid, d_ivl, d_coef, d_fk, d_fi, d_meta, d_cell;
     int64_t nfunc = 0;
+    // equal blocks of an equidistant grid: the assembly integrates only the kernels of d_fid_asm
+    // (copied blocks marked -1) and copies the others afterwards
+    bool equidistant = false, reuse = true;
+    DBuf d_fid_asm;
+    int64_t blocks_reused = 0;
     // band storage
     DBuf d_ilo, d_B, d_voff, d_val, d_counter;
     std::vector<int32_t> Bk;
@@ -261,6 +266,12 @@ struct tdbem_ctx {
         tv.nodes = nodes;
         tv.p1 = p1;
         tv.pt = pieces;
+        return tv;
+    }
+    TableView asm_tables() const
+    {
+        TableView tv = tables();
+        if (blocks_reused > 0) tv.fid = d_fid_asm.as<int32_t>();
         return tv;
     }
     BandView band() const
@@ -551,6 +562,10 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx* c, const double* t, int32_t N, tdbem
     c->N = N * (p + 1);
     c->cut = (int)cutoff;
     c->t.assign(t, t + N);
+    // t_n = n T / (N - 1) up to rounding: the inner nodes' bases are translates of one another
+    double dev = 0.0;
+    for (int s = 0; s < N; ++s) dev = std::max(dev, std::fabs(t[s] - s * (t[N - 1] / (N - 1))));
+    c->equidistant = dev <= 1e-12 * t[N - 1];
     TRY(upload(c, c->d_t, c->t.data(), c->t.size()));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_grid = true;
@@ -642,6 +657,19 @@ static tdbem_status build_tables(tdbem_ctx* c)
     const int64_t npieces = (int64_t)pc_f.size();
     TRY(upload(c, c->d_desc, desc.data(), desc.size()));
     TRY(upload(c, c->d_fid, fid.data(), fid.size()));
+    c->blocks_reused = 0;
+    if (c->reuse && c->equidistant) {
+        std::vector<int32_t> fa(fid);
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < N; ++i) {
+                int sk, si;
+                if (fa[(size_t)k * N + i] >= 0 && equal_block_source(nodes, k / p1, i / p1, sk, si)) {
+                    fa[(size_t)k * N + i] = -1;
+                    ++c->blocks_reused;
+                }
+            }
+        if (c->blocks_reused > 0) TRY(upload(c, c->d_fid_asm, fa.data(), fa.size()));
+    }
     // padding: the regular kernel reads all kMaxIntervals starts of a kernel at once
     ivl.insert(ivl.end(), 2 * kMaxIntervals, 0.0);
     TRY(upload(c, c->d_ivl, ivl.data(), ivl.size()));
@@ -721,11 +749,11 @@ static tdbem_status tune_tiles(tdbem_ctx* c, double* v64, float* v32)
     int best = 0;
     for (int v = 0; v < tile_variants(); ++v) {
         const int2* smp = c->d_tiles_sample[v].as<int2>();
-        launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
+        launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
                        std::min<int64_t>(c->ntiles_sample[v], 64), v, scratch_count.as<unsigned long long>(),
                        c->stream);
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
+        launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr, smp,
                        c->ntiles_sample[v], v, scratch_count.as<unsigned long long>(), c->stream);
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipGetLastError());
@@ -750,11 +778,11 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     TRY(set_device(c));
     c->assembled = false;
     c->prec = (int)prec;
-    hipEvent_t ev[5];
+    hipEvent_t ev[6];
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
     struct EvGuard {
         hipEvent_t* e;
-        ~EvGuard() { for (int s = 0; s < 5; ++s) (void)hipEventDestroy(e[s]); }
+        ~EvGuard() { for (int s = 0; s < 6; ++s) (void)hipEventDestroy(e[s]); }
     } guard{ev};
     HIPCHK(c, hipEventRecord(ev[0], c->stream));
     TRY(run_geometry(c));
@@ -763,23 +791,28 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     TRY(build_layout(c, (int)prec));
     ALLOC(c, c->d_counter, sizeof(unsigned long long) * 2);
     HIPCHK(c, hipMemsetAsync(c->d_counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
-    HIPCHK(c, hipEventRecord(ev[2], c->stream));
     double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
     float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
     unsigned long long* cnt = c->d_counter.as<unsigned long long>();
     TRY(tune_tiles(c, v64, v32));
+    HIPCHK(c, hipEventRecord(ev[2], c->stream));
     // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
     // storage
-    launch_regular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr,
+    launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr,
                    c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v, cnt, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[3], c->stream));
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
-    launch_singular(c->geom(), c->tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
+    launch_singular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
                     c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, v64, v32,
                     nullptr, nullptr, cnt + 1, c->stream);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    if (c->blocks_reused > 0) {
+        launch_block_copy(c->band(), v64, v32, c->stream);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipEventRecord(ev[5], c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     unsigned long long counts[2];
     HIPCHK(c, hipMemcpy(counts, c->d_counter.p, sizeof(counts), hipMemcpyDeviceToHost));
@@ -787,8 +820,8 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     ++c->assemblies;
     c->mm_variant = -1;
     if (rep) {
-        float ms[4];
-        for (int s = 0; s < 4; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
+        float ms[5];
+        for (int s = 0; s < 5; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
         rep->quad_evals = (int64_t)(counts[0] + counts[1]);
         rep->quad_evals_regular = (int64_t)counts[0];
         const int64_t E = c->E;
@@ -802,7 +835,9 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         rep->ms_layout = ms[1];
         rep->ms_regular = ms[2];
         rep->ms_singular = ms[3];
-        rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3];
+        rep->ms_reuse = ms[4];
+        rep->blocks_reused = c->blocks_reused;
+        rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3] + ms[4];
     }
     return TDBEM_OK;
 }
@@ -883,6 +918,8 @@ tdbem_status tdbem_matvec_free(tdbem_ctx* c, const double* x, double* y, tdbem_a
         rep->ms_regular = ms[2];
         rep->ms_singular = ms[3];
         rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3];
+        rep->ms_reuse = 0.0;
+        rep->blocks_reused = 0;
     }
     return TDBEM_OK;
 }
@@ -2332,6 +2369,15 @@ tdbem_status tdbem_assemble_tuning(tdbem_ctx* c, int32_t* tile_test, int32_t* ti
     if (tile_trial) *tile_trial = ts;
     if (ms)
         for (int v = 0; v < tile_variants(); ++v) ms[v] = c->tile_ms[v];
+    return TDBEM_OK;
+}
+
+tdbem_status tdbem_set_block_reuse(tdbem_ctx* c, int32_t enable)
+{
+    if (!c) return TDBEM_EINVAL;
+    c->err.clear();
+    if (enable != 0 && enable != 1) FAIL(c, TDBEM_EINVAL, "block reuse must be 0 or 1, got %d", enable);
+    c->reuse = enable == 1;
     return TDBEM_OK;
 }
 

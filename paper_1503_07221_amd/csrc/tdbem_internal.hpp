@@ -254,6 +254,26 @@ constexpr int kBT = 64;
 __host__ __device__ inline int64_t tri_index(int64_t l, int64_t j) { return l * (l + 1) / 2 + j; }
 __host__ __device__ inline int64_t band_tile(int64_t l, int64_t j) { return tri_index(l / kBT, j / kBT); }
 
+// Equal time blocks of an equidistant grid (eq. (relationAtildeBlock)): the bases of the inner
+// nodes 1..nodes-2 are translates of one another, so the node block (kn, in) of two inner nodes
+// with 2 <= in <= kn equals (kn - in + 1, 1), and the superdiagonal block (kn, kn + 1) with kn >= 2
+// equals (1, 2).  Sets (sk, si) and returns true for such a copy; false for the blocks that are
+// integrated (the first two columns, the last row, (1, 2) and (nodes - 2, nodes - 1)).  Every
+// source is itself integrated.
+__host__ __device__ inline bool equal_block_source(int nodes, int kn, int in, int& sk, int& si)
+{
+    if (kn < 1 || kn > nodes - 2 || in < 2 || in > nodes - 2 || in > kn + 1) return false;
+    if (in <= kn) {
+        sk = kn - in + 1;
+        si = 1;
+        return true;
+    }
+    if (kn == 1) return false;
+    sk = 1;
+    si = 2;
+    return true;
+}
+
 struct BandView {
     const int16_t* ilo;    // first trial index of every (k, l, j <= l), tiled as above
     const int32_t* B;      // B[k nt + t]
@@ -328,6 +348,9 @@ void launch_singular(GeomView g, TableView tv, const double* t, BandView band, c
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      int max_points, double* val, float* valf, const double* px, double* py,
                      unsigned long long* counter, hipStream_t s);
+// Copies every block that equal_block_source maps to another one from that block, in place in
+// the band storage (all rows k of a node, every basis pair of the node pair).
+void launch_block_copy(BandView band, double* val, float* valf, hipStream_t s);
 // Allocation-free entry query: static device staging of kNoAllocEntries queries (4 int32 index
 // arrays and the float64 results); noalloc_scratch returns its address on `device` (current).
 constexpr int64_t kNoAllocEntries = 65536;

@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from tests.conftest import gpu_available
+from tests.conftest import gpu_available, integrated_node_blocks
 from tests.test_oracle_convergence import Y00, g_n0, g_n1, phi_paper_n0, phi_paper_n1
 from workloads import equidistant_grid, graded_grid, icosphere, torus
 
@@ -89,7 +89,8 @@ def test_blocks_and_tables(ctx, tb, oracle_mod, case):
                 continue
             worst = max(worst, np.abs(G[k, i] - A[k, i]).max() / sc)
     assert worst <= BLOCK_TOL, worst
-    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, p=p)
+    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, p=p,
+                                                            node_blocks=integrated_node_blocks(grid))
 
 
 def test_rhs_and_product(ctx, tb, oracle_mod):

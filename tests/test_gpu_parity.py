@@ -9,7 +9,7 @@ held to MIXED_TOL relative per block.
 import numpy as np
 import pytest
 
-from tests.conftest import gpu_available
+from tests.conftest import gpu_available, integrated_node_blocks
 from workloads import equidistant_grid, graded_grid, get_config, icosphere, torus
 
 pytestmark = pytest.mark.gpu
@@ -138,7 +138,8 @@ def test_small_meshes_every_block(tb, oracle_mod, case):
     G = gpu_blocks(ctx, len(grid), len(xyz))
     assert_blocks_close(G, A)
     # the method's quadrature-point count, by brute force on the CPU
-    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, ss_order=order)
+    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, ss_order=order,
+                                                            node_blocks=integrated_node_blocks(grid))
     ctx.close()
 
 
@@ -161,7 +162,7 @@ def test_tile_shapes_every_block(tb, oracle_mod):
         assert ctx.assemble_tuning()[0] == shape
         blocks[v] = gpu_blocks(ctx, len(grid), len(xyz))
         assert_blocks_close(blocks[v], A)
-        assert rep["quad_evals"] == count
+        assert rep["quad_evals"] == count and rep["blocks_reused"] == 0
     assert np.abs(blocks[0] - blocks[1]).max() <= 1e-13 * np.abs(blocks[0]).max()
     ctx.assemble_set_tiles(-1)
     ctx.assemble()
@@ -169,6 +170,44 @@ def test_tile_shapes_every_block(tb, oracle_mod):
     assert shape in ((4, 8), (8, 8)) and min(ms) > 0.0
     with pytest.raises(tb.TdbemError) as e:
         ctx.assemble_set_tiles(2)
+    assert e.value.status == -1
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["sphere320_eq10", "sphere80_eq7_p1"])
+def test_equal_block_reuse(tb, oracle_mod, case):
+    """Equidistant grids, where the assembly copies equal blocks (eq. (relationAtildeBlock)) instead
+    of integrating them: every block against the oracle (which integrates every block), the
+    quadrature-point count over the integrated node blocks only, the same blocks as an assembly
+    with the copies switched off (which counts every block), and FP32 storage with copies."""
+    if case == "sphere320_eq10":
+        c = get_config("sphere320_eq10")
+        (xyz, tri), grid, p = c["mesh"], c["grid"], 0
+    else:
+        (xyz, tri), grid, p = icosphere(1), equidistant_grid(7, 3.0), 1
+    L, M = len(grid) * (p + 1), len(xyz)
+    A = oracle_mod.assemble_dense(xyz, tri, grid, tables=oracle_mod.fast_tables(xyz, grid, p=p), p=p)
+    ctx = tb.Context(0)
+    ctx.set_mesh(xyz, tri)
+    ctx.set_time_grid(grid, "bump", p=p)
+    rep = ctx.assemble()
+    assert rep["blocks_reused"] > 0
+    G = gpu_blocks(ctx, L, M)
+    assert_blocks_close(G, A)
+    assert rep["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, p=p,
+                                                            node_blocks=integrated_node_blocks(grid))
+    ctx.set_block_reuse(0)
+    rep0 = ctx.assemble()
+    assert rep0["blocks_reused"] == 0
+    assert rep0["quad_evals"] == oracle_mod.count_quad_evals(xyz, tri, grid, p=p) > rep["quad_evals"]
+    G0 = gpu_blocks(ctx, L, M)
+    assert np.abs(G - G0).max() <= 1e-13 * np.abs(G0).max()
+    ctx.set_block_reuse(1)
+    repm = ctx.assemble(tb.MIXED)
+    assert repm["blocks_reused"] == rep["blocks_reused"]
+    assert_blocks_close(gpu_blocks(ctx, L, M), A, tol=MIXED_TOL)
+    with pytest.raises(tb.TdbemError) as e:
+        ctx.set_block_reuse(2)
     assert e.value.status == -1
     ctx.close()
 

@@ -59,6 +59,7 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.tdbem_lp_make_pairs(None, 1, 0, None, None) == -1
     assert lib.tdbem_assemble_tuning(None, None, None, None) == -1
     assert lib.tdbem_assemble_set_tiles(None, 0, None) == -1
+    assert lib.tdbem_set_block_reuse(None, 1) == -1
     assert lib.tdbem_lp_train_pairs(None, None, None, None, 1, None, None, None) == -1
     assert lib.tdbem_lp_num_params(4) == 66112 and lib.tdbem_lp_num_params(0) == -1
     lib.tdbem_destroy(None)

@@ -560,6 +560,53 @@ def test_block_count_formula():
     assert 0.5 * (64 - 8 - 4) - 0.5 * (8 - 3 - 2) * max(8 - 3 - 1, 0) == 20
 
 
+@pytest.mark.parametrize("p", [0, 1])
+def test_equal_blocks_of_equidistant_grid(oracle_mod, p):
+    """On an equidistant grid the blocks of inner nodes depend on k - i only: A_{k,i} =
+    A_{k-i+1,1} for 2 <= i <= k <= N-2 and A_{k,k+1} = A_{1,2} for 2 <= k <= N-3 (eq.
+    (relationAtildeBlock), 0-based nodes, every basis pair of a node pair).  The blocks that stay
+    integrated are not copies: the first column against its shift, the last row against its
+    shift, (1, 2) against (0, 1).  For p = 1 the inner blocks also obey eq. (relationAblock):
+    A^{m1,m2} = (-1)^(m1+m2) A^{m2,m1}.  The oracle integrates every block on its own, so the
+    relations test its time bases and kernels, and they are what a copying assembly relies on."""
+    xyz, tri = icosphere(0)
+    N, p1 = 8, p + 1
+    grid = equidistant_grid(N, 4.0)
+    A = oracle_mod.assemble_dense(xyz, tri, grid, tables=oracle_mod.fast_tables(xyz, grid, p=p), p=p)
+    sc = np.abs(A).max()
+    blk = lambda k, i: A[k * p1:(k + 1) * p1, i * p1:(i + 1) * p1]
+    pairs = [((k, i), (k - i + 1, 1)) for k in range(2, N - 1) for i in range(2, k + 1)]
+    pairs += [((k, k + 1), (1, 2)) for k in range(2, N - 2)]
+    assert len(pairs) == 19
+    for (k, i), (a, b) in pairs:
+        assert np.abs(blk(k, i)).max() > 1e-6 * sc or np.abs(blk(a, b)).max() == 0.0
+        assert np.abs(blk(k, i) - blk(a, b)).max() <= 1e-12 * sc, (k, i)
+    assert min(np.abs(blk(k, 0) - blk(k + 1, 1)).max() for k in range(0, 4)) > 1e-2 * sc
+    assert max(np.abs(blk(N - 1, i) - blk(N - 2, i - 1)).max() for i in range(2, N)) > 1e-2 * sc
+    assert np.abs(blk(1, 2) - blk(0, 1)).max() > 1e-2 * sc
+    if p == 1:
+        for k in range(1, N - 1):
+            for i in range(1, N - 1):
+                for m1 in range(2):
+                    for m2 in range(2):
+                        d = A[2 * k + m1, 2 * i + m2] - (-1) ** (m1 + m2) * A[2 * k + m2, 2 * i + m1]
+                        assert np.abs(d).max() <= 1e-12 * sc, (k, i, m1, m2)
+
+
+def test_quad_count_over_node_blocks(oracle_mod):
+    """The count restricted to a set of node blocks and to its complement adds up to the full
+    count, and the all-true set gives the full count."""
+    xyz, tri = icosphere(0)
+    grid = equidistant_grid(7, 3.0)
+    full = oracle_mod.count_quad_evals(xyz, tri, grid, p=1)
+    rng = np.random.default_rng(5)
+    m = rng.random((7, 7)) < 0.5
+    a = oracle_mod.count_quad_evals(xyz, tri, grid, p=1, node_blocks=m)
+    b = oracle_mod.count_quad_evals(xyz, tri, grid, p=1, node_blocks=~m)
+    assert a > 0 and b > 0 and a + b == full
+    assert oracle_mod.count_quad_evals(xyz, tri, grid, p=1, node_blocks=np.ones((7, 7), bool)) == full
+
+
 # --- solver (Section 4, Algorithm 1) ---------------------------------------------------------
 def test_fgmres_and_alg1_against_lu(oracle_mod, small_blocks):
     """P15: FGMRES with and without the recursive block-Hessenberg preconditioner reaches the
