@@ -172,12 +172,16 @@ tdbem_status tdbem_assemble_set_tiles(tdbem_ctx *ctx, int32_t v, int32_t *nvaria
  * tdbem_matvec_free.  TDBEM_EINVAL unless enable is 0 or 1. */
 tdbem_status tdbem_set_block_reuse(tdbem_ctx *ctx, int32_t enable);
 
-/* Assemble the problems of n distinct contexts (meshes and grids of any sizes, all on one device)
- * concurrently: one host thread per context runs tdbem_assemble on that context's stream, so the
- * kernels of the problems overlap on the device (give every context its own stream for that).
- * reps: NULL or an array of n reports.  Returns the first non-OK status in context order (its
- * message is in that context); TDBEM_EINVAL for a NULL context, n outside 1..256 or a context
- * listed twice. */
+/* Assemble the problems of n distinct contexts (meshes, grids and orders of any sizes, all on one
+ * device) together, batching many small problems (Section 3 for each).  One host thread per
+ * context builds its tables and layout on its own stream; then the regular pairs of all problems
+ * run in ONE launch on the first context's stream (the tiles of the larger problems first, 4 x 8
+ * tiles), and each context finishes (singular pairs, equal-block copies, counts) on its stream.
+ * Every context then holds the same matrix as after tdbem_assemble; each report's ms_regular
+ * spans from the end of that context's layout to the end of the shared launch.  reps: NULL or an array of n reports.  Returns the first
+ * non-OK status in context order (its message is in that context); TDBEM_EINVAL for a NULL
+ * context, n outside 1..256, a context listed twice, contexts on different devices or a mesh of
+ * 2^24 triangles or more. */
 tdbem_status tdbem_assemble_group(tdbem_ctx *const *ctxs, int32_t n, tdbem_precision prec,
                                   tdbem_assembly_report *reps);
 

@@ -159,8 +159,8 @@ def load_library(path=LIB_PATH):
 
 
 def assemble_group(contexts, precision=FP64):
-    """Assemble the problems of several contexts concurrently (one host thread per context, each
-    on its context's stream); returns the list of assembly reports."""
+    """Assemble the problems of several contexts together (their regular pairs in one launch);
+    returns the list of assembly reports."""
     lib = load_library()
     n = len(contexts)
     hs = (ctypes.c_void_p * n)(*[c.h for c in contexts])

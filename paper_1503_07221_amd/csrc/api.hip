@@ -769,50 +769,68 @@ static tdbem_status tune_tiles(tdbem_ctx* c, double* v64, float* v32)
     return TDBEM_OK;
 }
 
-tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_report* rep)
+// One assembly in parts, so that a group of problems can share the regular-pair launch:
+// asm_begin (geometry, tables, layout, shape timing), the regular-pair launch on the context's
+// stream followed by ev[3], asm_tail (singular pairs, copies of equal blocks) and asm_end (wait,
+// counts, report).
+// (The singular pairs beside the regular ones on a second stream gained nothing: the regular
+// kernel's two waves per SIMD hold all of its VGPRs, so the singular waves only ran in its gaps
+// and lengthened it by their own time.)
+struct AsmRun {
+    hipEvent_t ev[6] = {};
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    AsmRun() = default;
+    AsmRun(const AsmRun&) = delete;
+    AsmRun& operator=(const AsmRun&) = delete;
+    ~AsmRun()
+    {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+static tdbem_status asm_begin(tdbem_ctx* c, tdbem_precision prec, AsmRun& R, bool tune)
 {
-    if (!c) return TDBEM_EINVAL;
     c->err.clear();
     if (!c->have_mesh || !c->have_grid) FAIL(c, TDBEM_ESTATE, "set the mesh and the time grid before assembling");
     if (prec != TDBEM_FP64 && prec != TDBEM_MIXED) FAIL(c, TDBEM_EINVAL, "unknown precision %d", (int)prec);
     TRY(set_device(c));
     c->assembled = false;
     c->prec = (int)prec;
-    hipEvent_t ev[6];
-    for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
-    struct EvGuard {
-        hipEvent_t* e;
-        ~EvGuard() { for (int s = 0; s < 6; ++s) (void)hipEventDestroy(e[s]); }
-    } guard{ev};
-    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    for (auto& e : R.ev) HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventRecord(R.ev[0], c->stream));
     TRY(run_geometry(c));
     TRY(build_tables(c));
-    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    HIPCHK(c, hipEventRecord(R.ev[1], c->stream));
     TRY(build_layout(c, (int)prec));
     ALLOC(c, c->d_counter, sizeof(unsigned long long) * 2);
     HIPCHK(c, hipMemsetAsync(c->d_counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
-    double* v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
-    float* v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
-    unsigned long long* cnt = c->d_counter.as<unsigned long long>();
-    TRY(tune_tiles(c, v64, v32));
-    HIPCHK(c, hipEventRecord(ev[2], c->stream));
-    // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
-    // storage
-    launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), v64, v32, nullptr, nullptr,
-                   c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v, cnt, c->stream);
-    HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    R.v64 = prec == TDBEM_FP64 ? c->d_val.as<double>() : nullptr;
+    R.v32 = prec == TDBEM_FP64 ? nullptr : c->d_val.as<float>();
+    if (tune) TRY(tune_tiles(c, R.v64, R.v32));
+    HIPCHK(c, hipEventRecord(R.ev[2], c->stream));
+    return TDBEM_OK;
+}
+
+static tdbem_status asm_tail(tdbem_ctx* c, AsmRun& R)
+{
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
     launch_singular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
-                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, v64, v32,
-                    nullptr, nullptr, cnt + 1, c->stream);
+                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, R.v64, R.v32,
+                    nullptr, nullptr, c->d_counter.as<unsigned long long>() + 1, c->stream);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    HIPCHK(c, hipEventRecord(R.ev[4], c->stream));
     if (c->blocks_reused > 0) {
-        launch_block_copy(c->band(), v64, v32, c->stream);
+        launch_block_copy(c->band(), R.v64, R.v32, c->stream);
         HIPCHK(c, hipGetLastError());
     }
-    HIPCHK(c, hipEventRecord(ev[5], c->stream));
+    HIPCHK(c, hipEventRecord(R.ev[5], c->stream));
+    return TDBEM_OK;
+}
+
+static tdbem_status asm_end(tdbem_ctx* c, AsmRun& R, tdbem_assembly_report* rep)
+{
     HIPCHK(c, hipStreamSynchronize(c->stream));
     unsigned long long counts[2];
     HIPCHK(c, hipMemcpy(counts, c->d_counter.p, sizeof(counts), hipMemcpyDeviceToHost));
@@ -820,8 +838,10 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
     ++c->assemblies;
     c->mm_variant = -1;
     if (rep) {
-        float ms[5];
+        hipEvent_t* ev = R.ev;
+        float ms[5], tot;
         for (int s = 0; s < 5; ++s) HIPCHK(c, hipEventElapsedTime(&ms[s], ev[s], ev[s + 1]));
+        HIPCHK(c, hipEventElapsedTime(&tot, ev[0], ev[5]));
         rep->quad_evals = (int64_t)(counts[0] + counts[1]);
         rep->quad_evals_regular = (int64_t)counts[0];
         const int64_t E = c->E;
@@ -837,9 +857,25 @@ tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_r
         rep->ms_singular = ms[3];
         rep->ms_reuse = ms[4];
         rep->blocks_reused = c->blocks_reused;
-        rep->ms_total = ms[0] + ms[1] + ms[2] + ms[3] + ms[4];
+        rep->ms_total = tot;
     }
     return TDBEM_OK;
+}
+
+tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_report* rep)
+{
+    if (!c) return TDBEM_EINVAL;
+    AsmRun R;
+    TRY(asm_begin(c, prec, R, true));
+    // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
+    // storage
+    launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), R.v64, R.v32, nullptr, nullptr,
+                   c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v,
+                   c->d_counter.as<unsigned long long>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipEventRecord(R.ev[3], c->stream));
+    TRY(asm_tail(c, R));
+    return asm_end(c, R, rep);
 }
 
 tdbem_status tdbem_assemble_group(tdbem_ctx* const* ctxs, int32_t n, tdbem_precision prec,
@@ -850,18 +886,101 @@ tdbem_status tdbem_assemble_group(tdbem_ctx* const* ctxs, int32_t n, tdbem_preci
         if (!ctxs[a]) return TDBEM_EINVAL;
         for (int b = 0; b < a; ++b)
             if (ctxs[a] == ctxs[b]) FAIL(ctxs[a], TDBEM_EINVAL, "a context appears twice in the group");
+        if (ctxs[a]->device != ctxs[0]->device)
+            FAIL(ctxs[a], TDBEM_EINVAL, "the contexts of a group must share one device");
+        if (ctxs[a]->have_mesh && ctxs[a]->E >= (1 << 24))
+            FAIL(ctxs[a], TDBEM_EINVAL, "a group problem may have at most 2^24 - 1 triangles");
     }
-    // one host thread per context: each runs the whole assembly on its context's stream, so the
-    // kernels of small problems run side by side and fill the device together
+    // every problem's tables and layout on its own stream (one host thread each, so the host work
+    // overlaps and the small launches share the device) ...
+    std::vector<AsmRun> runs(n);
     std::vector<tdbem_status> st(n, TDBEM_OK);
-    std::vector<std::thread> th;
-    th.reserve(n);
+    {
+        std::vector<std::thread> th;
+        th.reserve(n);
+        for (int a = 0; a < n; ++a) th.emplace_back([&, a]() { st[a] = asm_begin(ctxs[a], prec, runs[a], false); });
+        for (auto& t : th) t.join();
+    }
     for (int a = 0; a < n; ++a)
-        th.emplace_back([&, a]() { st[a] = tdbem_assemble(ctxs[a], prec, reps ? reps + a : nullptr); });
-    for (auto& t : th) t.join();
-    for (int a = 0; a < n; ++a)
-        if (st[a] != TDBEM_OK) return st[a];
-    return TDBEM_OK;
+        if (st[a] != TDBEM_OK) {
+            for (int b = 0; b < n; ++b) (void)hipStreamSynchronize(ctxs[b]->stream);
+            return st[a];
+        }
+    // ... then the regular pairs of all of them in one launch on the first context's stream (each
+    // tile tagged with its problem), and each problem's singular pairs and copies on its own stream
+    // after it
+    tdbem_ctx* c0 = ctxs[0];
+    std::vector<int> order(n);
+    for (int a = 0; a < n; ++a) order[a] = a;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ctxs[x]->E > ctxs[y]->E; });
+    std::vector<RegularProblem> probs(n);
+    std::vector<std::vector<int32_t>> tq(n);
+    for (int q = 0; q < n; ++q) {
+        tdbem_ctx* c = ctxs[order[q]];
+        probs[q] = RegularProblem{c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), runs[order[q]].v64,
+                                  runs[order[q]].v32, c->d_counter.as<unsigned long long>()};
+        tq[q] = regular_tiles(c->E, 0);
+        HIPCHK(c0, hipStreamWaitEvent(c0->stream, runs[order[q]].ev[2], 0));
+    }
+    // the kernel gives XCD x the x-th eighth of the list: every eighth gets the same share of every
+    // problem, larger problems first (tiles of different problems cost differently), padded to
+    // equal length with tiles past the end of problem 0, which leave at once
+    int64_t per = 0;
+    for (int x = 0; x < 8; ++x) {
+        int64_t cx = 0;
+        for (int q = 0; q < n; ++q) {
+            const int64_t nq = (int64_t)tq[q].size() / 2;
+            cx += nq * (x + 1) / 8 - nq * x / 8;
+        }
+        per = std::max(per, cx);
+    }
+    std::vector<int32_t> tiles;
+    tiles.reserve((size_t)(16 * per));
+    for (int x = 0; x < 8; ++x) {
+        for (int q = 0; q < n; ++q) {
+            const int64_t nq = (int64_t)tq[q].size() / 2, u0 = nq * x / 8, u1 = nq * (x + 1) / 8;
+            for (int64_t u = u0; u < u1; ++u) {
+                tiles.push_back((int32_t)((uint32_t)tq[q][2 * u] | ((uint32_t)q << 24)));
+                tiles.push_back(tq[q][2 * u + 1]);
+            }
+        }
+        while ((int64_t)tiles.size() < 2 * per * (x + 1)) {
+            tiles.push_back(0xFFFFFF);
+            tiles.push_back(0);
+        }
+    }
+    DBuf d_probs, d_tiles;
+    TRY(set_device(c0));
+    if (per > 0) {
+        TRY(upload(c0, d_probs, probs.data(), probs.size()));
+        TRY(upload(c0, d_tiles, tiles.data(), tiles.size()));
+        launch_regular_multi(d_probs.as<RegularProblem>(), d_tiles.as<int2>(), (int64_t)tiles.size() / 2,
+                             c0->stream);
+        HIPCHK(c0, hipGetLastError());
+    }
+    hipEvent_t done;
+    HIPCHK(c0, hipEventCreate(&done));
+    struct Guard {
+        hipEvent_t e;
+        ~Guard() { (void)hipEventDestroy(e); }
+    } guard{done};
+    HIPCHK(c0, hipEventRecord(done, c0->stream));
+    tdbem_status first = TDBEM_OK;
+    for (int a = 0; a < n; ++a) {
+        tdbem_ctx* c = ctxs[a];
+        TRY(set_device(c));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, done, 0));
+        HIPCHK(c, hipEventRecord(runs[a].ev[3], c->stream));
+        const tdbem_status r = asm_tail(c, runs[a]);
+        if (first == TDBEM_OK) first = r;
+    }
+    for (int a = 0; a < n; ++a) {
+        const tdbem_status r = asm_end(ctxs[a], runs[a], reps ? reps + a : nullptr);
+        if (first == TDBEM_OK) first = r;
+    }
+    // the device buffers of the launch are released only when every stream has passed it
+    HIPCHK(c0, hipEventSynchronize(done));
+    return first;
 }
 
 tdbem_status tdbem_matvec_free(tdbem_ctx* c, const double* x, double* y, tdbem_assembly_report* rep)

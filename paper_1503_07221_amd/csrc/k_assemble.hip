@@ -392,10 +392,13 @@ __device__ inline void stage_store(const TileRec& R, double2* stage, const doubl
     }
 }
 
-template <class Tile>
+// Multi: the tiles of several problems in one launch; the top 8 bits of a tile's test index name
+// its problem, whose views replace the launch's own.
+template <class Tile, bool Multi>
 __global__ void __launch_bounds__(Tile::kThreads, 2)
-k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView band, double* val, float* valf,
-               ProductView pv, const int2* __restrict__ tiles, int64_t ntiles, unsigned long long* counter)
+k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandView band_, double* val_,
+               float* valf_, ProductView pv, const int2* __restrict__ tiles, int64_t ntiles,
+               unsigned long long* counter_, const RegularProblem* __restrict__ probs)
 {
     constexpr int kTileT = Tile::kT, kTileS = Tile::kS, kTilePairs = Tile::kPairs, kTileEl = Tile::kEl, kTileSort = Tile::kSort;
     constexpr int kTileThreads = Tile::kThreads, kTileVt = Tile::kVt, kTileVs = Tile::kVs, kChunkMax = Tile::kChunkMax;
@@ -405,14 +408,34 @@ k_regular_tile(GeomView g, TableView tv, const double* __restrict__ t, BandView 
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tix = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tix >= ntiles) return;
-    const int2 tl = tiles[tix];
+    int2 tl = tiles[tix];
+    GeomView g = g_;
+    TableView tv = tv_;
+    const double* __restrict__ t = t_;
+    BandView band = band_;
+    double* val = val_;
+    float* valf = valf_;
+    unsigned long long* counter = counter_;
+    const PieceTable* ptab = &tv_.pt;
+    if constexpr (Multi) {
+        const RegularProblem& P = probs[(uint32_t)tl.x >> 24];
+        ptab = &P.tv.pt;
+        g = P.g;
+        tv = P.tv;
+        t = P.t;
+        band = P.band;
+        val = P.val;
+        valf = P.valf;
+        counter = P.counter;
+        tl.x &= 0xFFFFFF;
+    }
     const int E = g.E;
     const int tau0 = tl.x * kTileT, sig0 = tl.y * kTileS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     __shared__ PieceTable spt;
     __shared__ TileLds<Tile> L;
-    load_piece_table(spt, tv.pt);
+    load_piece_table(spt, *ptab);
     if (tid == 0) {
         int n = 0;
         for (int a = 0; a < kTileT && tau0 + a < E; ++a)
@@ -1151,11 +1174,20 @@ void launch_regular(GeomView g, TableView tv, const double* t, BandView band, do
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
     const ProductView pv{px, py, band.M};
     if (variant == 1)
-        hipLaunchKernelGGL(k_regular_tile<TileB>, grid, dim3(TileB::kThreads), 0, s, g, tv, t, band, val, valf, pv,
-                           tiles, ntiles, counter);
+        hipLaunchKernelGGL((k_regular_tile<TileB, false>), grid, dim3(TileB::kThreads), 0, s, g, tv, t, band, val,
+                           valf, pv, tiles, ntiles, counter, nullptr);
     else
-        hipLaunchKernelGGL(k_regular_tile<TileA>, grid, dim3(TileA::kThreads), 0, s, g, tv, t, band, val, valf, pv,
-                           tiles, ntiles, counter);
+        hipLaunchKernelGGL((k_regular_tile<TileA, false>), grid, dim3(TileA::kThreads), 0, s, g, tv, t, band, val,
+                           valf, pv, tiles, ntiles, counter, nullptr);
+}
+
+void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_t ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
+    const ProductView pv{nullptr, nullptr, 0};
+    hipLaunchKernelGGL((k_regular_tile<TileA, true>), grid, dim3(TileA::kThreads), 0, s, GeomView{}, TableView{},
+                       nullptr, BandView{}, nullptr, nullptr, pv, tiles, ntiles, nullptr, probs);
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau, in

@@ -344,6 +344,18 @@ void launch_regular(GeomView g, TableView tv, const double* t, BandView band, do
                     const double* px, double* py, const int2* tiles, int64_t ntiles, int variant,
                     unsigned long long* counter, hipStream_t s);
 std::vector<int32_t> regular_tiles(int E, int variant);
+// One launch over the tiles of several problems (shape 0): tile (a, b) of problem q is stored as
+// (a | q << 24, b); probs[q] holds that problem's views.
+struct RegularProblem {
+    GeomView g;
+    TableView tv;
+    const double* t;
+    BandView band;
+    double* val;
+    float* valf;
+    unsigned long long* counter;
+};
+void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_t ntiles, hipStream_t s);
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      int max_points, double* val, float* valf, const double* px, double* py,

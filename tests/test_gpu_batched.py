@@ -4,13 +4,14 @@ The product against the oracle's dense system (1e-13) with a right-hand-side cou
 multiple of the kernel's group of 4, and at full size against the single-vector product in FP64
 and FP32 storage (same values, other summation order: 1e-13).  The batched solve against separate
 solves of every right-hand side (the Krylov processes are the same up to rounding), to the
-1e-8 true residual, with and without the learned preconditioner.
+1e-8 true residual, with and without the learned preconditioner.  The group assembly (one
+regular-pair launch over several problems) against the oracle and against separate assemblies.
 """
 import numpy as np
 import pytest
 
-from tests.conftest import gpu_available
-from workloads import get_config, graded_grid, icosphere
+from tests.conftest import gpu_available, integrated_node_blocks
+from workloads import equidistant_grid, get_config, graded_grid, icosphere, torus
 from workloads.configs import pulse_direction
 
 pytestmark = pytest.mark.gpu
@@ -133,4 +134,41 @@ def test_assemble_group_uneven_meshes(tb):
     with pytest.raises(tb.TdbemError):
         tb.assemble_group([ctxs[0], ctxs[0]])
     for c in ctxs + [ref]:
+        c.close()
+
+
+def test_assemble_group_against_oracle(tb, oracle_mod):
+    """Four small problems in one regular-pair launch: an equidistant sphere (whose equal blocks are
+    copied), a graded sphere with p = 1 and two tori of different sizes and grids; every block of
+    every problem against the oracle (1e-11 of the block maximum) and the exact quadrature-point
+    counts, in FP64 and in FP32 storage (2e-6)."""
+    probs = [(icosphere(0), equidistant_grid(7, 3.0), 0), (icosphere(0), graded_grid(5, 3.0, seed=31), 1),
+             (torus(4, 3), graded_grid(5, 2.5, seed=22), 0), (torus(7, 5), graded_grid(6, 3.0, seed=23), 0)]
+    ctxs, refs = [], []
+    for (xyz, tri), grid, p in probs:
+        c = tb.Context(0, own_stream=True)
+        c.set_mesh(xyz, tri)
+        c.set_time_grid(grid, "bump", p=p)
+        ctxs.append(c)
+        # definition mode on the 20- and 24-triangle meshes (the fast mode's tables are ~2e-11 off
+        # for the p = 1 kernels of the last node there), fast mode on the 70-triangle torus
+        T = oracle_mod.fast_tables(xyz, grid, "bump", p=p) if len(tri) > 24 else None
+        refs.append((oracle_mod.assemble_dense(xyz, tri, grid, tables=T, p=p),
+                     oracle_mod.count_quad_evals(xyz, tri, grid, p=p, node_blocks=integrated_node_blocks(grid))))
+    for prec, tol in ((tb.FP64, 1e-11), (tb.MIXED, 2e-6)):
+        reps = tb.assemble_group(ctxs, prec)
+        for c, rep, ((xyz, tri), grid, p), (A, count) in zip(ctxs, reps, probs, refs):
+            L, M = A.shape[0], A.shape[2]
+            K, I, J, Lq = np.meshgrid(np.arange(L), np.arange(L), np.arange(M), np.arange(M), indexing="ij")
+            G = c.get_entries(K.ravel(), I.ravel(), J.ravel(), Lq.ravel()).reshape(A.shape)
+            for k in range(L):
+                for i in range(L):
+                    sc = np.abs(A[k, i]).max()
+                    if sc == 0.0:
+                        assert np.all(G[k, i] == 0.0), (k, i)
+                    else:
+                        assert np.abs(G[k, i] - A[k, i]).max() <= tol * sc, (k, i, p)
+            assert rep["quad_evals"] == count
+        assert reps[0]["blocks_reused"] > 0 and reps[1]["blocks_reused"] == 0
+    for c in ctxs:
         c.close()
