@@ -244,15 +244,17 @@ __device__ inline double recip(double r)
 //            boundary, into segments of at most kStage pieces.  The records go to LDS.
 //   stage    the pieces of a record (coefficients and piece records), the interval starts and
 //            the support are copied to LDS; the copy for the next record is loaded into
-//            registers while the current one is evaluated, so the inner loop reads LDS only.
+//            registers while the current one is evaluated and contracted, so the inner loop
+//            reads LDS only.
 //   phase 1  the lanes split the record's range into contiguous chunks; a lane keeps the
 //            coefficients of its current piece in registers and moves to the next piece when r
 //            passes its end (sorted neighbours share pieces); psi w/r and tpsi w/r of every
 //            point pair go to V (one plain store per point pair, each written by one lane).
 //   phase 2  after the last segment of a round, the 8 lanes of a triangle pair contract V:
-//            lane q sums over q' with lam_b(q') (R_b(q)), the group sums lam_a(q) R_b(q) with
-//            DPP moves, and the 3 x 3 block is merged in an LDS tile over the two vertex sets
-//            before one atomic add per (vertex, vertex) entry goes to the band storage.
+//            lane q sums its row over q' with lam_b(q') into R_b(q) (kept in the row's first
+//            two slots), lane (a, b) then sums lam_a(q) R_b(q) over the 7 rows, and the 3 x 3
+//            block is merged in an LDS tile over the two vertex sets before one atomic add per
+//            (vertex, vertex) entry goes to the band storage.
 // Two barriers per record.
 // ---------------------------------------------------------------------------------------------
 constexpr int kStage = 64;                           // pieces of one record held in LDS
@@ -803,7 +805,6 @@ k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandVi
                     nq += (unsigned long long)cnt;
                 }
                 __syncthreads();
-                if (more) stage_store<Tile>(L.rec[n + 1], L.stage, st);
                 if (last) {
                     // phase 2: lane (pair gp, row q = gm < 7) sums its row over q' into
                     // (R_0, R_1, R_2, T)(q), kept in the row's first two slots; lane gm then forms
@@ -853,6 +854,9 @@ k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandVi
                         if (gm == 0) atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * T));
                     }
                 }
+                // the next record's pieces go to LDS only now (phase 2 does not read them), so their
+                // global loads have had phase 1 and phase 2 to arrive
+                if (more) stage_store<Tile>(L.rec[n + 1], L.stage, st);
                 __syncthreads();
                 if (last) {
 #pragma unroll
