@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--lp-max-it", type=int, default=2000, help="iteration limit of the learned solve")
     ap.add_argument("--no-potential", action="store_true", help="skip the field evaluation leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-meshes group assembly leg")
+    ap.add_argument("--no-deterministic", action="store_true", help="skip the deterministic-mode leg")
     ap.add_argument("--no-equal-blocks", action="store_true",
                     help="skip the equidistant-grid leg (equal blocks copied against integrated)")
     ap.add_argument("--batch-rhs", type=int, default=32,
@@ -265,6 +266,25 @@ def equal_blocks_leg(tb, cfg):
                        "quad_evals": int(r1["quad_evals"]), "blocks_copied": int(r1["blocks_reused"])},
             "speedup": r0["ms_total"] / r1["ms_total"],
             "sampled_max_rel_diff": float(np.abs(e1 - e0).max() / max(np.abs(e0).max(), 1e-300))}
+
+
+def deterministic_leg(tb, cfg, ref_entries, sample):
+    """The deterministic mode on the workload: two FP64 assemblies (each a scale pass and a
+    fixed-point pass), their time, whether the sampled entries are bitwise equal, and their largest
+    difference from the ordinary assembly relative to the largest sampled entry."""
+    import numpy as np
+    c = tb.Context(0, deterministic=True)
+    c.set_mesh(*cfg["mesh"])
+    c.set_time_grid(cfg["grid"], cfg["cutoff"])
+    reps, ents = [], []
+    for _ in range(2):
+        reps.append(c.assemble(tb.FP64))
+        ents.append(c.get_entries(*sample))
+    c.close()
+    print(f"# deterministic: assembly {reps[-1]['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    return {"ms": reps[-1]["ms_total"], "quad_evals": int(reps[-1]["quad_evals"]),
+            "bitwise_equal_runs": bool(np.array_equal(ents[0].view(np.int64), ents[1].view(np.int64))),
+            "max_rel_diff_vs_ordinary": float(np.abs(ents[1] - ref_entries).max() / np.abs(ref_entries).max())}
 
 
 def potential_leg(ctx, tb, alpha, cfg):
@@ -722,6 +742,10 @@ def main():
         out["uneven"] = uneven_leg(tb)
     if not args.no_equal_blocks and budget.allows("equal_blocks", 25):
         out["equal_blocks"] = equal_blocks_leg(tb, cfg)
+    if not args.no_deterministic and budget.allows("deterministic", 20):
+        ctx.assemble(tb.FP64)
+        sample = sample_entries(ctx, cfg, 200000, 9)
+        out["deterministic"] = deterministic_leg(tb, cfg, ctx.get_entries(*sample), sample)
     ctx.close()
     emit()
 

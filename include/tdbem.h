@@ -60,6 +60,19 @@ typedef struct {
     void *stream;                /* hipStream_t to run on; NULL: the library creates one */
     int32_t ss_order;            /* Gauss points per direction of the Sauter-Schwab rules, 1..5
                                     (<= 0: 4); larger values give TDBEM_EINVAL */
+    int32_t deterministic;       /* 1: every assembly gives bitwise the same matrix on every run
+                                    (TDBEM_FP64 only).  The contributions are added as 64-bit
+                                    fixed-point integers, whose sums do not depend on the order of
+                                    the atomic additions; the scale, a power of two that keeps every
+                                    entry below 2^61, comes from a first ordinary pass, so the
+                                    assembly takes about twice as long.  Entries differ from the
+                                    ordinary assembly by ~1e-16 of the largest.  0: ordinary FP64
+                                    atomics (order-dependent in the last bits).  Others: EINVAL */
+    int32_t quad_regular;        /* points of the rule on each triangle of a regular pair: 7 (the
+                                    degree-5 rule) or 0 for it; other values TDBEM_EINVAL */
+    double psi_tol;              /* accuracy asked of the psi tables relative to each kernel's
+                                    maximum: 0 (the built-in tables, ~2e-12) or >= 2e-12; a smaller
+                                    value cannot be met and gives TDBEM_EINVAL */
 } tdbem_options;
 
 typedef struct {

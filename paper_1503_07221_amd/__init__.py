@@ -47,7 +47,8 @@ class TdbemError(RuntimeError):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("ss_order", ctypes.c_int32)]
+    _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("ss_order", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("quad_regular", ctypes.c_int32), ("psi_tol", ctypes.c_double)]
 
 
 class AssemblyReport(ctypes.Structure):
@@ -183,9 +184,10 @@ def _iptr(a):
 class Context:
     """One library context on a HIP device, running on torch's current stream of that device."""
 
-    def __init__(self, device=0, ss_order=4, own_stream=False):
+    def __init__(self, device=0, ss_order=4, own_stream=False, deterministic=False):
         """own_stream: run on a new stream of default priority (contexts assembled together with
-        assemble_group overlap only on distinct streams) instead of torch's current stream."""
+        assemble_group overlap only on distinct streams) instead of torch's current stream.
+        deterministic: assemblies give bitwise the same matrix on every run (FP64 only)."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -193,7 +195,7 @@ class Context:
             raise RuntimeError("tdbem needs a HIP device (torch.cuda.is_available() is False)")
         self.device = torch.device("cuda", device)
         self.stream = torch.cuda.Stream(self.device) if own_stream else torch.cuda.current_stream(self.device)
-        opt = _Options(device, ctypes.c_void_p(self.stream.cuda_stream), ss_order)
+        opt = _Options(device, ctypes.c_void_p(self.stream.cuda_stream), ss_order, 1 if deterministic else 0, 7, 0.0)
         h = ctypes.c_void_p()
         st = self.lib.tdbem_create(ctypes.byref(h), ctypes.byref(opt))
         if st != 0:

@@ -148,6 +148,9 @@ void ss_point(int kind, int reg, double xi, double e1, double e2, double e3, dou
 
 // every kTileSampleStride-th tile of the regular-pair kernel is timed to pick its tile shape
 static constexpr int64_t kTileSampleStride = 32;
+// The tables reach ~2e-12 of each kernel's maximum for psi (1e-13 for tilde psi); a tolerance
+// below this cannot be met.
+static constexpr double kPsiTolFloor = 2e-12;
 
 struct tdbem_ctx {
     int device = 0;
@@ -155,6 +158,7 @@ struct tdbem_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int ss_order = 4;
+    bool deterministic = false;   // fixed-point assembly: bitwise the same matrix on every run
     std::string err;
 
     int M = 0, E = 0, N = 0, cut = 0;   // N: temporal bases L = nodes (p + 1)
@@ -354,6 +358,10 @@ tdbem_status tdbem_create(tdbem_ctx** out, const tdbem_options* opt)
     c->device = opt ? opt->device : 0;
     c->ss_order = opt && opt->ss_order > 0 ? opt->ss_order : 4;
     if (c->ss_order > 5) { delete c; return TDBEM_EINVAL; }   // <= 6 * 5^4 points per pair (sorted in LDS)
+    if (opt && (opt->deterministic < 0 || opt->deterministic > 1)) { delete c; return TDBEM_EINVAL; }
+    if (opt && opt->quad_regular != 0 && opt->quad_regular != 7) { delete c; return TDBEM_EINVAL; }
+    if (opt && (opt->psi_tol < 0.0 || (opt->psi_tol > 0.0 && opt->psi_tol < kPsiTolFloor))) { delete c; return TDBEM_EINVAL; }
+    c->deterministic = opt && opt->deterministic == 1;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
         (void)hipGetLastError();
@@ -813,13 +821,45 @@ static tdbem_status asm_begin(tdbem_ctx* c, tdbem_precision prec, AsmRun& R, boo
     return TDBEM_OK;
 }
 
-static tdbem_status asm_tail(tdbem_ctx* c, AsmRun& R)
+// Deterministic mode, first pass: the ordinary assembly gives the largest entry, from which the
+// fixed-point scale 2^e (every final sum below 2^61) follows; the storage and the counters are
+// then cleared for the fixed-point pass.
+static tdbem_status fixed_scale(tdbem_ctx* c, AsmRun& R, double* fxs, int* fxe)
+{
+    launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), R.v64, nullptr, nullptr, nullptr,
+                   c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v,
+                   c->d_counter.as<unsigned long long>(), c->stream);
+    const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
+    launch_singular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
+                    c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, R.v64, nullptr,
+                    nullptr, nullptr, c->d_counter.as<unsigned long long>() + 1, c->stream);
+    HIPCHK(c, hipGetLastError());
+    DBuf d_max;
+    ALLOC(c, d_max, sizeof(double));
+    HIPCHK(c, hipMemsetAsync(d_max.p, 0, sizeof(double), c->stream));
+    launch_absmax(R.v64, c->nvals, d_max.as<double>(), c->stream);
+    HIPCHK(c, hipGetLastError());
+    double mx = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&mx, d_max.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *fxe = mx > 0.0 ? std::min(60 - std::ilogb(mx), 1000) : 0;
+    *fxs = std::ldexp(1.0, *fxe);
+    HIPCHK(c, hipMemsetAsync(c->d_val.p, 0, c->d_val.bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->d_counter.p, 0, sizeof(unsigned long long) * 2, c->stream));
+    return TDBEM_OK;
+}
+
+static tdbem_status asm_tail(tdbem_ctx* c, AsmRun& R, double fxs = 0.0, int fxe = 0)
 {
     const int n4 = c->ss_order * c->ss_order * c->ss_order * c->ss_order;
     launch_singular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), c->d_pairs.as<int32_t>(), c->npairs,
                     c->d_rules.as<double>(), c->d_roff.as<int32_t>(), c->d_rcnt.as<int32_t>(), 6 * n4, R.v64, R.v32,
-                    nullptr, nullptr, c->d_counter.as<unsigned long long>() + 1, c->stream);
+                    nullptr, nullptr, c->d_counter.as<unsigned long long>() + 1, c->stream, fxs);
     HIPCHK(c, hipGetLastError());
+    if (fxs > 0.0) {
+        launch_fixed_to_double(R.v64, c->nvals, fxe, c->stream);
+        HIPCHK(c, hipGetLastError());
+    }
     HIPCHK(c, hipEventRecord(R.ev[4], c->stream));
     if (c->blocks_reused > 0) {
         launch_block_copy(c->band(), R.v64, R.v32, c->stream);
@@ -865,16 +905,23 @@ static tdbem_status asm_end(tdbem_ctx* c, AsmRun& R, tdbem_assembly_report* rep)
 tdbem_status tdbem_assemble(tdbem_ctx* c, tdbem_precision prec, tdbem_assembly_report* rep)
 {
     if (!c) return TDBEM_EINVAL;
+    if (c->deterministic && prec != TDBEM_FP64) {
+        c->err.clear();
+        FAIL(c, TDBEM_EINVAL, "the deterministic assembly stores FP64 values (precision TDBEM_FP64)");
+    }
     AsmRun R;
     TRY(asm_begin(c, prec, R, true));
+    double fxs = 0.0;
+    int fxe = 0;
+    if (c->deterministic) TRY(fixed_scale(c, R, &fxs, &fxe));
     // both modes evaluate every quadrature point in FP64; the mixed mode rounds the sums into FP32
     // storage
     launch_regular(c->geom(), c->asm_tables(), c->d_t.as<double>(), c->band(), R.v64, R.v32, nullptr, nullptr,
                    c->d_tiles[c->tile_v].as<int2>(), c->ntiles[c->tile_v], c->tile_v,
-                   c->d_counter.as<unsigned long long>(), c->stream);
+                   c->d_counter.as<unsigned long long>(), c->stream, fxs);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipEventRecord(R.ev[3], c->stream));
-    TRY(asm_tail(c, R));
+    TRY(asm_tail(c, R, fxs, fxe));
     return asm_end(c, R, rep);
 }
 
@@ -890,6 +937,20 @@ tdbem_status tdbem_assemble_group(tdbem_ctx* const* ctxs, int32_t n, tdbem_preci
             FAIL(ctxs[a], TDBEM_EINVAL, "the contexts of a group must share one device");
         if (ctxs[a]->have_mesh && ctxs[a]->E >= (1 << 24))
             FAIL(ctxs[a], TDBEM_EINVAL, "a group problem may have at most 2^24 - 1 triangles");
+    }
+    bool any_det = false;
+    for (int a = 0; a < n; ++a) any_det = any_det || ctxs[a]->deterministic;
+    if (any_det) {
+        // the deterministic mode's two passes: each context on its own, side by side
+        std::vector<tdbem_status> st(n, TDBEM_OK);
+        std::vector<std::thread> th;
+        th.reserve(n);
+        for (int a = 0; a < n; ++a)
+            th.emplace_back([&, a]() { st[a] = tdbem_assemble(ctxs[a], prec, reps ? reps + a : nullptr); });
+        for (auto& t : th) t.join();
+        for (int a = 0; a < n; ++a)
+            if (st[a] != TDBEM_OK) return st[a];
+        return TDBEM_OK;
     }
     // every problem's tables and layout on its own stream (one host thread each, so the host work
     // overlaps and the small launches share the device) ...

@@ -148,10 +148,19 @@ __device__ inline double group8_sum(double v)
     return v;
 }
 
+// Deterministic assembly: a contribution v enters the storage as the 64-bit integer
+// round(v * fxs) (fxs a power of two), added with integer atomics, whose sum does not depend on
+// the order of the additions (two's complement addition is exact modulo 2^64; the final sums fit).
+__device__ inline unsigned long long to_fixed(double v, double fxs)
+{
+    return (unsigned long long)__double2ll_rn(v * fxs);
+}
+
 // P(l, j) += v for the half P of the assembly (A = P + P^T): in the lower-triangle storage an
-// off-diagonal contribution lands at (max, min) and a diagonal one counts twice.
+// off-diagonal contribution lands at (max, min) and a diagonal one counts twice.  fxs > 0: val
+// holds the fixed-point integers of the deterministic mode.
 __device__ inline void scatter_half(const BandView& band, double* val, float* valf, int k, int i, int l, int j,
-                                    double v)
+                                    double v, double fxs)
 {
     if (j > l) { const int tmp = j; j = l; l = tmp; }
     if (j == l) v *= 2.0;
@@ -159,7 +168,8 @@ __device__ inline void scatter_half(const BandView& band, double* val, float* va
     const int B = band_width(band, k, l, j);
     if (s < 0 || s >= B) return;   // outside the band: the value is zero (support test)
     const int64_t idx = band_value_index(band, k, l, j, s, B);
-    if (valf) atomicAdd(valf + idx, (float)v);
+    if (fxs > 0.0) atomicAdd(reinterpret_cast<unsigned long long*>(val) + idx, to_fixed(v, fxs));
+    else if (valf) atomicAdd(valf + idx, (float)v);
     else atomicAdd(val + idx, v);
 }
 
@@ -172,13 +182,13 @@ struct ProductView {
 };
 
 __device__ inline void deposit(const BandView& band, double* val, float* valf, const ProductView& pv, int k, int i,
-                               int l, int j, double v)
+                               int l, int j, double v, double fxs = 0.0)
 {
     if (pv.y) {
         atomicAdd(pv.y + (int64_t)k * pv.M + l, v * pv.x[(int64_t)i * pv.M + j]);
         atomicAdd(pv.y + (int64_t)k * pv.M + j, v * pv.x[(int64_t)i * pv.M + l]);
     } else {
-        scatter_half(band, val, valf, k, i, l, j, v);
+        scatter_half(band, val, valf, k, i, l, j, v, fxs);
     }
 }
 
@@ -395,12 +405,13 @@ __device__ inline void stage_store(const TileRec& R, double2* stage, const doubl
 }
 
 // Multi: the tiles of several problems in one launch; the top 8 bits of a tile's test index name
-// its problem, whose views replace the launch's own.
-template <class Tile, bool Multi>
+// its problem, whose views replace the launch's own.  Fixed: the deterministic mode (the merged
+// vertex tile and the storage hold fixed-point integers of scale fxs, see to_fixed).
+template <class Tile, bool Multi, bool Fixed>
 __global__ void __launch_bounds__(Tile::kThreads, 2)
 k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandView band_, double* val_,
                float* valf_, ProductView pv, const int2* __restrict__ tiles, int64_t ntiles,
-               unsigned long long* counter_, const RegularProblem* __restrict__ probs)
+               unsigned long long* counter_, const RegularProblem* __restrict__ probs, double fxs)
 {
     constexpr int kTileT = Tile::kT, kTileS = Tile::kS, kTilePairs = Tile::kPairs, kTileEl = Tile::kEl, kTileSort = Tile::kSort;
     constexpr int kTileThreads = Tile::kThreads, kTileVt = Tile::kVt, kTileVs = Tile::kVs, kChunkMax = Tile::kChunkMax;
@@ -850,8 +861,16 @@ k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandVi
                             row[1] = make_double2(0.0, 0.0);
                         }
                         const double al = L.alpha[gp];
-                        atomicAdd(&L.acc[L.aoff[9 * gp + gm]], fma(al, S, L.beta[9 * gp + gm] * T));
-                        if (gm == 0) atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * T));
+                        if constexpr (Fixed) {
+                            unsigned long long* acq = reinterpret_cast<unsigned long long*>(L.acc);
+                            atomicAdd(acq + L.aoff[9 * gp + gm], to_fixed(fma(al, S, L.beta[9 * gp + gm] * T), fxs));
+                            if (gm == 0)
+                                atomicAdd(acq + L.aoff[9 * gp + 8], to_fixed(fma(al, S8, L.beta[9 * gp + 8] * T), fxs));
+                        } else {
+                            atomicAdd(&L.acc[L.aoff[9 * gp + gm]], fma(al, S, L.beta[9 * gp + gm] * T));
+                            if (gm == 0)
+                                atomicAdd(&L.acc[L.aoff[9 * gp + 8]], fma(al, S8, L.beta[9 * gp + 8] * T));
+                        }
                     }
                 }
                 // the next record's pieces go to LDS only now (phase 2 does not read them), so their
@@ -862,6 +881,24 @@ k_regular_tile(GeomView g_, TableView tv_, const double* __restrict__ t_, BandVi
 #pragma unroll
                     for (int h = 0; h < kDz; ++h) {
                         const int z = tid + h * kTileThreads;
+                        if constexpr (Fixed) {
+                            // integer sums of the tile go to the storage as they are
+                            unsigned long long* acq = reinterpret_cast<unsigned long long*>(L.acc);
+                            if (z < kTileVt * kTileVs && acq[z] != 0ull) {
+                                const unsigned long long q = acq[z];
+                                if (dz_B[h] > 0) {
+                                    const int s = i - dz_ilo[h];
+                                    if (s >= 0 && s < dz_B[h]) {
+                                        const int lr = dz_lj[h] & 255, jr = (dz_lj[h] >> 8) & 255;
+                                        const int64_t idx = dz_vo[h] + ((int64_t)lr * dz_B[h] + s) * kBT + jr;
+                                        atomicAdd(reinterpret_cast<unsigned long long*>(val) + idx,
+                                                  (dz_lj[h] >> 16) ? 2ull * q : q);
+                                    }
+                                }
+                                acq[z] = 0ull;
+                            }
+                            continue;
+                        }
                         if (z < kTileVt * kTileVs) {
                             const double v = L.acc[z];
                             if (v != 0.0) {
@@ -907,7 +944,7 @@ constexpr int kSingU = 8;      // trial indices of one time row taken in one rou
 __global__ void __launch_bounds__(kSingThreads)
 k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band, const int32_t* __restrict__ pairs,
            const double* __restrict__ rules, const int32_t* __restrict__ roff, const int32_t* __restrict__ rcnt,
-           int P, double* val, float* valf, ProductView pv, unsigned long long* counter)
+           int P, double* val, float* valf, ProductView pv, unsigned long long* counter, double fxs)
 {
     extern __shared__ double sing_lds[];
     double* key = sing_lds;                                   // P sorted distances
@@ -1062,7 +1099,8 @@ k_singular(GeomView g, TableView tv, const double* __restrict__ t, BandView band
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    deposit(band, val, valf, pv, k, i, g.v[px[a] * E + tau], g.v[py[b] * E + sig], half * loc[a][b]);
+                    deposit(band, val, valf, pv, k, i, g.v[px[a] * E + tau], g.v[py[b] * E + sig], half * loc[a][b],
+                            fxs);
         }
     }
     const unsigned long long tot = wave_sum_u64(nq);
@@ -1172,17 +1210,25 @@ void tile_shape(int variant, int* test, int* trial)
 
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
                     const double* px, double* py, const int2* tiles, int64_t ntiles, int variant,
-                    unsigned long long* counter, hipStream_t s)
+                    unsigned long long* counter, hipStream_t s, double fxs)
 {
     if (ntiles <= 0) return;
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
     const ProductView pv{px, py, band.M};
-    if (variant == 1)
-        hipLaunchKernelGGL((k_regular_tile<TileB, false>), grid, dim3(TileB::kThreads), 0, s, g, tv, t, band, val,
-                           valf, pv, tiles, ntiles, counter, nullptr);
-    else
-        hipLaunchKernelGGL((k_regular_tile<TileA, false>), grid, dim3(TileA::kThreads), 0, s, g, tv, t, band, val,
-                           valf, pv, tiles, ntiles, counter, nullptr);
+    if (fxs > 0.0) {
+        if (variant == 1)
+            hipLaunchKernelGGL((k_regular_tile<TileB, false, true>), grid, dim3(TileB::kThreads), 0, s, g, tv, t,
+                               band, val, nullptr, pv, tiles, ntiles, counter, nullptr, fxs);
+        else
+            hipLaunchKernelGGL((k_regular_tile<TileA, false, true>), grid, dim3(TileA::kThreads), 0, s, g, tv, t,
+                               band, val, nullptr, pv, tiles, ntiles, counter, nullptr, fxs);
+    } else if (variant == 1) {
+        hipLaunchKernelGGL((k_regular_tile<TileB, false, false>), grid, dim3(TileB::kThreads), 0, s, g, tv, t, band,
+                           val, valf, pv, tiles, ntiles, counter, nullptr, 0.0);
+    } else {
+        hipLaunchKernelGGL((k_regular_tile<TileA, false, false>), grid, dim3(TileA::kThreads), 0, s, g, tv, t, band,
+                           val, valf, pv, tiles, ntiles, counter, nullptr, 0.0);
+    }
 }
 
 void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_t ntiles, hipStream_t s)
@@ -1190,8 +1236,8 @@ void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_
     if (ntiles <= 0) return;
     const dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
     const ProductView pv{nullptr, nullptr, 0};
-    hipLaunchKernelGGL((k_regular_tile<TileA, true>), grid, dim3(TileA::kThreads), 0, s, GeomView{}, TableView{},
-                       nullptr, BandView{}, nullptr, nullptr, pv, tiles, ntiles, nullptr, probs);
+    hipLaunchKernelGGL((k_regular_tile<TileA, true, false>), grid, dim3(TileA::kThreads), 0, s, GeomView{},
+                       TableView{}, nullptr, BandView{}, nullptr, nullptr, pv, tiles, ntiles, nullptr, probs, 0.0);
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau, in
@@ -1215,7 +1261,8 @@ std::vector<int32_t> regular_tiles(int E, int variant)
 
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs, int64_t npairs,
                      const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt, int max_points, double* val,
-                     float* valf, const double* px, double* py, unsigned long long* counter, hipStream_t s)
+                     float* valf, const double* px, double* py, unsigned long long* counter, hipStream_t s,
+                     double fxs)
 {
     if (npairs <= 0) return;
     int P = 64;
@@ -1223,7 +1270,7 @@ void launch_singular(GeomView g, TableView tv, const double* t, BandView band, c
     const size_t lds = (size_t)P * (sizeof(double) + sizeof(uint16_t));
     const ProductView pv{px, py, band.M};
     hipLaunchKernelGGL(k_singular, dim3((unsigned)npairs), dim3(kSingThreads), lds, s, g, tv, t, band, pairs, ss_rules,
-                       ss_off, ss_cnt, P, val, valf, pv, counter);
+                       ss_off, ss_cnt, P, val, valf, pv, counter, fxs);
 }
 
 void launch_get_entries(BandView band, const double* val, const float* valf, int64_t n, const int32_t* k,

@@ -1,6 +1,7 @@
-// Equal time blocks of an equidistant grid (eq. (relationAtildeBlock), Section 5.1): the blocks
-// that equal_block_source maps to an integrated block are filled by copying that block's stored
-// values, so an equidistant assembly integrates O(N) node blocks instead of O(N^2).
+// Kernels on the stored band as a whole.  Equal time blocks of an equidistant grid (eq.
+// (relationAtildeBlock), Section 5.1): the blocks that equal_block_source maps to an integrated
+// block are filled by copying that block's stored values, so an equidistant assembly integrates
+// O(N) node blocks instead of O(N^2).  The deterministic assembly's scale and conversion.
 #include "tdbem_internal.hpp"
 
 namespace tdbem {
@@ -60,6 +61,42 @@ void launch_block_copy(BandView band, double* val, float* valf, hipStream_t s)
         hipLaunchKernelGGL(k_block_copy<float>, grid, dim3(256), 0, s, band, valf);
     else
         hipLaunchKernelGGL(k_block_copy<double>, grid, dim3(256), 0, s, band, val);
+}
+
+// Largest |value| of the storage: a non-negative double orders like its bit pattern, so the
+// maximum is an integer atomic max over the patterns.
+__global__ void __launch_bounds__(256) k_absmax(const double* __restrict__ val, int64_t n,
+                                                unsigned long long* __restrict__ out)
+{
+    double m = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(val[s]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// Fixed-point integers of scale 2^e (two's complement in the 8 bytes of each value) to doubles:
+// one rounding to 53 bits, then an exact scaling.
+__global__ void __launch_bounds__(256) k_fixed_to_double(double* __restrict__ val, int64_t n, int e)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const long long q = __double_as_longlong(val[s]);
+    val[s] = ldexp((double)q, -e);
+}
+
+void launch_absmax(const double* val, int64_t n, double* out, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int64_t blocks = (n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384;
+    hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, val, n,
+                       reinterpret_cast<unsigned long long*>(out));
+}
+
+void launch_fixed_to_double(double* val, int64_t n, int e, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fixed_to_double, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, n, e);
 }
 
 }  // namespace tdbem

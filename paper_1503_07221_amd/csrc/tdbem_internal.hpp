@@ -340,9 +340,10 @@ void launch_layout(BandView band, const double* xyz, const double* rho, const do
 // 512; tiles of a shape from regular_tiles(E, variant).
 int tile_variants();
 void tile_shape(int variant, int* test, int* trial);
+// fxs > 0: deterministic mode, val holds fixed-point integers of scale fxs (FP64 storage only).
 void launch_regular(GeomView g, TableView tv, const double* t, BandView band, double* val, float* valf,
                     const double* px, double* py, const int2* tiles, int64_t ntiles, int variant,
-                    unsigned long long* counter, hipStream_t s);
+                    unsigned long long* counter, hipStream_t s, double fxs = 0.0);
 std::vector<int32_t> regular_tiles(int E, int variant);
 // One launch over the tiles of several problems (shape 0): tile (a, b) of problem q is stored as
 // (a | q << 24, b); probs[q] holds that problem's views.
@@ -359,10 +360,14 @@ void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_
 void launch_singular(GeomView g, TableView tv, const double* t, BandView band, const int32_t* pairs,
                      int64_t npairs, const double* ss_rules, const int32_t* ss_off, const int32_t* ss_cnt,
                      int max_points, double* val, float* valf, const double* px, double* py,
-                     unsigned long long* counter, hipStream_t s);
+                     unsigned long long* counter, hipStream_t s, double fxs = 0.0);
 // Copies every block that equal_block_source maps to another one from that block, in place in
 // the band storage (all rows k of a node, every basis pair of the node pair).
 void launch_block_copy(BandView band, double* val, float* valf, hipStream_t s);
+// Deterministic mode: *out = max |val| over n values (out zeroed by the caller), and the in-place
+// conversion of fixed-point integers of scale 2^e back to doubles.
+void launch_absmax(const double* val, int64_t n, double* out, hipStream_t s);
+void launch_fixed_to_double(double* val, int64_t n, int e, hipStream_t s);
 // Allocation-free entry query: static device staging of kNoAllocEntries queries (4 int32 index
 // arrays and the float64 results); noalloc_scratch returns its address on `device` (current).
 constexpr int64_t kNoAllocEntries = 65536;

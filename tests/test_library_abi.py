@@ -67,6 +67,19 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.tdbem_create(None, None) == -1
 
 
+def test_create_rejects_options_it_cannot_meet():
+    """tdbem_options: a deterministic flag other than 0/1, a regular rule other than the 7-point one
+    and a table tolerance below what the tables reach are refused before any device call."""
+    import ctypes
+    import paper_1503_07221_amd as tb
+    lib = tb.load_library()
+    h = ctypes.c_void_p()
+    for kw in ({"deterministic": 2}, {"quad_regular": 6}, {"psi_tol": 1e-14}, {"psi_tol": -1.0}, {"ss_order": 6}):
+        opt = tb._Options(0, None, kw.get("ss_order", 4), kw.get("deterministic", 0), kw.get("quad_regular", 7),
+                          kw.get("psi_tol", 0.0))
+        assert lib.tdbem_create(ctypes.byref(h), ctypes.byref(opt)) == -1, kw
+
+
 def test_package_does_not_import_the_oracle():
     """The product path never routes through the CPU oracle."""
     for root, _, files in os.walk(os.path.join(ROOT, "paper_1503_07221_amd")):
