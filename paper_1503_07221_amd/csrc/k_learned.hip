@@ -69,15 +69,6 @@ __device__ inline void load_features(float (*xs)[kPad], const LpGraph& g, int64_
     for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(&xs[r][c0 + 4 * q]) = a[q];
 }
 
-// LDS ws[o][c] = W[o][part*64 + c] (bfloat16 -> float).
-__device__ inline void load_weights(float (*ws)[kPad], const uint16_t* __restrict__ W, int part)
-{
-    const int o = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
-    const uint16_t* src = W + o * (4 * kH) + part * kH + c0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) ws[o][c0 + q] = bf16_to_float(src[q]);
-}
-
 // LDS wt[c][o] = W[o][part*64 + c] (transposed block).
 __device__ inline void load_weights_t(float (*wt)[kPad], const uint16_t* __restrict__ W, int part)
 {
@@ -107,61 +98,67 @@ k_lp_input(int64_t n, LpGraph g, const double* __restrict__ v, const double* __r
     H0[s] = a;
 }
 
-// One message-passing layer on a tile of 64 nodes: U = X W^T + b, Hout = Hin + relu(U).
-// Thread (tn, to) owns nodes 4 tn..4 tn+3 and channels 4 to..4 to+3.
+// One message-passing layer on a tile of 64 nodes, U = X W^T + b, Hout = Hin + relu(U), with the
+// 64 x 256 x 64 product on the matrix cores (v_mfma_f32_16x16x32_bf16): wave w forms the output
+// channels 16 w .. 16 w + 15 of the tile's 64 nodes as four 16 x 16 blocks over K = 256.  A float32
+// feature x enters as three bfloat16 parts hi + mid + lo (8 + 8 + 8 significant bits, x - hi - mid -
+// lo below 2^-24 |x|); each part times a bfloat16 weight is exact in float32 and the products are
+// accumulated in float32, so the layer keeps float32 accuracy.
+// Fragments: lane l holds A[m = l % 16][k = 8 (l / 16) + i], B[k = 8 (l / 16) + i][n = l % 16] for
+// i < 8, and D[m = 4 (l / 16) + r][n = l % 16] for r < 4.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
 __global__ void __launch_bounds__(256)
 k_lp_layer(int64_t n, LpGraph g, const float* __restrict__ Hin, const uint16_t* __restrict__ W,
-           const float* __restrict__ bias, float* __restrict__ Hout, float* __restrict__ U)
+                const float* __restrict__ bias, float* __restrict__ Hout, float* __restrict__ U)
 {
     __shared__ float xs[kTile][kPad];
-    __shared__ float ws[kH][kPad];
     const int64_t n0 = (int64_t)blockIdx.x * kTile;
-    const int tn = threadIdx.x & 15, to = threadIdx.x >> 4;
-    float acc[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    floatx4 acc[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int part = 0; part < 4; ++part) {
         load_features(xs, g, n, n0, part, Hin);
-        load_weights(ws, W, part);
         __syncthreads();
-#pragma unroll 4
-        for (int c = 0; c < kH; c += 4) {
-            float4 xa[4], wb[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) xa[a] = *reinterpret_cast<const float4*>(&xs[4 * tn + a][c]);
+        for (int ks = 0; ks < kH; ks += 32) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (16 * wave + col) * (4 * kH) + part * kH + ks + 8 * kq);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) wb[b] = *reinterpret_cast<const float4*>(&ws[4 * to + b][c]);
+            for (int t = 0; t < 4; ++t) {
+                const float* xr = &xs[16 * t + col][ks + 8 * kq];
+                bf16x8 hi, mid, lo;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    acc[a][b] = fmaf(xa[a].x, wb[b].x, acc[a][b]);
-                    acc[a][b] = fmaf(xa[a].y, wb[b].y, acc[a][b]);
-                    acc[a][b] = fmaf(xa[a].z, wb[b].z, acc[a][b]);
-                    acc[a][b] = fmaf(xa[a].w, wb[b].w, acc[a][b]);
+                for (int i = 0; i < 8; ++i) {
+                    const float x = xr[i];
+                    const __bf16 h = (__bf16)x;
+                    const float r1 = x - (float)h;
+                    const __bf16 m = (__bf16)r1;
+                    hi[i] = h;
+                    mid[i] = m;
+                    lo[i] = (__bf16)(r1 - (float)m);
                 }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, b, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, b, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, b, acc[t], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
+    const int ch = 16 * wave + col;
+    const float bc = bias[ch];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t node = n0 + 4 * tn + a;
-        if (node >= n) continue;
-        float4 u, h;
-        u.x = acc[a][0] + bias[4 * to + 0];
-        u.y = acc[a][1] + bias[4 * to + 1];
-        u.z = acc[a][2] + bias[4 * to + 2];
-        u.w = acc[a][3] + bias[4 * to + 3];
-        const float4 hi = *reinterpret_cast<const float4*>(Hin + node * kH + 4 * to);
-        h.x = hi.x + fmaxf(u.x, 0.f);
-        h.y = hi.y + fmaxf(u.y, 0.f);
-        h.z = hi.z + fmaxf(u.z, 0.f);
-        h.w = hi.w + fmaxf(u.w, 0.f);
-        *reinterpret_cast<float4*>(Hout + node * kH + 4 * to) = h;
-        if (U) *reinterpret_cast<float4*>(U + node * kH + 4 * to) = u;
-    }
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t node = n0 + 16 * t + 4 * kq + r;
+            if (node >= n) continue;
+            const float u = acc[t][r] + bc;
+            Hout[node * kH + ch] = Hin[node * kH + ch] + fmaxf(u, 0.f);
+            if (U) U[node * kH + ch] = u;
+        }
 }
 
 // z_n = s * sum_c wout[c] H[n][c]
@@ -205,7 +202,10 @@ k_lp_output_bwd(int64_t n, const float* __restrict__ H, const uint16_t* __restri
     if (q == 0) partial[(int64_t)blockIdx.x * kH + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 
-// Backward of a layer, part 1: DU = dH * [U > 0] and dX_p = DU W_p (the 4 feature blocks).
+// Backward of a layer, part 1: DU = dH * [U > 0] and dX_p = DU W_p (the 4 feature blocks), the
+// products on the matrix cores as in k_lp_layer (DU split into three bfloat16 parts; the
+// weights are bfloat16 values, exact in either format).  Wave w forms the channels 16 w .. 16 w +
+// 15 of every part for the tile's 64 nodes.
 __global__ void __launch_bounds__(256)
 k_lp_layer_bwd_dx(int64_t n, const float* __restrict__ U, const float* __restrict__ dH,
                   const uint16_t* __restrict__ W, float* __restrict__ DU, float* __restrict__ dX)
@@ -227,39 +227,46 @@ k_lp_layer_bwd_dx(int64_t n, const float* __restrict__ U, const float* __restric
             ds[r][c0 + q] = d;
         }
     }
-    const int tn = threadIdx.x & 15, tc = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int c = 16 * wave + col;
     for (int part = 0; part < 4; ++part) {
         load_weights_t(wt, W, part);
         __syncthreads();
-        float acc[4][4];
+        floatx4 acc[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
-#pragma unroll 4
-        for (int o = 0; o < kH; o += 4) {
-            float4 da[4], wb[4];
+        for (int ks = 0; ks < kH; ks += 32) {
+            bf16x8 b;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) da[a] = *reinterpret_cast<const float4*>(&ds[4 * tn + a][o]);
+            for (int i = 0; i < 8; ++i) b[i] = (__bf16)wt[c][ks + 8 * kq + i];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) wb[b] = *reinterpret_cast<const float4*>(&wt[4 * tc + b][o]);
+            for (int t = 0; t < 4; ++t) {
+                const float* dr = &ds[16 * t + col][ks + 8 * kq];
+                bf16x8 hi, mid, lo;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    acc[a][b] = fmaf(da[a].x, wb[b].x, acc[a][b]);
-                    acc[a][b] = fmaf(da[a].y, wb[b].y, acc[a][b]);
-                    acc[a][b] = fmaf(da[a].z, wb[b].z, acc[a][b]);
-                    acc[a][b] = fmaf(da[a].w, wb[b].w, acc[a][b]);
+                for (int i = 0; i < 8; ++i) {
+                    const float x = dr[i];
+                    const __bf16 h = (__bf16)x;
+                    const float r1 = x - (float)h;
+                    const __bf16 m = (__bf16)r1;
+                    hi[i] = h;
+                    mid[i] = m;
+                    lo[i] = (__bf16)(r1 - (float)m);
                 }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, b, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, b, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, b, acc[t], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int64_t node = n0 + 4 * tn + a;
-            if (node < n)
-                *reinterpret_cast<float4*>(dX + ((int64_t)part * n + node) * kH + 4 * tc) =
-                    make_float4(acc[a][0], acc[a][1], acc[a][2], acc[a][3]);
-        }
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t node = n0 + 16 * t + 4 * kq + r;
+                if (node < n) dX[((int64_t)part * n + node) * kH + c] = acc[t][r];
+            }
         __syncthreads();
     }
 }

@@ -157,11 +157,16 @@ def test_training_cuts_iterations(ctx, tb):
     assert torch.linalg.norm(a_g - a_e).item() <= 1e-8 * torch.linalg.norm(a_e).item()
     r = g - ctx.matvec(a_g)
     assert torch.linalg.norm(r).item() <= 1e-8 * torch.linalg.norm(g).item()
-    # the network for one cycle of 20 iterations, then Algorithm 1 (2, 10) from there
+    # the network for one cycle of 20 iterations, then Algorithm 1 (2, 10) from there: the same
+    # solution in the operator's norm (two solves to a 1e-8 residual differ by A^{-1} of at most
+    # 2e-8 |g|, which the conditioning of this system turns into ~1e-6 in alpha)
     alpha2, mixed = ctx.solve(g, tol=1e-8, restart=20, max_it=400, precond_inner=(2, 10),
                               precond_kind=tb.PRECOND_LEARNED_THEN_ALG1)
     assert mixed["converged"] and mixed["iterations"] > 20
-    assert torch.linalg.norm(alpha2 - alpha).item() <= 1e-6 * torch.linalg.norm(alpha).item()
+    gn = torch.linalg.norm(g).item()
+    assert torch.linalg.norm(g - ctx.matvec(alpha2)).item() <= 1e-8 * gn
+    assert torch.linalg.norm(ctx.matvec((alpha2 - alpha).contiguous())).item() <= 2e-8 * gn
+    assert torch.linalg.norm(alpha2 - alpha).item() <= 1e-4 * torch.linalg.norm(alpha).item()
 
 
 def test_pairs_training_across_geometries(tb):
