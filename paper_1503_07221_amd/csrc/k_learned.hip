@@ -523,6 +523,45 @@ k_matvec_tri_t(BandView band, const VT* __restrict__ val, const double* __restri
         const bool uni = __ballot(act && ib != ib0) == 0;
         const int slo0 = ib0 < 0 ? -ib0 : 0, shi0 = N - ib0 < B ? N - ib0 : B;
         const VT* __restrict__ v = vt + (int64_t)lr * B * kBT;
+        if (uni) {
+            // 8 slots at a time: the loads issued together (clamped to the row's last slot, so
+            // every address is in range), the mirrored sums of the 8 slots reduced over the
+            // lanes by one butterfly that leaves slot s0 + q summed in lane 8 q
+            for (int s0 = 0; s0 < B; s0 += 8) {
+                double a[8], c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int s = s0 + u;
+                    const double av = (double)v[(s < B ? s : B - 1) * kBT];
+                    a[u] = s < B && s >= slo && s < shi ? av : 0.0;
+                    c[u] = j < l ? a[u] * yj : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (a[u] != 0.0) {
+                        const int s = s0 + u;
+                        if (staged) atomicAdd(&s_dir[ib + s - ibase][lane], a[u] * yl);
+                        else atomicAdd(x + (int64_t)(ib + s) * M + j, a[u] * yl);
+                    }
+                const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+                double h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) h[u] = (b5 ? c[u + 4] : c[u]) + __shfl_xor(b5 ? c[u] : c[u + 4], 32, 64);
+                double q[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) q[u] = (b4 ? h[u + 2] : h[u]) + __shfl_xor(b4 ? h[u] : h[u + 2], 16, 64);
+                double w = (b3 ? q[1] : q[0]) + __shfl_xor(b3 ? q[0] : q[1], 8, 64);
+                w += __shfl_xor(w, 1, 64);
+                w += __shfl_xor(w, 2, 64);
+                w += __shfl_xor(w, 4, 64);
+                const int s = s0 + (lane >> 3);
+                if ((lane & 7) == 0 && s < B && s >= slo0 && s < shi0 && w != 0.0) {
+                    if (staged) atomicAdd(&s_mir[ib0 + s - ibase][lr], w);
+                    else atomicAdd(x + (int64_t)(ib0 + s) * M + l, w);
+                }
+            }
+            continue;
+        }
         for (int s = 0; s < B; ++s) {
             const bool in = s >= slo && s < shi;
             const double a = in ? (double)v[s * kBT] : 0.0;
@@ -530,14 +569,8 @@ k_matvec_tri_t(BandView band, const VT* __restrict__ val, const double* __restri
                 if (staged) atomicAdd(&s_dir[ib + s - ibase][lane], a * yl);
                 else atomicAdd(x + (int64_t)(ib + s) * M + j, a * yl);
             }
-            double c = (in && j < l) ? a * yj : 0.0;
-            if (uni) {
-                for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
-                if (lane == 0 && s >= slo0 && s < shi0 && c != 0.0) {
-                    if (staged) atomicAdd(&s_mir[ib0 + s - ibase][lr], c);
-                    else atomicAdd(x + (int64_t)(ib0 + s) * M + l, c);
-                }
-            } else if (c != 0.0) {
+            const double c = (in && j < l) ? a * yj : 0.0;
+            if (c != 0.0) {
                 if (staged) atomicAdd(&s_mir[ib + s - ibase][lr], c);
                 else atomicAdd(x + (int64_t)(ib + s) * M + l, c);
             }
