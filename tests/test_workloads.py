@@ -41,3 +41,17 @@ def test_graded_grid_ratio():
     h = np.diff(t)
     assert t[0] == 0.0 and abs(t[-1] - 8.0) < 1e-12 and np.all(h > 0)
     assert abs(h.max() / h.min() - 4.0) < 1e-9
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark measures one GPU: --gpus 2 ends at once with a message and status 2, before
+    anything touches a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=300)
+    assert res.returncode == 2
+    assert "one GPU" in json.loads(res.stdout.strip().splitlines()[-1])["error"]
