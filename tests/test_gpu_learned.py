@@ -145,7 +145,10 @@ def test_training_cuts_iterations(ctx, tb):
     assert learned["converged"] and plain["converged"]
     assert learned["iterations"] < 0.5 * plain["iterations"], (learned["iterations"], plain["iterations"])
     # the same solve with the iteration's z = P(v), w = A z replayed from a captured HIP graph: every
-    # replay must act like the eager launches, so the Givens estimates follow the same sequence
+    # replay must act like the eager launches, so the Givens estimates follow the same sequence.  The
+    # products add with atomics, whose order changes the last bits of every product, and that drift
+    # grows over hundreds of Arnoldi steps: the first 20 estimates must agree to 1e-8 (a replay that
+    # used stale or wrong buffers would differ at once), all of them to 1e-3
     est_e, est_g = [], []
     a_e, d_e = ctx.solve(g, tol=1e-8, restart=500, max_it=500, precond_kind=tb.PRECOND_LEARNED,
                          progress=lambda it, e: est_e.append(e))
@@ -153,7 +156,8 @@ def test_training_cuts_iterations(ctx, tb):
                          use_graph=True, progress=lambda it, e: est_g.append(e))
     assert d_g["converged"] and abs(d_g["iterations"] - d_e["iterations"]) <= 1
     k = min(len(est_e), len(est_g))
-    assert np.allclose(est_g[:k], est_e[:k], rtol=1e-6, atol=0.0)
+    assert np.allclose(est_g[:20], est_e[:20], rtol=1e-8, atol=0.0)
+    assert np.allclose(est_g[:k], est_e[:k], rtol=1e-3, atol=0.0)
     assert torch.linalg.norm(a_g - a_e).item() <= 1e-8 * torch.linalg.norm(a_e).item()
     r = g - ctx.matvec(a_g)
     assert torch.linalg.norm(r).item() <= 1e-8 * torch.linalg.norm(g).item()
