@@ -12,6 +12,7 @@
 // the lower-triangle storage forms on the fly (scatter_half).
 #include "tdbem_internal.hpp"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -1241,21 +1242,37 @@ void launch_regular_multi(const RegularProblem* probs, const int2* tiles, int64_
 }
 
 // Tiles (tau tile a, sigma tile b) of the regular-pair kernel holding at least one sigma > tau, in
-// row order.  (Ordering the tiles by the distance of the two blocks, so that workgroups running
-// together share Chebyshev pieces, measured slower with per-lane global coefficient loads: 1.69 s
-// against 1.59 s on the 5120-triangle sphere with 64 bases.)
+// Morton (Z) order over squares of triangle index space: the key interleaves the bits of the test
+// and trial triangle ranges in units of TS triangles (a TT-triangle test tile is TS / TT of a
+// unit).  Each XCD takes one contiguous range of the list, so the workgroups it runs together cover
+// a compact patch of (tau, sigma) pairs at similar distances, which need the same Chebyshev
+// windows: the stage loads hit its L2 more often.  On the 5120-triangle sphere with 64 bases:
+// 1.54 s against 1.60 s in row order (units of TT x TS triangles: 1.58 s; of 2 TS: 1.58 s).
 std::vector<int32_t> regular_tiles(int E, int variant)
 {
     int TT, TS;
     tile_shape(variant, &TT, &TS);
-    std::vector<int32_t> out;
-    const int nA = (E + TT - 1) / TT, nB = (E + TS - 1) / TS;
+    const int nA = (E + TT - 1) / TT, nB = (E + TS - 1) / TS, per = TS / TT > 0 ? TS / TT : 1;
+    std::vector<std::pair<uint64_t, int64_t>> keyed;
     for (int a = 0; a < nA; ++a)
         for (int b = 0; b < nB; ++b)
             if (b * TS + TS - 1 > a * TT) {
-                out.push_back(a);
-                out.push_back(b);
+                const uint32_t x = (uint32_t)(a / per), y = (uint32_t)b;
+                uint64_t key = 0;
+                for (int bit = 0; bit < 21; ++bit)
+                    key |= ((uint64_t)((x >> bit) & 1u) << (2 * bit)) | ((uint64_t)((y >> bit) & 1u) << (2 * bit + 1));
+                keyed.push_back({key, (int64_t)a * nB + b});
             }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const std::pair<uint64_t, int64_t>& p, const std::pair<uint64_t, int64_t>& q) {
+                         return p.first < q.first;
+                     });
+    std::vector<int32_t> out;
+    out.reserve(2 * keyed.size());
+    for (const auto& kv : keyed) {
+        out.push_back((int32_t)(kv.second / nB));
+        out.push_back((int32_t)(kv.second % nB));
+    }
     return out;
 }
 
