@@ -158,8 +158,11 @@ tdbem_status tdbem_set_time_grid(tdbem_ctx *ctx, const double *t, int32_t N, tdb
  * psi_{k,i}, tilde psi_{k,i} of eq. (psis) tabulated as piecewise Chebyshev series
  * (Section 3.1), 7-point rule for pairs without a common vertex, Sauter-Schwab rules for
  * coincident, edge and vertex pairs, entries kept where supp psi_{k,i} meets the distance
- * range of the two hats (eq. (SparsitySmallBlock)).  rep may be NULL.
- * TDBEM_ESTATE without mesh and grid, TDBEM_ENOMEM if the storage does not fit. */
+ * range of the two hats (eq. (SparsitySmallBlock)).  On an equidistant grid the blocks that equal
+ * another one (eq. (relationAtildeBlock)) are copied, not integrated (tdbem_set_block_reuse); with
+ * tdbem_options.deterministic the storage is bitwise reproducible.  rep may be NULL.
+ * TDBEM_ESTATE without mesh and grid, TDBEM_ENOMEM if the storage does not fit, TDBEM_EINVAL for
+ * TDBEM_MIXED in the deterministic mode. */
 tdbem_status tdbem_assemble(tdbem_ctx *ctx, tdbem_precision prec, tdbem_assembly_report *rep);
 
 /* The regular-pair kernel is compiled for two tile shapes (test x trial triangles per workgroup:
