@@ -14,8 +14,11 @@ sample of the same workload, the block matvec, the FGMRES solve to a relative re
 with the recursive block-Hessenberg preconditioner (Algorithm 1), the mixed-precision form
 (FP64 quadrature, FP32 storage and FP32 inner products, FP64 solver) with its error against FP64, the
 field off the surface, the learned preconditioner (trained on the GPU, then used in FGMRES) with
-the batched right-hand sides, and the uneven-mesh group assembly.  One JSON line is printed at
-the end (or on SIGTERM, with what has been measured by then).
+the batched right-hand sides, the uneven-mesh group assembly (one regular-pair launch over eight
+spheres), the same sphere on an equidistant grid with and without the copies of equal blocks, and
+the deterministic mode.  One JSON line is printed at the end (or on SIGTERM, with what has been
+measured by then).  `--config5` runs instead the learned preconditioner's training on pairs from
+ten random spheres and tori and the solve of the 20480-triangle torus.
 
 `--copy-calibration` runs only a plain 1 GiB device copy (the reference kernel that scales the
 FETCH_SIZE / WRITE_SIZE hardware counters into HBM bytes).
